@@ -1,0 +1,190 @@
+"""ctypes binding of the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the library's product path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+RC_R = 6.0
+RC_A = 4.5
+N_DESC = 102
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-ffp-contract=off keeps a*b+c unfused)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class StepParams(ct.Structure):
+    _fields_ = [("dt", ct.c_double), ("T0", ct.c_double), ("T1", ct.c_double),
+                ("B0", ct.c_double * 3), ("B1", ct.c_double * 3), ("alpha", ct.c_double),
+                ("gammaL", ct.c_double), ("mu_s", ct.c_double), ("mid_tol", ct.c_double),
+                ("rcR", ct.c_double), ("rcA", ct.c_double), ("n_ramp", ct.c_int64),
+                ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
+                ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int)]
+
+
+class Obs(ct.Structure):
+    _fields_ = [("step", ct.c_double), ("E_nep", ct.c_double), ("E_kin", ct.c_double),
+                ("E_z", ct.c_double), ("T_lat", ct.c_double), ("T_spin", ct.c_double),
+                ("M", ct.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ct.CDLL(LIB_PATH)
+        P = ct.c_void_p
+        L.or_eval.argtypes = [ct.c_int, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
+                              ct.c_double, P, P, P, P, P, P, P, P]
+        L.or_neighbors.argtypes = [ct.c_int, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
+        L.or_philox.argtypes = [P, P, P]
+        L.or_field_lin.argtypes = [ct.c_int, P, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
+                                   ct.c_double, P, P]
+        L.or_normals.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_uint64, ct.c_uint32, P]
+        L.or_run.argtypes = [ct.c_int, P, P, P, P, P, P, P, P, ct.c_int, ct.POINTER(StepParams),
+                             ct.POINTER(ct.c_int64), ct.c_int64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ct.c_void_p) if a is not None else None
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def neighbors(pos, box, pbc, rc, use_cells=False, maxnb=256):
+    """Neighbour sets r_ij < rc (minimum image), ascending j per atom."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    cnt = np.zeros(n, np.int32)
+    nbr = np.full((n, maxnb), -1, np.int32)
+    rc_ = lib().or_neighbors(n, _p(pos), _p(_f64(box)), _p(_i32(pbc)), rc, int(use_cells), maxnb,
+                             _p(cnt), _p(nbr))
+    if rc_ != 0:
+        raise RuntimeError("neighbour overflow")
+    return [nbr[i, :cnt[i]].copy() for i in range(n)]
+
+
+def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0), act=0,
+             rcR=RC_R, rcA=RC_A, want=("E", "F", "H")):
+    """Energy, forces, fields (and optionally q, Fp, per-atom E) of one system."""
+    types = _i32(types)
+    pos = _f64(pos)
+    spin = _f64(spin)
+    n = types.shape[0]
+    out = {}
+    E = np.zeros(1)
+    Ez = np.zeros(1)
+    Ei = np.zeros(n) if "Ei" in want else None
+    F = np.zeros((n, 3)) if "F" in want else None
+    H = np.zeros((n, 3)) if "H" in want else None
+    q = np.zeros((n, N_DESC)) if "q" in want else None
+    Fp = np.zeros((n, N_DESC)) if "Fp" in want else None
+    lib().or_eval(n, _p(types), _p(pos), _p(spin), _p(_f64(box)), _p(_i32(pbc)), _p(_f64(params)),
+                  rcR, rcA, act, mu_s, _p(_f64(B)), _p(E), _p(Ez), _p(Ei), _p(F), _p(H), _p(q), _p(Fp))
+    out["E"] = float(E[0])
+    out["Ez"] = float(Ez[0])
+    for k, v in (("Ei", Ei), ("F", F), ("H", H), ("q", q), ("Fp", Fp)):
+        if v is not None:
+            out[k] = v
+    return out
+
+
+def field_lin(types, pos, spin_hat, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0),
+              act=0, rcR=RC_R, rcA=RC_A):
+    """Field of the frozen-Fp magnetic energy (Fp* taken at spin_hat) at spins `spin`."""
+    types = _i32(types)
+    n = types.shape[0]
+    H = np.zeros((n, 3))
+    lib().or_field_lin(n, _p(types), _p(_f64(pos)), _p(_f64(spin_hat)), _p(_f64(spin)), _p(_f64(box)),
+                       _p(_i32(pbc)), _p(_f64(params)), rcR, rcA, act, mu_s, _p(_f64(B)), _p(H))
+    return H
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib().or_philox(_p(c), _p(k), _p(o))
+    return o
+
+
+def normals(seed, atom, step, stream):
+    xi = np.zeros(3)
+    lib().or_normals(seed, atom, step, stream, _p(xi))
+    return xi
+
+
+def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
+                mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
+                K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A) -> StepParams:
+    sp = StepParams()
+    sp.dt = dt
+    sp.T0 = T0
+    sp.T1 = T0 if T1 is None else T1
+    for a in range(3):
+        sp.B0[a] = B0[a]
+        sp.B1[a] = (B0 if B1 is None else B1)[a]
+    sp.alpha = alpha
+    sp.gammaL = gammaL
+    sp.mu_s = mu_s
+    sp.mid_tol = mid_tol
+    sp.mid_cap = mid_cap
+    sp.rcR = rcR
+    sp.rcA = rcA
+    sp.n_ramp = n_ramp
+    sp.seed = seed
+    sp.ensemble = ensemble
+    sp.K_corr = K_corr
+    sp.act = act
+    sp.sequential = sequential
+    return sp
+
+
+def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps, step0=0):
+    """n_steps of the spin-lattice step; returns (pos, vel, spin, step, obs[n_steps])."""
+    types = _i32(types)
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    spin = _f64(spin).copy()
+    colour = _i32(colour)
+    ncol = int(colour.max()) + 1 if colour.size else 0
+    st = ct.c_int64(step0)
+    obs = (Obs * max(n_steps, 1))()
+    lib().or_run(types.shape[0], _p(types), _p(pos), _p(vel), _p(spin), _p(_f64(box)), _p(_i32(pbc)),
+                 _p(_f64(params)), _p(colour), ncol, ct.byref(sp), ct.byref(st), n_steps,
+                 ct.cast(obs, ct.c_void_p))
+    ob = np.array([[o.step, o.E_nep, o.E_kin, o.E_z, o.T_lat, o.T_spin, o.M[0], o.M[1], o.M[2]]
+                   for o in obs[:n_steps]]).reshape(n_steps, 9)
+    return pos, vel, spin, st.value, ob
