@@ -1,0 +1,283 @@
+/*
+ * nepspin.h -- C ABI of the MI355X spin-lattice NEP library.
+ *
+ * The library evaluates a spin-aware neuro-evolution potential E(R,S) and
+ * advances coupled lattice/spin dynamics with it on one AMD Instinct MI355X
+ * (gfx950). Method: "Extreme-Scale Atomistic Simulation of Real-Temperature
+ * Magnetic Skyrmion Dynamics by Coupled Spin-Lattice Modeling":
+ *   - unified energy surface E(R,S) with lattice and spin driving terms,
+ *     Sec. 5.2 "Unified spin-lattice execution";
+ *   - spin-aware local descriptor (structural radial/angular channels plus
+ *     onsite, pairwise exchange/DMI/anisotropic/single-ion, and spin-weighted
+ *     angular channels), Sec. 5.1 "A spin-aware local descriptor pipeline" and
+ *     "Implementation-oriented descriptor organization";
+ *   - Chebyshev radial basis of size 8, Sec. 5.2 "SVE2 predicated
+ *     vectorization" and "SME three-stage pipeline";
+ *   - symplectic spin-lattice integrator with a predictor-corrector spin
+ *     update scheduled last, Sec. 3 and Sec. 5.1 "Self-consistent midpoint
+ *     spin update"; finite-temperature baths on both lattice and spins, Sec. 8.
+ *
+ * Units: Angstrom, eV, fs, atomic mass units, K, Tesla. Spins are
+ * dimensionless vectors (|s| = 1 on magnetic atoms); the effective field
+ * H = -dE/ds is in eV. Species 0 (Fe) carries a spin, species 1 (Ge) does not:
+ * spin rows of species-1 atoms are ignored (treated as zero) and their field
+ * rows are returned as zero.
+ *
+ * Conventions for every call:
+ *   - Return value: 0 (SL_OK) on success, a negative sl_status otherwise; the
+ *     library never aborts or exits. sl_last_error() gives a message for the
+ *     calling thread's last failure.
+ *   - Ownership: the caller owns every array it passes. Inputs are copied
+ *     before the call returns; outputs are written into caller buffers. Opaque
+ *     handles are owned by the library and released only by the matching
+ *     *_destroy call.
+ *   - Atom order is the caller's order; any internal reordering is invisible.
+ *   - Arrays are C-contiguous; "[n][3]" means 3 doubles per atom, atom-major.
+ *   - Threading: an nep_model may be shared by several threads once created;
+ *     an sl_sim must be used by one thread at a time; server calls are
+ *     thread-safe.
+ */
+#ifndef NEPSPIN_H
+#define NEPSPIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SL_OK = 0,
+    SL_E_INVALID = -1,    /* bad argument, size or hyper-parameter          */
+    SL_E_OOM = -2,        /* device memory or HBM budget exceeded           */
+    SL_E_BOX = -3,        /* periodic box edge < 2 (r_c^R + skin)           */
+    SL_E_DEVICE = -4,     /* HIP runtime error                              */
+    SL_E_NONFINITE = -5,  /* NaN/Inf in the state of a replica              */
+    SL_E_NOTFOUND = -6,   /* unknown replica id                             */
+    SL_E_BUSY = -7,       /* replica not finished yet                       */
+    SL_E_OVERFLOW = -8,   /* neighbour list capacity exceeded, or two spins
+                             of one colour within coupling range            */
+    SL_E_NOLIB = -9       /* no usable GPU / device code                    */
+} sl_status;
+
+/* Arithmetic of the potential (descriptor, read-out, backward, couplings).
+ * Positions, velocities, spins, minimum-image displacements, spin rotations
+ * and energy sums are FP64 in every mode. */
+typedef enum {
+    SL_FP64 = 0,          /* everything FP64                                */
+    SL_FP32_MIXED = 1,    /* potential in FP32, accumulated in FP32          */
+    SL_FP32_BF16H = 2     /* as SL_FP32_MIXED, with the input->hidden
+                             contraction of the read-out in BF16 (FP32 sums) */
+} sl_precision;
+
+const char *sl_last_error(void);
+
+typedef struct nep_model nep_model;
+typedef struct sl_sim sl_sim;
+typedef struct sl_server sl_server;
+
+/* ---------------------------------------------------------------------- */
+/* Model                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Hyper-parameters of the spin-aware NEP. This build supports exactly:
+ * n_max_R = 8 (9 radial-set functions), n_max_A = 6 (7 angular-set
+ * functions), l_max = 4, basis_K = 8 (Chebyshev T_0..T_8), n_hidden = 64,
+ * n_species = 2, rc_R = 6.0, rc_A = 4.5 (Angstrom); anything else is
+ * SL_E_INVALID. */
+typedef struct {
+    int n_max_R, n_max_A, l_max, basis_K, n_hidden, n_species;
+    double rc_R, rc_A;
+} nep_spin_hparams;
+
+/* params: 15,438 doubles in this order (tau = 2 t_i + t_j is the ordered
+ * species pair of centre i and neighbour j):
+ *   c^R[4][9][9], c^A[4][7][9], c^ex[4][9][9], c^dm[4][9][9], c^an[4][9][9],
+ *   c^si[4][9][9], c^sa[4][7][9], then for species t = 0, 1:
+ *   W0[64][102], b0[64], w1[64], b1[1].
+ * Radial functions: f_k(r) = (T_k(x)+1)/2 * (1+cos(pi r/rc))/2 with
+ * x = 2(r/rc-1)^2-1 for r < rc (zero beyond); g^X_n(r) = sum_k c^X[tau][n][k] f_k(r).
+ * Descriptor q[102] of atom i (sums over neighbours within the channel's
+ * cutoff, rc_R for R/ex/dm/an/si and rc_A for A/sa; j,k independent):
+ *   0..8    q^R_n     = sum_j g^R_n(r_ij)
+ *   9..36   q^A_{nl}  = sum_j sum_k g^A_n(r_ij) g^A_n(r_ik) P_l(rhat_ij.rhat_ik), at 9+4n+l-1
+ *   37      q^os      = s_i.s_i
+ *   38..46  q^ex_n    = sum_j g^ex_n (s_i.s_j)
+ *   47..55  q^dm_n    = sum_j g^dm_n rhat_ij.(s_i x s_j)
+ *   56..64  q^an_n    = sum_j g^an_n (s_i.rhat_ij)(s_j.rhat_ij)
+ *   65..73  q^si_n    = sum_j g^si_n (s_i.rhat_ij)^2
+ *   74..101 q^sa_{nl} = sum_j sum_k g^A_n(r_ij) g^sa_n(r_ik) (s_i.s_k) P_l(rhat_ij.rhat_ik)
+ * Energy: E_i = b1 + sum_h w1_h tanh(b0_h + sum_d W0_hd q_d), E_NEP = sum_i E_i.
+ * The model keeps a device copy of the parameters. */
+int nep_model_create(const nep_spin_hparams *hp, const double *params, size_t n_params,
+                     nep_model **out);
+int nep_model_destroy(nep_model *m);
+
+/* One system, caller-owned and read-only. types[n] in {0,1}; pos[n][3];
+ * spin[n][3] (rows of species 1 ignored); box edges; pbc[a] = 1 for a
+ * periodic axis (minimum image), 0 for a free axis. mu_s is the moment of a
+ * species-0 atom in Bohr magnetons; B the applied field in Tesla (Zeeman
+ * energy -mu_s mu_B B.s_i on species-0 atoms). */
+typedef struct {
+    int64_t n_atoms;
+    const int32_t *types;
+    const double *pos;
+    const double *spin;
+    double box[3];
+    int32_t pbc[3];
+    double mu_s;
+    double B[3];
+} sl_system_view;
+
+/* Execution options. device_ptrs = 0: the output pointers of nep_spin_eval
+ * are host memory. device_ptrs = 1: they are device memory of the current
+ * HIP device. hip_stream: a hipStream_t, or NULL for the library's stream.
+ * A NULL sl_exec means host pointers and the library's stream; calls return
+ * after the results are in place. */
+typedef struct {
+    int device_ptrs;
+    void *hip_stream;
+} sl_exec;
+
+/* Energy, forces and fields of one system (Sec. 5.2: one pass producing both
+ * lattice and spin driving terms).
+ *   energy[1]      : E_NEP + E_Zeeman (FP64 sum)
+ *   energy_atom[n] : E_i (NEP part), or NULL
+ *   force[n][3]    : F_i = -dE/dr_i, or NULL
+ *   field[n][3]    : H_i = -dE/ds_i (+ mu_s mu_B B), species-0 rows; or NULL
+ * Errors: SL_E_INVALID (bad sizes/types), SL_E_BOX, SL_E_OVERFLOW (more than
+ * 128 neighbours inside 6.5 A or 64 inside 5 A), SL_E_DEVICE. */
+int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec,
+                  double *energy, double *energy_atom, double *force, double *field,
+                  const sl_exec *ex);
+
+/* Intermediate arrays of the same evaluation, for inspection: q[n][102]
+ * (descriptor, caller order) and Fp[n][102] = dE_i/dq_i. Either may be NULL.
+ * Same pointer rules and errors as nep_spin_eval. */
+int nep_spin_descriptors(const nep_model *m, const sl_system_view *sys, sl_precision prec,
+                         double *q, double *Fp, const sl_exec *ex);
+
+/* ---------------------------------------------------------------------- */
+/* Spin-lattice integration                                               */
+/* ---------------------------------------------------------------------- */
+
+/* One step n -> n+1 is the symmetric splitting B A O S A B:
+ *   B: v += (dt/2) kappa F/m;  A: r += (dt/2) v, wrapped into the box;
+ *   O (ensemble = 1): v = c1 v + sqrt((1-c1^2) kappa kB T_n/m) xi, c1 = exp(-gamma_L dt);
+ *   S: spin step at the mid positions: for p = 0..K_corr, the magnetic part of
+ *      E is linearised with Fp taken at reference spins S_hat (S_hat = S^n for
+ *      p = 0, then normalise((S^n + S^(p-1))/2)); from S^n, every spin of
+ *      colour 0,1,..,C-1 and then C-1,..,0 takes an implicit-midpoint
+ *      Rodrigues rotation over dt/2 with
+ *        omega = (h + alpha_s xbar x h)/(1+alpha_s^2),
+ *        h = H_lin(xbar) + mu_s mu_B B_n + eta_i,
+ *        eta_i = sqrt(2 alpha_s kB T_n hbar/dt) xi_i (fixed for the step),
+ *      iterated until max|y'-y| <= mid_tol or mid_cap iterations;
+ *   A; then E, F, H at (R^{n+1}, S^{n+1}); B.
+ * T_n = T0 + (T1-T0) min(n, n_ramp)/n_ramp and B_n likewise (constant T0, B0
+ * when n_ramp = 0). xi are Philox4x32-10 normals keyed by seed, counted by
+ * (atom index in the caller's order, step, stream 0 lattice / 1 spin).
+ * kappa = 9.648533212e-3, kB = 8.617333262e-5 eV/K, hbar = 0.6582119569 eV fs,
+ * mu_B = 5.7883818060e-5 eV/T, masses 55.845 (Fe) and 72.630 (Ge) u. */
+typedef struct {
+    double dt, T0, T1, B0[3], B1[3], alpha_s, gamma_L;
+    int64_t n_ramp;
+    int ensemble;        /* 0 NVE (no O step, alpha_s must be 0 for NVE spins), 1 Langevin */
+    int K_corr;          /* number of corrector passes (0 = predictor only)  */
+    double mid_tol;      /* per-spin midpoint tolerance, e.g. 1e-15           */
+    int mid_cap;         /* per-spin midpoint iteration cap, e.g. 50          */
+    uint64_t seed;       /* Philox key                                        */
+    double skin;         /* Verlet skin (A); lists rebuilt when an atom moved
+                            more than skin/2 since the last build             */
+} sl_integrator_params;
+
+typedef struct {
+    int64_t step;
+    double E_pot;        /* E_NEP at the end of the step                     */
+    double E_kin;
+    double E_zeeman;
+    double T_lattice;    /* 2 E_kin / (3 N kB)                               */
+    double T_spin;       /* sum|s x H|^2 / (2 kB sum s.H) over spins          */
+    double M[3];         /* mean spin                                         */
+} sl_observables;
+
+/* Create a simulation of one system: copies the state to the device and
+ * evaluates F^0. vel[n][3] may be NULL (zero). colour[n]: colour class
+ * (0..C-1) of each species-0 atom and -1 elsewhere, no two same-colour spins
+ * within r_c^R + skin; NULL lets the library colour greedily.
+ * Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM, SL_E_OVERFLOW, SL_E_DEVICE. */
+int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel,
+              const int32_t *colour, const sl_integrator_params *ip, sl_precision prec,
+              sl_sim **out);
+
+/* Advance n_steps steps. per_step_out[n_steps] receives the observables of
+ * every step, or NULL. Errors: SL_E_NONFINITE (state not finite),
+ * SL_E_OVERFLOW, SL_E_DEVICE. */
+int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *per_step_out);
+
+/* State in caller order: pos, vel, spin [n][3] (any may be NULL), step. */
+int sl_get_state(const sl_sim *s, double *pos, double *vel, double *spin, int64_t *step);
+
+/* Replace the state (checkpoint resume); F is re-evaluated. */
+int sl_set_state(sl_sim *s, const double *pos, const double *vel, const double *spin, int64_t step);
+
+int sl_destroy(sl_sim *s);
+
+/* ---------------------------------------------------------------------- */
+/* Replica serving                                                        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* 0: free device memory minus 4 GiB            */
+    int max_slots;             /* most replicas resident at once               */
+    sl_precision precision;
+    int steps_per_batch;       /* steps per batched launch sequence             */
+    int K_corr;                /* corrector passes, common to all replicas     */
+} sl_server_config;
+
+typedef enum { SL_QUEUED = 0, SL_RUNNING = 1, SL_DONE = 2, SL_FAILED = 3 } sl_replica_state;
+
+typedef struct {
+    int state;                 /* sl_replica_state                              */
+    int error;                 /* sl_status of a failed replica                 */
+    int64_t steps_done, n_steps;
+    double t_submit, t_admit, t_done;     /* seconds since server start        */
+    double step_latency_p50, step_latency_p99;   /* seconds, over its steps     */
+    int64_t n_latency_samples;
+} sl_replica_status;
+
+/* A server owns a worker thread that admits queued replicas while slots and
+ * the HBM budget allow, keeps their state on the device, and advances all
+ * resident replicas together in batched launches. Results of a replica do
+ * not depend on which other replicas share the device. */
+int sl_server_create(const nep_model *m, const sl_server_config *cfg, sl_server **out);
+
+/* Queue a replica (inputs copied; colour may be NULL). ip->K_corr must equal
+ * the server's. Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the
+ * whole budget). */
+int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const double *vel,
+                      const int32_t *colour, const sl_integrator_params *ip, int64_t n_steps,
+                      uint64_t *id_out);
+
+int sl_replica_poll(sl_server *sv, uint64_t id, sl_replica_status *out);
+
+/* Final state of a finished replica (any pointer may be NULL); SL_E_BUSY
+ * while it runs. obs receives its last step's observables. */
+int sl_replica_fetch(sl_server *sv, uint64_t id, double *pos, double *vel, double *spin,
+                     sl_observables *obs);
+
+/* Block until every submitted replica is done or failed. */
+int sl_server_drain(sl_server *sv);
+
+/* Aggregate counters since creation: steps (batched launches), atom-steps,
+ * busy seconds. Any pointer may be NULL. */
+int sl_server_stats(sl_server *sv, int64_t *batched_steps, double *atom_steps, double *busy_s);
+
+int sl_server_destroy(sl_server *sv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

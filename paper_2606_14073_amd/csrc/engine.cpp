@@ -1,0 +1,1403 @@
+// engine.cpp -- host runtime of the spin-lattice NEP library: model upload,
+// the batch engine (replica layout in HBM, step sequencing on one HIP stream)
+// and the C ABI declared in nepspin.h, including the replica server.
+#include "engine.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "nepspin.h"
+
+using namespace nep;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+extern "C" const char *sl_last_error(void) { return g_err.c_str(); }
+
+#define HIPCHK(x)                                                                                \
+    do {                                                                                         \
+        hipError_t e_ = (x);                                                                     \
+        if (e_ != hipSuccess) return fail(SL_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+static int dalloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(SL_E_OOM, std::string("hipMalloc of ") + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    return SL_OK;
+}
+
+template <typename T>
+static void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+static double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// model
+// ---------------------------------------------------------------------------
+
+constexpr size_t MODEL_DEV = 324 + 252 + 4 * 324 + 252 + 2 * DP * NH + 2 * NH + 2 * NH + 2;
+
+struct nep_model {
+    std::vector<double> p;
+    double *d64 = nullptr;
+    float *d32 = nullptr;
+    float *dbf = nullptr;
+    ModelDev<double> m64{};
+    ModelDev<float> m32{};
+    std::mutex eval_mu;
+    struct Engine *eval_eng[3] = {nullptr, nullptr, nullptr};
+};
+
+template <typename real>
+static void model_layout(const std::vector<double> &p, std::vector<real> &h) {
+    h.assign(MODEL_DEV, real(0));
+    size_t o = 0;
+    auto copy = [&](int off, int n) {
+        for (int k = 0; k < n; k++) h[o + k] = (real)p[off + k];
+        o += n;
+    };
+    copy(P_CR, 324);
+    copy(P_CA, 252);
+    copy(P_CEX, 324);
+    copy(P_CDM, 324);
+    copy(P_CAN, 324);
+    copy(P_CSI, 324);
+    copy(P_CSA, 252);
+    for (int t = 0; t < 2; t++) {
+        const double *W0 = p.data() + P_MLP + t * P_MLP_STRIDE;
+        for (int d = 0; d < ND; d++)
+            for (int hh = 0; hh < NH; hh++) h[o + (size_t)d * NH + hh] = (real)W0[hh * ND + d];
+        o += (size_t)DP * NH;
+    }
+    for (int t = 0; t < 2; t++)
+        for (int hh = 0; hh < NH; hh++) h[o++] = (real)p[P_MLP + t * P_MLP_STRIDE + NH * ND + hh];
+    for (int t = 0; t < 2; t++)
+        for (int hh = 0; hh < NH; hh++) h[o++] = (real)p[P_MLP + t * P_MLP_STRIDE + NH * ND + NH + hh];
+    for (int t = 0; t < 2; t++) h[o++] = (real)p[P_MLP + t * P_MLP_STRIDE + NH * ND + 2 * NH];
+}
+
+template <typename real>
+static ModelDev<real> model_ptrs(real *base, const float *bf) {
+    ModelDev<real> m;
+    size_t o = 0;
+    m.cR = base + o; o += 324;
+    m.cA = base + o; o += 252;
+    m.cEX = base + o; o += 324;
+    m.cDM = base + o; o += 324;
+    m.cAN = base + o; o += 324;
+    m.cSI = base + o; o += 324;
+    m.cSA = base + o; o += 252;
+    m.W0 = base + o; o += 2 * (size_t)DP * NH;
+    m.b0 = base + o; o += 2 * NH;
+    m.w1 = base + o; o += 2 * NH;
+    m.b1 = base + o; o += 2;
+    m.W0bf = bf;
+    return m;
+}
+
+static float to_bf16(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    float r;
+    std::memcpy(&r, &u, 4);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// replica and engine
+// ---------------------------------------------------------------------------
+
+struct Replica {
+    uint64_t id = 0;
+    int64_t n = 0, n_fe = 0;
+    std::vector<int> fe_idx, ge_idx;       // caller index of internal atoms
+    std::vector<int> colour_fe;            // colour of each spin carrier (internal order)
+    int ncol = 0;
+    RepDev dev{};                          // parameters (host copy)
+    int fe_off = -1, ge_off = -1;          // position in the current layout, -1 when not resident
+    int slot = -1;                         // replica index in the layout
+    std::vector<double> pos, vel, spin;    // caller order, used before admission / after eviction
+    int64_t n_steps = 0, steps_done = 0;
+    int state = SL_QUEUED, error = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::vector<double> lat;
+    double obs_last[NOBS] = {0};
+    int64_t obs_step = 0;
+    size_t bytes = 0;
+};
+
+static size_t bytes_per_atom(sl_precision prec) {
+    const size_t rs = prec == SL_FP64 ? 8 : 4;
+    size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
+    b += rs * (2 * DP + 1 + NA * NAB + 12 + 6 * MAXR + 6 * MAXA);
+    b += rs * (MAXFE * 9 + 8) / 2 + 64;
+    return b;
+}
+
+struct Engine {
+    nep_model *M = nullptr;
+    sl_precision prec = SL_FP64;
+    int K_corr = 1;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+
+    std::vector<Replica *> reps;
+    int N = 0, N_fe = 0, n_cells = 0;
+    size_t cap = 0, cap_fe = 0, cap_cells = 0, cap_rep = 0, cap_chunks = 0;
+
+    // device arrays
+    int *rid = nullptr, *orig = nullptr, *colour = nullptr;
+    RepDev *rep = nullptr;
+    d4 *pos = nullptr, *vel = nullptr, *spin = nullptr, *force = nullptr, *field = nullptr, *pos_ref = nullptr,
+       *spin_n = nullptr, *spin_hat = nullptr, *eta = nullptr;
+    int *nbrR = nullptr, *cntR = nullptr, *cntFeR = nullptr, *revR = nullptr;
+    int *nbrA = nullptr, *cntA = nullptr, *cntFeA = nullptr, *revA = nullptr, *a2r = nullptr;
+    int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
+    int *flags = nullptr;
+    void *work = nullptr;      // real-typed work arrays, one allocation
+    size_t work_bytes = 0;
+    Work<double> w64{};
+    Work<float> w32{};
+    Chunk *chunks = nullptr;
+    int *chunk_ptr = nullptr, *col_idx = nullptr;
+    double *partial = nullptr, *obs = nullptr;
+    size_t cap_obs = 0, cap_col = 0;
+    int n_chunks = 0;
+    std::vector<int> col_ptr;
+
+    ~Engine() { release(); }
+
+    void release() {
+        dfree(rid); dfree(orig); dfree(colour); dfree(rep);
+        dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
+        dfree(spin_n); dfree(spin_hat); dfree(eta);
+        dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
+        dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
+        dfree(cell_of); dfree(cell_cnt); dfree(cell_start); dfree(cell_fill); dfree(cell_atoms);
+        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(partial); dfree(obs);
+        if (work) (void)hipFree(work);
+        work = nullptr;
+        cap = cap_fe = cap_cells = cap_rep = cap_chunks = cap_obs = cap_col = 0;
+        if (own_stream && st) (void)hipStreamDestroy(st);
+        st = nullptr;
+        own_stream = false;
+    }
+
+    Sys sys() const {
+        Sys S;
+        S.N = N;
+        S.N_fe = N_fe;
+        S.n_rep = (int)reps.size();
+        S.n_cells = n_cells;
+        S.rid = rid;
+        S.orig = orig;
+        S.rep = rep;
+        S.pos = pos; S.vel = vel; S.spin = spin; S.force = force; S.field = field; S.pos_ref = pos_ref;
+        S.spin_n = spin_n; S.spin_hat = spin_hat; S.eta = eta;
+        S.colour = colour;
+        S.nbrR = nbrR; S.cntR = cntR; S.cntFeR = cntFeR; S.revR = revR;
+        S.nbrA = nbrA; S.cntA = cntA; S.cntFeA = cntFeA; S.revA = revA; S.a2r = a2r;
+        S.cell_of = cell_of; S.cell_cnt = cell_cnt; S.cell_start = cell_start; S.cell_fill = cell_fill;
+        S.cell_atoms = cell_atoms;
+        S.flags = flags;
+        return S;
+    }
+
+    int ensure_stream() {
+        if (!st) {
+            HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            own_stream = true;
+        }
+        return SL_OK;
+    }
+
+    template <typename real>
+    void carve(Work<real> &w, size_t c, size_t cf) {
+        real *b = (real *)work;
+        size_t o = 0;
+        auto take = [&](size_t n) {
+            real *p = b + o;
+            o += (n + 63) & ~(size_t)63;
+            return p;
+        };
+        w.q = take(c * DP);
+        w.Fp = take(c * DP);
+        w.Ei = take(c);
+        w.AB = take(c * NA * NAB);
+        w.pbR = take((size_t)MAXR * c * 6);
+        w.pbA = take((size_t)MAXA * c * 6);
+        w.ownR = take(c * 6);
+        w.ownA = take(c * 6);
+        w.craw = take((size_t)MAXFE * cf * 3);
+        w.cpl = take((size_t)MAXFE * cf * 6);
+        w.selfc = take(cf * 8);
+        w.bf16 = prec == SL_FP32_BF16H;
+    }
+
+    static size_t work_count(size_t c, size_t cf) {
+        auto r = [](size_t n) { return (n + 63) & ~(size_t)63; };
+        return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r((size_t)MAXR * c * 6) + r((size_t)MAXA * c * 6) +
+               2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
+    }
+
+    int reserve(size_t n, size_t nfe, size_t ncell, size_t nrep, size_t nchunk) {
+        int rc;
+        if (n > cap || nfe > cap_fe) {
+            size_t c = std::max(n, cap + cap / 4), cf = std::max(nfe, cap_fe + cap_fe / 4);
+            c = std::max<size_t>(c, 64);
+            cf = std::max<size_t>(cf, 64);
+            dfree(rid); dfree(orig); dfree(colour);
+            dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
+            dfree(spin_n); dfree(spin_hat); dfree(eta);
+            dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
+            dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
+            dfree(cell_of); dfree(cell_atoms);
+            if (work) (void)hipFree(work);
+            work = nullptr;
+            cap = cap_fe = 0;
+            if ((rc = dalloc(&rid, c)) || (rc = dalloc(&orig, c)) || (rc = dalloc(&colour, c)) ||
+                (rc = dalloc(&pos, c)) || (rc = dalloc(&vel, c)) || (rc = dalloc(&spin, c)) ||
+                (rc = dalloc(&force, c)) || (rc = dalloc(&field, c)) || (rc = dalloc(&pos_ref, c)) ||
+                (rc = dalloc(&spin_n, c)) || (rc = dalloc(&spin_hat, c)) || (rc = dalloc(&eta, c)) ||
+                (rc = dalloc(&nbrR, (size_t)MAXR * c)) || (rc = dalloc(&cntR, c)) || (rc = dalloc(&cntFeR, c)) ||
+                (rc = dalloc(&revR, (size_t)MAXR * c)) || (rc = dalloc(&nbrA, (size_t)MAXA * c)) ||
+                (rc = dalloc(&cntA, c)) || (rc = dalloc(&cntFeA, c)) || (rc = dalloc(&revA, (size_t)MAXA * c)) ||
+                (rc = dalloc(&a2r, (size_t)MAXA * c)) || (rc = dalloc(&cell_of, c)) ||
+                (rc = dalloc(&cell_atoms, c)))
+                return rc;
+            const size_t rs = prec == SL_FP64 ? 8 : 4;
+            work_bytes = work_count(c, cf) * rs;
+            hipError_t e = hipMalloc(&work, work_bytes);
+            if (e != hipSuccess) {
+                work = nullptr;
+                (void)hipGetLastError();
+                return fail(SL_E_OOM, "hipMalloc of work arrays failed");
+            }
+            HIPCHK(hipMemset(work, 0, work_bytes));
+            cap = c;
+            cap_fe = cf;
+            if (prec == SL_FP64) carve(w64, c, cf);
+            else carve(w32, c, cf);
+        }
+        if (ncell > cap_cells) {
+            dfree(cell_cnt); dfree(cell_start); dfree(cell_fill);
+            size_t c = std::max(ncell, cap_cells + cap_cells / 4);
+            if ((rc = dalloc(&cell_cnt, c)) || (rc = dalloc(&cell_start, c)) || (rc = dalloc(&cell_fill, c))) return rc;
+            cap_cells = c;
+        }
+        if (nrep > cap_rep) {
+            dfree(rep); dfree(chunk_ptr); dfree(obs);
+            size_t c = std::max<size_t>(nrep, 2 * cap_rep);
+            if ((rc = dalloc(&rep, c)) || (rc = dalloc(&chunk_ptr, c + 1))) return rc;
+            cap_rep = c;
+            cap_obs = 0;
+        }
+        if (nchunk > cap_chunks) {
+            dfree(chunks); dfree(partial);
+            size_t c = std::max(nchunk, 2 * cap_chunks);
+            if ((rc = dalloc(&chunks, c)) || (rc = dalloc(&partial, c * NOBS))) return rc;
+            cap_chunks = c;
+        }
+        if (!flags) {
+            if ((rc = dalloc(&flags, NFLAGS))) return rc;
+            HIPCHK(hipMemset(flags, 0, NFLAGS * sizeof(int)));
+        }
+        if (!col_idx || cap_col < cap_fe) {
+            dfree(col_idx);
+            if ((rc = dalloc(&col_idx, cap_fe))) return rc;
+            cap_col = cap_fe;
+        }
+        return SL_OK;
+    }
+
+    int ensure_obs(size_t nsteps) {
+        size_t need = std::max<size_t>(nsteps, 1) * std::max<size_t>(reps.size(), 1) * NOBS;
+        if (need > cap_obs) {
+            dfree(obs);
+            int rc = dalloc(&obs, need);
+            if (rc) return rc;
+            cap_obs = need;
+        }
+        return SL_OK;
+    }
+
+    // cell grid of one replica (cells at least r_list wide)
+    static void cell_grid(Replica &r, const double *pos_caller) {
+        const double rl = RC_R + r.dev.skin;
+        for (int a = 0; a < 3; a++) {
+            if (r.dev.pbc[a]) {
+                r.dev.nc[a] = std::max(1, (int)std::floor(r.dev.box[a] / rl));
+                r.dev.cell_lo[a] = 0.0;
+                r.dev.cell_w[a] = r.dev.box[a] / r.dev.nc[a];
+            } else {
+                double mn = 1e300, mx = -1e300;
+                for (int64_t i = 0; i < r.n; i++) {
+                    mn = std::min(mn, pos_caller[3 * i + a]);
+                    mx = std::max(mx, pos_caller[3 * i + a]);
+                }
+                if (r.n == 0) mn = mx = 0;
+                const double margin = 2.0 * rl;
+                const double ext = (mx - mn) + 2 * margin;
+                r.dev.nc[a] = std::max(1, (int)std::floor(ext / rl));
+                r.dev.cell_lo[a] = mn - margin;
+                r.dev.cell_w[a] = ext / r.dev.nc[a];
+            }
+        }
+    }
+
+    // Place replicas new_reps in a fresh layout. State of replicas already
+    // resident is moved device-to-device; others are uploaded from r->pos etc.
+    int set_layout(const std::vector<Replica *> &new_reps) {
+        int rc;
+        if ((rc = ensure_stream())) return rc;
+        // old device state must survive reallocation: stage it on the host when
+        // the arrays will grow, else move inside the device
+        size_t n = 0, nfe = 0, ncell = 0, nchunk = 0;
+        for (Replica *r : new_reps) {
+            n += r->n;
+            nfe += r->n_fe;
+            ncell += (size_t)r->dev.nc[0] * r->dev.nc[1] * r->dev.nc[2];
+            nchunk += (r->n_fe + 255) / 256 + (r->n - r->n_fe + 255) / 256;
+        }
+        const bool grow = n > cap || nfe > cap_fe;
+        std::vector<Replica *> moved;
+        for (Replica *r : reps) {
+            if (std::find(new_reps.begin(), new_reps.end(), r) != new_reps.end() && r->fe_off >= 0) moved.push_back(r);
+        }
+        // snapshot resident state (host) when reallocating or when ranges may overlap
+        std::vector<std::vector<d4>> snap(moved.size() * 5);
+        for (size_t k = 0; k < moved.size(); k++) {
+            Replica *r = moved[k];
+            d4 *src[5] = {pos, vel, spin, force, field};
+            for (int a = 0; a < 5; a++) {
+                snap[5 * k + a].resize(r->n);
+                if (r->n_fe)
+                    HIPCHK(hipMemcpyAsync(snap[5 * k + a].data(), src[a] + r->fe_off, r->n_fe * sizeof(d4),
+                                          hipMemcpyDeviceToHost, st));
+                if (r->n - r->n_fe)
+                    HIPCHK(hipMemcpyAsync(snap[5 * k + a].data() + r->n_fe, src[a] + r->ge_off,
+                                          (r->n - r->n_fe) * sizeof(d4), hipMemcpyDeviceToHost, st));
+            }
+            HIPCHK(hipMemcpyAsync(&r->dev, rep + r->slot, sizeof(RepDev), hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        (void)grow;
+        for (Replica *r : reps) {
+            r->fe_off = r->ge_off = -1;
+            r->slot = -1;
+        }
+        if ((rc = reserve(n, nfe, ncell, new_reps.size(), nchunk))) return rc;
+        reps = new_reps;
+        N = (int)n;
+        N_fe = (int)nfe;
+        // offsets
+        int fo = 0, go = (int)nfe, cb = 0;
+        std::vector<int> h_rid(n), h_orig(n), h_col(n, -1);
+        std::vector<RepDev> h_rep(reps.size());
+        std::vector<Chunk> h_chunks;
+        std::vector<int> h_cptr;
+        int cmax = 0;
+        for (size_t k = 0; k < reps.size(); k++) {
+            Replica *r = reps[k];
+            r->slot = (int)k;
+            r->fe_off = fo;
+            r->ge_off = go;
+            r->dev.cell_base = cb;
+            r->dev.n_atoms = (int)r->n;
+            r->dev.fe_off = fo;
+            r->dev.n_fe = (int)r->n_fe;
+            r->dev.ge_off = go;
+            r->dev.n_ge = (int)(r->n - r->n_fe);
+            cb += r->dev.nc[0] * r->dev.nc[1] * r->dev.nc[2];
+            h_cptr.push_back((int)h_chunks.size());
+            for (int64_t a = 0; a < r->n_fe; a++) {
+                h_rid[fo + a] = (int)k;
+                h_orig[fo + a] = r->fe_idx[a];
+                h_col[fo + a] = r->colour_fe.empty() ? -1 : r->colour_fe[a];
+            }
+            for (int64_t a = 0; a < r->n - r->n_fe; a++) {
+                h_rid[go + a] = (int)k;
+                h_orig[go + a] = r->ge_idx[a];
+            }
+            for (int64_t b = 0; b < r->n_fe; b += 256) h_chunks.push_back({(int)k, (int)(fo + b), (int)std::min<int64_t>(fo + r->n_fe, fo + b + 256)});
+            for (int64_t b = 0; b < r->n - r->n_fe; b += 256)
+                h_chunks.push_back({(int)k, (int)(go + b), (int)std::min<int64_t>(go + r->n - r->n_fe, go + b + 256)});
+            cmax = std::max(cmax, r->ncol);
+            fo += (int)r->n_fe;
+            go += (int)(r->n - r->n_fe);
+            h_rep[k] = r->dev;
+        }
+        h_cptr.push_back((int)h_chunks.size());
+        n_cells = cb;
+        n_chunks = (int)h_chunks.size();
+        // colour classes
+        col_ptr.assign(cmax + 1, 0);
+        std::vector<int> h_colidx;
+        h_colidx.reserve(nfe);
+        for (int c = 0; c < cmax; c++) {
+            col_ptr[c] = (int)h_colidx.size();
+            for (Replica *r : reps)
+                for (int64_t a = 0; a < r->n_fe; a++)
+                    if (!r->colour_fe.empty() && r->colour_fe[a] == c) h_colidx.push_back(r->fe_off + (int)a);
+        }
+        col_ptr[cmax] = (int)h_colidx.size();
+        if (n) {
+            HIPCHK(hipMemcpyAsync(rid, h_rid.data(), n * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(orig, h_orig.data(), n * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(colour, h_col.data(), n * 4, hipMemcpyHostToDevice, st));
+        }
+        if (!h_rep.empty()) HIPCHK(hipMemcpyAsync(rep, h_rep.data(), h_rep.size() * sizeof(RepDev), hipMemcpyHostToDevice, st));
+        if (!h_chunks.empty()) HIPCHK(hipMemcpyAsync(chunks, h_chunks.data(), h_chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(chunk_ptr, h_cptr.data(), h_cptr.size() * 4, hipMemcpyHostToDevice, st));
+        if (!h_colidx.empty()) HIPCHK(hipMemcpyAsync(col_idx, h_colidx.data(), h_colidx.size() * 4, hipMemcpyHostToDevice, st));
+        // state
+        std::vector<d4> buf;
+        for (size_t k = 0; k < reps.size(); k++) {
+            Replica *r = reps[k];
+            auto mk = std::find(moved.begin(), moved.end(), r);
+            d4 *dst[5] = {pos, vel, spin, force, field};
+            if (mk != moved.end()) {
+                size_t m = mk - moved.begin();
+                for (int a = 0; a < 5; a++) {
+                    if (r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, snap[5 * m + a].data(), r->n_fe * sizeof(d4),
+                                              hipMemcpyHostToDevice, st));
+                    if (r->n - r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, snap[5 * m + a].data() + r->n_fe,
+                                              (r->n - r->n_fe) * sizeof(d4), hipMemcpyHostToDevice, st));
+                }
+            } else {
+                const double *src[3] = {r->pos.data(), r->vel.data(), r->spin.data()};
+                for (int a = 0; a < 3; a++) {
+                    buf.assign(r->n, d4{0, 0, 0, 0});
+                    for (int64_t q = 0; q < r->n_fe; q++) {
+                        const int c = r->fe_idx[q];
+                        buf[q] = d4{src[a][3 * c], src[a][3 * c + 1], src[a][3 * c + 2], 0.0};
+                    }
+                    for (int64_t q = 0; q < r->n - r->n_fe; q++) {
+                        const int c = r->ge_idx[q];
+                        if (a == 2) buf[r->n_fe + q] = d4{0, 0, 0, 0};   // no spin on species 1
+                        else buf[r->n_fe + q] = d4{src[a][3 * c], src[a][3 * c + 1], src[a][3 * c + 2], 0.0};
+                    }
+                    if (r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, buf.data(), r->n_fe * sizeof(d4), hipMemcpyHostToDevice, st));
+                    if (r->n - r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, buf.data() + r->n_fe, (r->n - r->n_fe) * sizeof(d4),
+                                              hipMemcpyHostToDevice, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+            }
+        }
+        // force a neighbour rebuild, then F and H of the current state
+        int one = 1;
+        HIPCHK(hipMemcpyAsync(flags + F_REBUILD, &one, 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (N) {
+            const Sys S = sys();
+            launch_rebuild(S, RC_R + max_skin(), RC_A + max_skin(), st);
+            evaluate(spin);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return SL_OK;
+    }
+
+    double max_skin() const {
+        double s = 0;
+        for (Replica *r : reps) s = std::max(s, r->dev.skin);
+        return s;
+    }
+
+    // forward + backward at the current positions and the given spins
+    void evaluate(const d4 *spins) {
+        const Sys S = sys();
+        if (prec == SL_FP64) {
+            launch_forward(S, M->m64, w64, spins, st);
+            launch_backward(S, M->m64, w64, st);
+        } else {
+            launch_forward(S, M->m32, w32, spins, st);
+            launch_backward(S, M->m32, w32, st);
+        }
+    }
+
+    void rebuild_if_needed() {
+        const Sys S = sys();
+        launch_skin_check(S, st);
+        launch_rebuild(S, RC_R + max_skin(), RC_A + max_skin(), st);
+    }
+
+    template <typename real>
+    void spin_step(const ModelDev<real> &m, const Work<real> &w) {
+        const Sys S = sys();
+        launch_spin_prep(S, st);
+        for (int p = 0; p <= K_corr; p++) {
+            launch_forward(S, m, w, spin_hat, st);
+            launch_assemble(S, m, w, st);
+            if (p > 0) launch_spin_restore(S, st);
+            launch_sweep(S, w, col_ptr.data(), col_idx, (int)col_ptr.size() - 1, st);
+            if (p < K_corr) launch_spin_mid(S, st);
+        }
+    }
+
+    // one B A O S A B step of every active replica; observables to obs_out[n_rep][NOBS]
+    void step(double *obs_out) {
+        const Sys S = sys();
+        launch_kick(S, st);
+        launch_drift(S, st);
+        rebuild_if_needed();
+        launch_langevin(S, st);
+        if (prec == SL_FP64) spin_step(M->m64, w64);
+        else spin_step(M->m32, w32);
+        launch_drift(S, st);
+        rebuild_if_needed();
+        evaluate(spin);
+        launch_kick(S, st);
+        if (prec == SL_FP64) launch_observe(S, w64, chunks, n_chunks, chunk_ptr, partial, obs_out, st);
+        else launch_observe(S, w32, chunks, n_chunks, chunk_ptr, partial, obs_out, st);
+        launch_step_end(S, st);
+    }
+
+    int read_flags(int *h) {
+        HIPCHK(hipMemcpyAsync(h, flags, NFLAGS * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return SL_OK;
+    }
+
+    int check_flags() {
+        int h[NFLAGS];
+        int rc = read_flags(h);
+        if (rc) return rc;
+        if (h[F_OVERFLOW] & 1) return fail(SL_E_OVERFLOW, "neighbour list capacity exceeded (more than 128 atoms within rc_R+skin, 64 within rc_A+skin or 64 spin neighbours)");
+        if (h[F_OVERFLOW] & 2) return fail(SL_E_OVERFLOW, "asymmetric neighbour lists");
+        if (h[F_COLOUR]) return fail(SL_E_OVERFLOW, "two spins of the same colour are within coupling range");
+        return SL_OK;
+    }
+
+    // state of replica r in caller order
+    int download(Replica *r, double *p, double *v, double *s) {
+        d4 *src[3] = {pos, vel, spin};
+        double *dst[3] = {p, v, s};
+        std::vector<d4> buf(r->n);
+        for (int a = 0; a < 3; a++) {
+            if (!dst[a]) continue;
+            if (r->n_fe) HIPCHK(hipMemcpyAsync(buf.data(), src[a] + r->fe_off, r->n_fe * sizeof(d4), hipMemcpyDeviceToHost, st));
+            if (r->n - r->n_fe)
+                HIPCHK(hipMemcpyAsync(buf.data() + r->n_fe, src[a] + r->ge_off, (r->n - r->n_fe) * sizeof(d4),
+                                      hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < r->n; q++) {
+                const int c = q < r->n_fe ? r->fe_idx[q] : r->ge_idx[q - r->n_fe];
+                dst[a][3 * c] = buf[q].x;
+                dst[a][3 * c + 1] = buf[q].y;
+                dst[a][3 * c + 2] = buf[q].z;
+            }
+        }
+        return SL_OK;
+    }
+
+    int download_ff(Replica *r, double *F, double *H) {
+        d4 *src[2] = {force, field};
+        double *dst[2] = {F, H};
+        std::vector<d4> buf(r->n);
+        for (int a = 0; a < 2; a++) {
+            if (!dst[a]) continue;
+            if (r->n_fe) HIPCHK(hipMemcpyAsync(buf.data(), src[a] + r->fe_off, r->n_fe * sizeof(d4), hipMemcpyDeviceToHost, st));
+            if (r->n - r->n_fe)
+                HIPCHK(hipMemcpyAsync(buf.data() + r->n_fe, src[a] + r->ge_off, (r->n - r->n_fe) * sizeof(d4),
+                                      hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t q = 0; q < r->n; q++) {
+                const int c = q < r->n_fe ? r->fe_idx[q] : r->ge_idx[q - r->n_fe];
+                dst[a][3 * c] = buf[q].x;
+                dst[a][3 * c + 1] = buf[q].y;
+                dst[a][3 * c + 2] = buf[q].z;
+            }
+        }
+        return SL_OK;
+    }
+
+    template <typename real>
+    int download_rows(Replica *r, const real *src, int width, int stride, double *dst) {
+        std::vector<real> buf((size_t)r->n * stride);
+        if (r->n_fe)
+            HIPCHK(hipMemcpyAsync(buf.data(), src + (size_t)r->fe_off * stride, (size_t)r->n_fe * stride * sizeof(real),
+                                  hipMemcpyDeviceToHost, st));
+        if (r->n - r->n_fe)
+            HIPCHK(hipMemcpyAsync(buf.data() + (size_t)r->n_fe * stride, src + (size_t)r->ge_off * stride,
+                                  (size_t)(r->n - r->n_fe) * stride * sizeof(real), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t q = 0; q < r->n; q++) {
+            const int c = q < r->n_fe ? r->fe_idx[q] : r->ge_idx[q - r->n_fe];
+            for (int k = 0; k < width; k++) dst[(size_t)c * width + k] = (double)buf[(size_t)q * stride + k];
+        }
+        return SL_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// replica construction and validation
+// ---------------------------------------------------------------------------
+
+static int check_view(const sl_system_view *sys, double skin) {
+    if (!sys || sys->n_atoms < 0 || (sys->n_atoms > 0 && (!sys->types || !sys->pos)))
+        return fail(SL_E_INVALID, "system view: missing arrays");
+    if (sys->n_atoms > INT_MAX / 2) return fail(SL_E_INVALID, "too many atoms");
+    for (int64_t i = 0; i < sys->n_atoms; i++)
+        if (sys->types[i] != 0 && sys->types[i] != 1) return fail(SL_E_INVALID, "species must be 0 or 1");
+    for (int a = 0; a < 3; a++) {
+        if (!(sys->box[a] > 0) && sys->pbc[a]) return fail(SL_E_BOX, "periodic box edge must be positive");
+        if (sys->pbc[a] && sys->box[a] < 2.0 * (RC_R + skin))
+            return fail(SL_E_BOX, "periodic box edge shorter than 2 (rc_R + skin)");
+    }
+    for (int64_t i = 0; i < 3 * sys->n_atoms; i++)
+        if (!std::isfinite(sys->pos[i]) || (sys->spin && !std::isfinite(sys->spin[i])))
+            return fail(SL_E_INVALID, "non-finite position or spin");
+    return SL_OK;
+}
+
+// greedy colouring of the spin carriers (graph: r < rc_R + skin + 0.5), in index order
+static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int> &col) {
+    const int64_t n = sys->n_atoms;
+    col.assign(n, -1);
+    const double rc = RC_R + skin + 0.5, rc2 = rc * rc;
+    std::vector<int> fe;
+    for (int64_t i = 0; i < n; i++)
+        if (sys->types[i] == 0) fe.push_back((int)i);
+    // bin spin carriers
+    int nc[3];
+    double lo[3], w[3];
+    for (int a = 0; a < 3; a++) {
+        double mn = 1e300, mx = -1e300;
+        for (int i : fe) {
+            double x = sys->pos[3 * i + a];
+            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x / sys->box[a]);
+            mn = std::min(mn, x);
+            mx = std::max(mx, x);
+        }
+        if (sys->pbc[a]) {
+            lo[a] = 0;
+            nc[a] = std::max(1, (int)std::floor(sys->box[a] / rc));
+            w[a] = sys->box[a] / nc[a];
+        } else {
+            lo[a] = mn - 1;
+            double ext = mx - mn + 2;
+            nc[a] = std::max(1, (int)std::floor(ext / rc));
+            w[a] = ext / nc[a];
+        }
+        if (nc[a] > 1024) return fail(SL_E_INVALID, "colouring grid too large");
+    }
+    std::vector<std::vector<int>> cells((size_t)nc[0] * nc[1] * nc[2]);
+    std::vector<int> cid(n, -1);
+    for (int i : fe) {
+        int c[3];
+        for (int a = 0; a < 3; a++) {
+            double x = sys->pos[3 * i + a] - lo[a];
+            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x / sys->box[a]);
+            c[a] = std::min(nc[a] - 1, std::max(0, (int)std::floor(x / w[a])));
+        }
+        cid[i] = (c[0] * nc[1] + c[1]) * nc[2] + c[2];
+        cells[cid[i]].push_back(i);
+    }
+    for (int i : fe) {
+        const int ci = cid[i];
+        int c0 = ci / (nc[1] * nc[2]), c1 = (ci / nc[2]) % nc[1], c2 = ci % nc[2];
+        std::vector<char> used(64, 0);
+        for (int dx = -1; dx <= 1; dx++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dz = -1; dz <= 1; dz++) {
+                    int cc[3] = {c0 + dx, c1 + dy, c2 + dz};
+                    bool ok = true;
+                    for (int a = 0; a < 3; a++) {
+                        if (cc[a] < 0 || cc[a] >= nc[a]) {
+                            if (sys->pbc[a]) cc[a] = (cc[a] + nc[a]) % nc[a];
+                            else ok = false;
+                        }
+                    }
+                    if (!ok) continue;
+                    for (int j : cells[(cc[0] * nc[1] + cc[1]) * nc[2] + cc[2]]) {
+                        if (j == i || col[j] < 0) continue;
+                        double d2 = 0;
+                        for (int a = 0; a < 3; a++) {
+                            double x = sys->pos[3 * j + a] - sys->pos[3 * i + a];
+                            if (sys->pbc[a]) x -= sys->box[a] * std::nearbyint(x / sys->box[a]);
+                            d2 += x * x;
+                        }
+                        if (d2 < rc2 && col[j] < (int)used.size()) used[col[j]] = 1;
+                    }
+                }
+        int c = 0;
+        while (c < (int)used.size() && used[c]) c++;
+        col[i] = c;
+    }
+    return SL_OK;
+}
+
+static int make_replica(const sl_system_view *sys, const double *vel, const int32_t *colour,
+                        const sl_integrator_params *ip, bool need_colour, Replica &r) {
+    const double skin = ip ? ip->skin : 0.5;
+    if (ip && !(ip->skin >= 0 && ip->skin < 5)) return fail(SL_E_INVALID, "skin must be in [0, 5)");
+    int rc = check_view(sys, skin);
+    if (rc) return rc;
+    const int64_t n = sys->n_atoms;
+    r.n = n;
+    r.fe_idx.clear();
+    r.ge_idx.clear();
+    for (int64_t i = 0; i < n; i++) (sys->types[i] == 0 ? r.fe_idx : r.ge_idx).push_back((int)i);
+    r.n_fe = (int64_t)r.fe_idx.size();
+    r.pos.assign(sys->pos, sys->pos + 3 * n);
+    r.vel.assign(3 * n, 0.0);
+    if (vel) r.vel.assign(vel, vel + 3 * n);
+    r.spin.assign(3 * n, 0.0);
+    if (sys->spin) r.spin.assign(sys->spin, sys->spin + 3 * n);
+    for (int64_t i = 0; i < n; i++)
+        if (sys->types[i] != 0) r.spin[3 * i] = r.spin[3 * i + 1] = r.spin[3 * i + 2] = 0.0;
+    RepDev &d = r.dev;
+    std::memset(&d, 0, sizeof(d));
+    for (int a = 0; a < 3; a++) {
+        d.box[a] = sys->box[a];
+        d.pbc[a] = sys->pbc[a] ? 1 : 0;
+        d.B0[a] = d.B1[a] = sys->B[a];
+    }
+    d.mu_s = sys->mu_s;
+    d.skin = skin;
+    d.active = 1;
+    d.step_end = LLONG_MAX;
+    if (ip) {
+        if (!(ip->dt != 0 && std::isfinite(ip->dt))) return fail(SL_E_INVALID, "dt must be finite and non-zero");
+        if (ip->mid_cap < 1 || ip->mid_cap > 1000) return fail(SL_E_INVALID, "mid_cap must be in [1, 1000]");
+        if (ip->K_corr < 0 || ip->K_corr > 64) return fail(SL_E_INVALID, "K_corr must be in [0, 64]");
+        if (ip->alpha_s < 0 || ip->T0 < 0 || ip->T1 < 0 || ip->gamma_L < 0)
+            return fail(SL_E_INVALID, "alpha_s, temperatures and gamma_L must be non-negative");
+        d.dt = ip->dt;
+        d.T0 = ip->T0;
+        d.T1 = ip->T1;
+        d.alpha = ip->alpha_s;
+        d.gammaL = ip->gamma_L;
+        d.mid_tol = ip->mid_tol;
+        d.mid_cap = ip->mid_cap;
+        d.n_ramp = ip->n_ramp;
+        d.seed = ip->seed;
+        d.ensemble = ip->ensemble;
+        for (int a = 0; a < 3; a++) {
+            d.B0[a] = ip->B0[a];
+            d.B1[a] = ip->B1[a];
+        }
+    }
+    if (need_colour) {
+        std::vector<int> col;
+        if (colour) {
+            col.assign(colour, colour + n);
+        } else {
+            rc = greedy_colour(sys, skin, col);
+            if (rc) return rc;
+        }
+        r.colour_fe.resize(r.n_fe);
+        r.ncol = 0;
+        for (int64_t q = 0; q < r.n_fe; q++) {
+            const int c = col[r.fe_idx[q]];
+            if (c < 0 || c > 4096) return fail(SL_E_INVALID, "colour of a spin carrier must be in [0, 4096]");
+            r.colour_fe[q] = c;
+            r.ncol = std::max(r.ncol, c + 1);
+        }
+    }
+    Engine::cell_grid(r, sys->pos);
+    return SL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// model API
+// ---------------------------------------------------------------------------
+
+extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params, size_t n_params,
+                                nep_model **out) {
+    if (!out) return fail(SL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!hp || !params) return fail(SL_E_INVALID, "hparams and params are required");
+    if (hp->n_max_R != 8 || hp->n_max_A != 6 || hp->l_max != 4 || hp->basis_K != 8 || hp->n_hidden != 64 ||
+        hp->n_species != 2 || hp->rc_R != RC_R || hp->rc_A != RC_A)
+        return fail(SL_E_INVALID, "unsupported hyper-parameters (this build: n_max_R 8, n_max_A 6, l_max 4, "
+                                  "basis_K 8, n_hidden 64, 2 species, rc 6.0/4.5)");
+    if (n_params != (size_t)N_PARAMS) return fail(SL_E_INVALID, "expected 15438 parameters");
+    for (size_t k = 0; k < n_params; k++)
+        if (!std::isfinite(params[k])) return fail(SL_E_INVALID, "non-finite parameter");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return fail(SL_E_NOLIB, "no HIP device");
+    }
+    auto m = std::make_unique<nep_model>();
+    m->p.assign(params, params + n_params);
+    std::vector<double> h64;
+    std::vector<float> h32;
+    model_layout(m->p, h64);
+    model_layout(m->p, h32);
+    std::vector<float> hbf(2 * (size_t)DP * NH);
+    const size_t w0off = 324 + 252 + 4 * 324 + 252;
+    for (size_t k = 0; k < hbf.size(); k++) hbf[k] = to_bf16((float)h64[w0off + k]);
+    int rc;
+    if ((rc = dalloc(&m->d64, MODEL_DEV)) || (rc = dalloc(&m->d32, MODEL_DEV)) || (rc = dalloc(&m->dbf, hbf.size())))
+        return rc;
+    HIPCHK(hipMemcpy(m->d64, h64.data(), MODEL_DEV * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(m->d32, h32.data(), MODEL_DEV * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(m->dbf, hbf.data(), hbf.size() * 4, hipMemcpyHostToDevice));
+    m->m64 = model_ptrs(m->d64, m->dbf);
+    m->m32 = model_ptrs(m->d32, m->dbf);
+    *out = m.release();
+    return SL_OK;
+}
+
+extern "C" int nep_model_destroy(nep_model *m) {
+    if (!m) return SL_OK;
+    for (auto &e : m->eval_eng) delete e;
+    dfree(m->d64);
+    dfree(m->d32);
+    dfree(m->dbf);
+    delete m;
+    return SL_OK;
+}
+
+static int check_prec(sl_precision p) {
+    if (p != SL_FP64 && p != SL_FP32_MIXED && p != SL_FP32_BF16H) return fail(SL_E_INVALID, "unknown precision");
+    return SL_OK;
+}
+
+// evaluation of one system on the model's cached engine
+static int eval_common(const nep_model *mc, const sl_system_view *sys, sl_precision prec, Replica &r,
+                       Engine *&eng) {
+    nep_model *m = const_cast<nep_model *>(mc);
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r))) return rc;
+    Engine *&e = m->eval_eng[prec];
+    if (!e) {
+        e = new Engine();
+        e->M = m;
+        e->prec = prec;
+    }
+    eng = e;
+    e->reps.clear();   // the previous call's replica no longer exists
+    if ((rc = e->set_layout({&r}))) return rc;
+    return e->check_flags();
+}
+
+extern "C" int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec, double *energy,
+                             double *energy_atom, double *force, double *field, const sl_exec *ex) {
+    if (!m) return fail(SL_E_INVALID, "model is NULL");
+    std::lock_guard<std::mutex> lk(const_cast<nep_model *>(m)->eval_mu);
+    if (sys && sys->n_atoms == 0) {
+        int rc = check_prec(prec);
+        if (rc) return rc;
+        const double z = 0.0;
+        if (energy) {
+            if (ex && ex->device_ptrs) HIPCHK(hipMemcpy(energy, &z, 8, hipMemcpyHostToDevice));
+            else *energy = 0.0;
+        }
+        return SL_OK;
+    }
+    Replica r;
+    Engine *e = nullptr;
+    int rc = eval_common(m, sys, prec, r, e);
+    if (rc) return rc;
+    const int64_t n = r.n;
+    const bool dev = ex && ex->device_ptrs;
+    std::vector<double> Fh, Hh, Eh;
+    double *F = force, *H = field;
+    if (dev) {
+        if (force) { Fh.resize(3 * n); F = Fh.data(); }
+        if (field) { Hh.resize(3 * n); H = Hh.data(); }
+    }
+    if ((rc = e->download_ff(&r, F, H))) return rc;
+    if ((rc = e->ensure_obs(1))) return rc;
+    const Sys S = e->sys();
+    if (prec == SL_FP64) launch_observe(S, e->w64, e->chunks, e->n_chunks, e->chunk_ptr, e->partial, e->obs, e->st);
+    else launch_observe(S, e->w32, e->chunks, e->n_chunks, e->chunk_ptr, e->partial, e->obs, e->st);
+    double ob[NOBS];
+    HIPCHK(hipMemcpyAsync(ob, e->obs, sizeof(ob), hipMemcpyDeviceToHost, e->st));
+    HIPCHK(hipStreamSynchronize(e->st));
+    double *Ea = energy_atom;
+    if (dev && energy_atom) { Eh.resize(n); Ea = Eh.data(); }
+    if (Ea) {
+        if (prec == SL_FP64) rc = e->download_rows(&r, e->w64.Ei, 1, 1, Ea);
+        else rc = e->download_rows(&r, e->w32.Ei, 1, 1, Ea);
+        if (rc) return rc;
+    }
+    const double Etot = ob[0] + ob[2];
+    hipStream_t ust = ex && ex->hip_stream ? (hipStream_t)ex->hip_stream : e->st;
+    if (dev) {
+        if (energy) HIPCHK(hipMemcpyAsync(energy, &Etot, 8, hipMemcpyHostToDevice, ust));
+        if (force) HIPCHK(hipMemcpyAsync(force, Fh.data(), 24 * n, hipMemcpyHostToDevice, ust));
+        if (field) HIPCHK(hipMemcpyAsync(field, Hh.data(), 24 * n, hipMemcpyHostToDevice, ust));
+        if (energy_atom) HIPCHK(hipMemcpyAsync(energy_atom, Eh.data(), 8 * n, hipMemcpyHostToDevice, ust));
+        HIPCHK(hipStreamSynchronize(ust));
+    } else if (energy) {
+        *energy = Etot;
+    }
+    if (ob[8] != 0) return fail(SL_E_NONFINITE, "non-finite energy, force or state");
+    return SL_OK;
+}
+
+extern "C" int nep_spin_descriptors(const nep_model *m, const sl_system_view *sys, sl_precision prec, double *q,
+                                    double *Fp, const sl_exec *ex) {
+    if (!m) return fail(SL_E_INVALID, "model is NULL");
+    std::lock_guard<std::mutex> lk(const_cast<nep_model *>(m)->eval_mu);
+    if (sys && sys->n_atoms == 0) return check_prec(prec);
+    Replica r;
+    Engine *e = nullptr;
+    int rc = eval_common(m, sys, prec, r, e);
+    if (rc) return rc;
+    const bool dev = ex && ex->device_ptrs;
+    std::vector<double> qh, fh;
+    double *Q = q, *P = Fp;
+    if (dev) {
+        if (q) { qh.resize((size_t)r.n * ND); Q = qh.data(); }
+        if (Fp) { fh.resize((size_t)r.n * ND); P = fh.data(); }
+    }
+    if (Q) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.q, ND, DP, Q) : e->download_rows(&r, e->w32.q, ND, DP, Q);
+    if (rc) return rc;
+    if (P) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.Fp, ND, DP, P) : e->download_rows(&r, e->w32.Fp, ND, DP, P);
+    if (rc) return rc;
+    if (dev) {
+        hipStream_t ust = ex->hip_stream ? (hipStream_t)ex->hip_stream : e->st;
+        if (q) HIPCHK(hipMemcpyAsync(q, qh.data(), qh.size() * 8, hipMemcpyHostToDevice, ust));
+        if (Fp) HIPCHK(hipMemcpyAsync(Fp, fh.data(), fh.size() * 8, hipMemcpyHostToDevice, ust));
+        HIPCHK(hipStreamSynchronize(ust));
+    }
+    return SL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single-system simulation
+// ---------------------------------------------------------------------------
+
+struct sl_sim {
+    Engine eng;
+    Replica r;
+};
+
+static void fill_obs(const double *o, int64_t step, int64_t n_atoms, sl_observables *out) {
+    out->step = step;
+    out->E_pot = o[0];
+    out->E_kin = o[1];
+    out->E_zeeman = o[2];
+    out->T_lattice = n_atoms ? 2.0 * o[1] / (3.0 * n_atoms * KB) : 0.0;
+    out->T_spin = o[4] != 0 ? o[3] / (2.0 * KB * o[4]) : 0.0;
+    const double nfe = o[9];
+    for (int a = 0; a < 3; a++) out->M[a] = nfe > 0 ? o[5 + a] / nfe : 0.0;
+}
+
+extern "C" int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel, const int32_t *colour,
+                         const sl_integrator_params *ip, sl_precision prec, sl_sim **out) {
+    if (!out) return fail(SL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!m || !ip) return fail(SL_E_INVALID, "model and integrator parameters are required");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    auto s = std::make_unique<sl_sim>();
+    if ((rc = make_replica(sys, vel, colour, ip, true, s->r))) return rc;
+    s->eng.M = const_cast<nep_model *>(m);
+    s->eng.prec = prec;
+    s->eng.K_corr = ip->K_corr;
+    if ((rc = s->eng.set_layout({&s->r}))) return rc;
+    if ((rc = s->eng.check_flags())) return rc;
+    *out = s.release();
+    return SL_OK;
+}
+
+extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *per_step_out) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    if (n_steps < 0) return fail(SL_E_INVALID, "n_steps must be non-negative");
+    Engine &e = s->eng;
+    const int64_t chunk = 256;
+    std::vector<double> h(chunk * NOBS);
+    int rc;
+    if ((rc = e.ensure_obs(chunk))) return rc;
+    int64_t step0 = 0;
+    {
+        RepDev d;
+        HIPCHK(hipMemcpy(&d, e.rep, sizeof(RepDev), hipMemcpyDeviceToHost));
+        step0 = d.step;
+    }
+    for (int64_t done = 0; done < n_steps; done += chunk) {
+        const int64_t k = std::min(chunk, n_steps - done);
+        for (int64_t q = 0; q < k; q++) e.step(e.obs + q * NOBS);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h.data(), e.obs, k * NOBS * 8, hipMemcpyDeviceToHost, e.st));
+        HIPCHK(hipStreamSynchronize(e.st));
+        if ((rc = e.check_flags())) return rc;
+        for (int64_t q = 0; q < k; q++) {
+            double o[NOBS + 1];
+            std::memcpy(o, h.data() + q * NOBS, NOBS * 8);
+            o[9] = (double)s->r.n_fe;
+            if (per_step_out) fill_obs(o, step0 + done + q + 1, s->r.n, per_step_out + done + q);
+            if (o[8] != 0) return fail(SL_E_NONFINITE, "state became non-finite at step " + std::to_string(step0 + done + q + 1));
+        }
+    }
+    return SL_OK;
+}
+
+extern "C" int sl_get_state(const sl_sim *s, double *pos, double *vel, double *spin, int64_t *step) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    sl_sim *x = const_cast<sl_sim *>(s);
+    int rc = x->eng.download(&x->r, pos, vel, spin);
+    if (rc) return rc;
+    if (step) {
+        RepDev d;
+        HIPCHK(hipMemcpy(&d, x->eng.rep, sizeof(RepDev), hipMemcpyDeviceToHost));
+        *step = d.step;
+    }
+    return SL_OK;
+}
+
+extern "C" int sl_set_state(sl_sim *s, const double *pos, const double *vel, const double *spin, int64_t step) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    if (!pos || !vel || !spin) return fail(SL_E_INVALID, "pos, vel and spin are required");
+    Replica &r = s->r;
+    RepDev d;
+    HIPCHK(hipMemcpy(&d, s->eng.rep, sizeof(RepDev), hipMemcpyDeviceToHost));
+    r.dev = d;
+    r.dev.step = step;
+    r.dev.active = 1;
+    r.pos.assign(pos, pos + 3 * r.n);
+    r.vel.assign(vel, vel + 3 * r.n);
+    r.spin.assign(spin, spin + 3 * r.n);
+    for (int64_t q = 0; q < r.n - r.n_fe; q++) {
+        const int c = r.ge_idx[q];
+        r.spin[3 * c] = r.spin[3 * c + 1] = r.spin[3 * c + 2] = 0;
+    }
+    r.fe_off = r.ge_off = -1;   // re-upload from the host copies
+    s->eng.reps.clear();
+    int rc = s->eng.set_layout({&r});
+    if (rc) return rc;
+    return s->eng.check_flags();
+}
+
+extern "C" int sl_destroy(sl_sim *s) {
+    delete s;
+    return SL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// replica server
+// ---------------------------------------------------------------------------
+
+struct sl_server {
+    nep_model *m = nullptr;
+    sl_server_config cfg{};
+    Engine eng;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::deque<Replica *> queue;
+    std::map<uint64_t, std::unique_ptr<Replica>> all;
+    std::vector<Replica *> resident;
+    std::thread worker;
+    bool stop = false;
+    int worker_error = 0;
+    std::string worker_msg;
+    uint64_t next_id = 1;
+    double t0 = 0;
+    size_t budget = 0, used = 0;
+    int64_t batched_steps = 0;
+    double atom_steps = 0, busy = 0;
+    size_t pending = 0;
+
+    void run();
+};
+
+static double pct(std::vector<double> v, double p) {
+    if (v.empty()) return 0;
+    std::sort(v.begin(), v.end());
+    const double x = p * (v.size() - 1);
+    const size_t a = (size_t)x;
+    const size_t b = std::min(a + 1, v.size() - 1);
+    return v[a] + (v[b] - v[a]) * (x - a);
+}
+
+void sl_server::run() {
+    const int spb = std::max(1, cfg.steps_per_batch);
+    std::vector<hipEvent_t> ev(spb + 1);
+    for (auto &e : ev) (void)hipEventCreate(&e);
+    std::vector<double> hobs;
+    double last_done_t = 0;
+    for (;;) {
+        std::vector<Replica *> next;
+        bool changed = false;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            // retire finished or failed replicas
+            std::vector<Replica *> keep;
+            for (Replica *r : resident) {
+                if (r->steps_done >= r->n_steps || r->state == SL_FAILED) {
+                    lk.unlock();
+                    r->pos.assign(3 * r->n, 0);
+                    r->vel.assign(3 * r->n, 0);
+                    r->spin.assign(3 * r->n, 0);
+                    int rc = eng.download(r, r->pos.data(), r->vel.data(), r->spin.data());
+                    lk.lock();
+                    if (rc && r->state != SL_FAILED) {
+                        r->state = SL_FAILED;
+                        r->error = rc;
+                    }
+                    if (r->state != SL_FAILED) r->state = SL_DONE;
+                    r->t_done = now_s() - t0;
+                    used -= r->bytes;
+                    pending--;
+                    changed = true;
+                } else {
+                    keep.push_back(r);
+                }
+            }
+            // admit queued replicas while slots and budget allow (in arrival order)
+            while (!queue.empty() && (int)keep.size() < cfg.max_slots && used + queue.front()->bytes <= budget) {
+                Replica *r = queue.front();
+                queue.pop_front();
+                r->state = SL_RUNNING;
+                r->t_admit = now_s() - t0;
+                used += r->bytes;
+                keep.push_back(r);
+                changed = true;
+            }
+            if (changed) done_cv.notify_all();
+            if (keep.empty() && queue.empty()) {
+                resident.clear();
+                if (stop) break;
+                cv.wait(lk, [&] { return stop || !queue.empty(); });
+                if (stop && queue.empty()) break;
+                continue;
+            }
+            next = keep;
+        }
+        if (changed || next != eng.reps) {
+            int rc = eng.set_layout(next);
+            if (!rc) rc = eng.check_flags();
+            std::lock_guard<std::mutex> lk(mu);
+            resident = next;
+            if (rc) {
+                for (Replica *r : next) {
+                    r->state = SL_FAILED;
+                    r->error = rc;
+                }
+                worker_error = rc;
+                worker_msg = g_err;
+                continue;
+            }
+        }
+        // batched steps of every resident replica
+        int64_t k = spb;
+        for (Replica *r : next) k = std::min<int64_t>(k, r->n_steps - r->steps_done);
+        if (k <= 0) k = 1;
+        if (eng.ensure_obs(k)) {
+            std::lock_guard<std::mutex> lk(mu);
+            worker_error = SL_E_OOM;
+            for (Replica *r : next) { r->state = SL_FAILED; r->error = SL_E_OOM; }
+            continue;
+        }
+        const double tb = now_s();
+        (void)hipEventRecord(ev[0], eng.st);
+        const size_t nr = next.size();
+        for (int64_t q = 0; q < k; q++) {
+            eng.step(eng.obs + q * nr * NOBS);
+            (void)hipEventRecord(ev[q + 1], eng.st);
+        }
+        hobs.resize(k * nr * NOBS);
+        (void)hipMemcpyAsync(hobs.data(), eng.obs, hobs.size() * 8, hipMemcpyDeviceToHost, eng.st);
+        hipError_t herr = hipStreamSynchronize(eng.st);
+        int frc = herr == hipSuccess ? eng.check_flags() : SL_E_DEVICE;
+        const double te = now_s();
+        std::vector<double> lat(k);
+        for (int64_t q = 0; q < k; q++) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            lat[q] = ms * 1e-3;
+        }
+        // the first step of a batch also waited for the host
+        if (last_done_t > 0) lat[0] += std::max(0.0, tb - last_done_t);
+        last_done_t = te;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            batched_steps += k;
+            busy += te - tb;
+            for (size_t a = 0; a < nr; a++) {
+                Replica *r = next[a];
+                if (r->state != SL_RUNNING) continue;
+                const int64_t kk = std::min<int64_t>(k, r->n_steps - r->steps_done);
+                for (int64_t q = 0; q < kk; q++) {
+                    const double *o = hobs.data() + (q * nr + a) * NOBS;
+                    if (o[8] != 0 && r->state == SL_RUNNING) {
+                        r->state = SL_FAILED;
+                        r->error = SL_E_NONFINITE;
+                    }
+                    r->lat.push_back(lat[q]);
+                }
+                if (kk > 0) {
+                    std::memcpy(r->obs_last, hobs.data() + ((kk - 1) * nr + a) * NOBS, NOBS * 8);
+                    r->obs_step = r->dev.step + r->steps_done + kk;
+                }
+                r->steps_done += kk;
+                atom_steps += (double)kk * r->n;
+                if (frc) {
+                    r->state = SL_FAILED;
+                    r->error = frc;
+                }
+            }
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+}
+
+extern "C" int sl_server_create(const nep_model *m, const sl_server_config *cfg, sl_server **out) {
+    if (!out) return fail(SL_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!m || !cfg) return fail(SL_E_INVALID, "model and config are required");
+    int rc = check_prec(cfg->precision);
+    if (rc) return rc;
+    if (cfg->max_slots < 1 || cfg->steps_per_batch < 1 || cfg->K_corr < 0 || cfg->K_corr > 64)
+        return fail(SL_E_INVALID, "max_slots and steps_per_batch must be >= 1, K_corr in [0, 64]");
+    auto s = std::make_unique<sl_server>();
+    s->m = const_cast<nep_model *>(m);
+    s->cfg = *cfg;
+    s->eng.M = s->m;
+    s->eng.prec = cfg->precision;
+    s->eng.K_corr = cfg->K_corr;
+    size_t budget = cfg->hbm_budget_bytes;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        const size_t reserve = (size_t)4 << 30;
+        budget = fr > reserve ? fr - reserve : fr / 2;
+    }
+    s->budget = budget;
+    s->t0 = now_s();
+    sl_server *raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return SL_OK;
+}
+
+extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const double *vel, const int32_t *colour,
+                                 const sl_integrator_params *ip, int64_t n_steps, uint64_t *id_out) {
+    if (!sv || !ip || !id_out) return fail(SL_E_INVALID, "server, params and id_out are required");
+    if (ip->K_corr != sv->cfg.K_corr) return fail(SL_E_INVALID, "K_corr must equal the server's");
+    if (n_steps < 1) return fail(SL_E_INVALID, "n_steps must be >= 1");
+    auto r = std::make_unique<Replica>();
+    int rc = make_replica(sys, vel, colour, ip, true, *r);
+    if (rc) return rc;
+    r->n_steps = n_steps;
+    r->bytes = bytes_per_atom(sv->cfg.precision) * (size_t)r->n + 4096;
+    if (r->bytes > sv->budget) return fail(SL_E_OOM, "replica larger than the whole HBM budget");
+    r->dev.step_end = r->dev.step + n_steps;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    r->id = sv->next_id++;
+    r->t_submit = now_s() - sv->t0;
+    r->state = SL_QUEUED;
+    *id_out = r->id;
+    sv->queue.push_back(r.get());
+    sv->all[r->id] = std::move(r);
+    sv->pending++;
+    sv->cv.notify_all();
+    return SL_OK;
+}
+
+extern "C" int sl_replica_poll(sl_server *sv, uint64_t id, sl_replica_status *out) {
+    if (!sv || !out) return fail(SL_E_INVALID, "server and out are required");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(id);
+    if (it == sv->all.end()) return fail(SL_E_NOTFOUND, "unknown replica id");
+    Replica *r = it->second.get();
+    out->state = r->state;
+    out->error = r->error;
+    out->steps_done = r->steps_done;
+    out->n_steps = r->n_steps;
+    out->t_submit = r->t_submit;
+    out->t_admit = r->t_admit;
+    out->t_done = r->t_done;
+    out->step_latency_p50 = pct(r->lat, 0.50);
+    out->step_latency_p99 = pct(r->lat, 0.99);
+    out->n_latency_samples = (int64_t)r->lat.size();
+    return SL_OK;
+}
+
+extern "C" int sl_replica_fetch(sl_server *sv, uint64_t id, double *pos, double *vel, double *spin,
+                                sl_observables *obs) {
+    if (!sv) return fail(SL_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(id);
+    if (it == sv->all.end()) return fail(SL_E_NOTFOUND, "unknown replica id");
+    Replica *r = it->second.get();
+    if (r->state == SL_QUEUED || r->state == SL_RUNNING) return fail(SL_E_BUSY, "replica not finished");
+    if (r->state == SL_FAILED) return fail(r->error ? r->error : SL_E_NONFINITE, "replica failed");
+    if (pos) std::memcpy(pos, r->pos.data(), 24 * r->n);
+    if (vel) std::memcpy(vel, r->vel.data(), 24 * r->n);
+    if (spin) std::memcpy(spin, r->spin.data(), 24 * r->n);
+    if (obs) {
+        double o[NOBS + 1];
+        std::memcpy(o, r->obs_last, NOBS * 8);
+        o[9] = (double)r->n_fe;
+        fill_obs(o, r->obs_step, r->n, obs);
+    }
+    return SL_OK;
+}
+
+extern "C" int sl_server_drain(sl_server *sv) {
+    if (!sv) return fail(SL_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->done_cv.wait(lk, [&] { return sv->pending == 0 || sv->worker_error != 0; });
+    if (sv->worker_error) return fail(sv->worker_error, "server worker: " + sv->worker_msg);
+    return SL_OK;
+}
+
+extern "C" int sl_server_stats(sl_server *sv, int64_t *batched_steps, double *atom_steps, double *busy_s) {
+    if (!sv) return fail(SL_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (batched_steps) *batched_steps = sv->batched_steps;
+    if (atom_steps) *atom_steps = sv->atom_steps;
+    if (busy_s) *busy_s = sv->busy;
+    return SL_OK;
+}
+
+extern "C" int sl_server_destroy(sl_server *sv) {
+    if (!sv) return SL_OK;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv.notify_all();
+    }
+    if (sv->worker.joinable()) sv->worker.join();
+    delete sv;
+    return SL_OK;
+}

@@ -1,0 +1,80 @@
+// engine.h -- device data of one batch of replicas and the kernel launchers.
+#pragma once
+
+#include "common.h"
+
+namespace nep {
+
+constexpr int MAXFE = 64;     // listed spin-carrying neighbours kept for the spin couplings
+
+// flags[] words
+enum { F_REBUILD = 0, F_OVERFLOW = 1, F_COLOUR = 2, F_NONFINITE = 3, NFLAGS = 8 };
+
+// Atoms of all resident replicas, concatenated: [0, N_fe) are spin-carrying
+// (species 0) atoms of every replica in replica order, [N_fe, N) the others.
+// Slot-major neighbour arrays are indexed [slot * N + atom].
+struct Sys {
+    int N, N_fe, n_rep, n_cells;
+    const int *rid;        // [N]
+    const int *orig;       // [N] index in the replica's caller order
+    RepDev *rep;           // [n_rep]
+    d4 *pos, *vel, *spin, *force, *field, *pos_ref, *spin_n, *spin_hat, *eta;
+    const int *colour;     // [N] colour on spin carriers, -1 elsewhere
+    int *nbrR, *cntR, *cntFeR, *revR;
+    int *nbrA, *cntA, *cntFeA, *revA, *a2r;
+    int *cell_of, *cell_cnt, *cell_start, *cell_fill, *cell_atoms;
+    int *flags;
+};
+
+template <typename real>
+struct ModelDev {
+    const real *cR, *cA, *cEX, *cDM, *cAN, *cSI, *cSA;   // [4][n][9]
+    const real *W0;        // [2][64][DP], zero padded
+    const real *b0, *w1, *b1;
+    const float *W0bf;     // [2][64][DP], W0 rounded to bf16 (for the BF16 variant)
+};
+
+template <typename real>
+struct Work {
+    real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
+    real *pbR, *pbA;            // pair records [MAXR|MAXA][N][6]: dE_i/dd_ij, dE_i/ds_j
+    real *ownR, *ownA;          // [N][6]: sum_j dE_i/dd_ij, dE_i/ds_i
+    real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij
+    real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat
+    real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i
+    int bf16;                   // read-out input->hidden contraction in BF16
+};
+
+// ---- launchers (kernels_*.hip) ----
+void launch_skin_check(const Sys &S, hipStream_t st);
+void launch_rebuild(const Sys &S, double r_listR, double r_listA, hipStream_t st);
+
+template <typename real>
+void launch_forward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin,
+                    hipStream_t st);
+template <typename real>
+void launch_backward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, const int *col_idx,
+                  int n_colours, hipStream_t st);
+
+void launch_kick(const Sys &S, hipStream_t st);
+void launch_drift(const Sys &S, hipStream_t st);
+void launch_langevin(const Sys &S, hipStream_t st);
+void launch_spin_prep(const Sys &S, hipStream_t st);
+void launch_spin_restore(const Sys &S, hipStream_t st);
+void launch_spin_mid(const Sys &S, hipStream_t st);
+void launch_step_end(const Sys &S, hipStream_t st);
+
+// per-replica fixed-order reductions: out[r][NOBS]
+constexpr int NOBS = 9;   // E_nep, E_kin, E_z, Ts_num, Ts_den, Mx, My, Mz, nonfinite
+struct Chunk {
+    int rid, begin, end;
+};
+template <typename real>
+void launch_observe(const Sys &S, const Work<real> &W, const Chunk *chunks, int n_chunks,
+                    const int *chunk_ptr, double *partial, double *out, hipStream_t st);
+
+}  // namespace nep

@@ -1,0 +1,296 @@
+// kernels_int.hip -- the spin-lattice step on the device: velocity and
+// position half-steps, the lattice Langevin step, the spin sweep over a fixed
+// colouring of the spin carriers, and fixed-order per-replica reductions.
+// Positions, velocities, spins and all sums are FP64.
+#include "engine.h"
+
+namespace nep {
+
+namespace {
+
+inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+__global__ void k_kick(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    if (!R.active) return;
+    const double c = 0.5 * R.dt * KAPPA / mass_of(i < S.N_fe ? 0 : 1);
+    d4 v = S.vel[i];
+    const d4 f = S.force[i];
+    v.x += c * f.x;
+    v.y += c * f.y;
+    v.z += c * f.z;
+    S.vel[i] = v;
+}
+
+__global__ void k_drift(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    if (!R.active) return;
+    const double h = 0.5 * R.dt;
+    d4 p = S.pos[i];
+    const d4 v = S.vel[i];
+    p.x += h * v.x;
+    p.y += h * v.y;
+    p.z += h * v.z;
+    if (R.pbc[0]) p.x -= R.box[0] * floor(p.x / R.box[0]);
+    if (R.pbc[1]) p.y -= R.box[1] * floor(p.y / R.box[1]);
+    if (R.pbc[2]) p.z -= R.box[2] * floor(p.z / R.box[2]);
+    S.pos[i] = p;
+}
+
+__device__ inline double temperature(const RepDev &R) { return R.T0 + (R.T1 - R.T0) * ramp_frac(R); }
+
+__global__ void k_langevin(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    if (!R.active || R.ensemble != 1) return;
+    const double c1 = exp(-R.gammaL * R.dt);
+    const double sig = sqrt((1.0 - c1 * c1) * KAPPA * KB * temperature(R) / mass_of(i < S.N_fe ? 0 : 1));
+    double xi[3];
+    gauss3(R.seed, (uint32_t)S.orig[i], (unsigned long long)R.step, 0u, xi);
+    d4 v = S.vel[i];
+    v.x = c1 * v.x + sig * xi[0];
+    v.y = c1 * v.y + sig * xi[1];
+    v.z = c1 * v.z + sig * xi[2];
+    S.vel[i] = v;
+}
+
+// noise field of the step and the reference copies S^n, S_hat
+__global__ void k_spin_prep(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    if (!R.active) return;
+    const double T = temperature(R);
+    d4 e = {0, 0, 0, 0};
+    if (R.alpha > 0 && T > 0) {
+        const double sig = sqrt(2.0 * R.alpha * KB * T * HBAR / R.dt);
+        double xi[3];
+        gauss3(R.seed, (uint32_t)S.orig[i], (unsigned long long)R.step, 1u, xi);
+        e.x = sig * xi[0];
+        e.y = sig * xi[1];
+        e.z = sig * xi[2];
+    }
+    S.eta[i] = e;
+    const d4 s = S.spin[i];
+    S.spin_n[i] = s;
+    S.spin_hat[i] = s;
+}
+
+__global__ void k_spin_restore(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    if (!S.rep[S.rid[i]].active) return;
+    S.spin[i] = S.spin_n[i];
+}
+
+__global__ void k_spin_mid(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    if (!S.rep[S.rid[i]].active) return;
+    const d4 a = S.spin_n[i], b = S.spin[i];
+    const double x = 0.5 * (a.x + b.x), y = 0.5 * (a.y + b.y), z = 0.5 * (a.z + b.z);
+    const double n = sqrt(x * x + y * y + z * z);
+    d4 h = {x / n, y / n, z / n, 0.0};
+    S.spin_hat[i] = h;
+}
+
+// One colour class: every spin takes an implicit-midpoint Rodrigues rotation
+// over tau = dt/2 in the field of its (other-colour) neighbours, its own
+// anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
+template <typename real>
+__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, const int *idx, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const int i = idx[t];
+    const RepDev &R = S.rep[S.rid[i]];
+    if (!R.active) return;
+    const size_t ld = S.N, lf = S.N_fe;
+    const int nfe = min(S.cntFeR[i], MAXFE);
+    double hx = 0, hy = 0, hz = 0;
+    for (int s = 0; s < nfe; s++) {
+        const int j = S.nbrR[s * ld + i];
+        const real *c = W.cpl + ((size_t)s * lf + i) * 6;
+        const double J = c[0], D = c[1], K = c[2], rx = c[3], ry = c[4], rz = c[5];
+        const d4 sj = S.spin[j];
+        const double sr = sj.x * rx + sj.y * ry + sj.z * rz;
+        hx -= J * sj.x + D * (sj.y * rz - sj.z * ry) + K * sr * rx;
+        hy -= J * sj.y + D * (sj.z * rx - sj.x * rz) + K * sr * ry;
+        hz -= J * sj.z + D * (sj.x * ry - sj.y * rx) + K * sr * rz;
+    }
+    const real *o = W.selfc + (size_t)i * 8;
+    const double Axx = o[0], Ayy = o[1], Azz = o[2], Axy = o[3], Axz = o[4], Ayz = o[5], os = o[6];
+    const double fr = ramp_frac(R), zs = R.mu_s * MUB;
+    const d4 e = S.eta[i];
+    hx += zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr) + e.x;
+    hy += zs * (R.B0[1] + (R.B1[1] - R.B0[1]) * fr) + e.y;
+    hz += zs * (R.B0[2] + (R.B1[2] - R.B0[2]) * fr) + e.z;
+    const double al = R.alpha, inv = 1.0 / (1.0 + al * al), tau = 0.5 * R.dt / HBAR;
+    const d4 s4 = S.spin[i];
+    const double sx = s4.x, sy = s4.y, sz = s4.z;
+    double yx = sx, yy = sy, yz = sz;
+    for (int it = 0; it < R.mid_cap; it++) {
+        double mx = sx + yx, my = sy + yy, mz = sz + yz;
+        const double mn = 1.0 / sqrt(mx * mx + my * my + mz * mz);
+        mx *= mn;
+        my *= mn;
+        mz *= mn;
+        const double h0 = hx - 2.0 * (Axx * mx + Axy * my + Axz * mz + os * mx);
+        const double h1 = hy - 2.0 * (Axy * mx + Ayy * my + Ayz * mz + os * my);
+        const double h2 = hz - 2.0 * (Axz * mx + Ayz * my + Azz * mz + os * mz);
+        const double wx = (h0 + al * (my * h2 - mz * h1)) * inv;
+        const double wy = (h1 + al * (mz * h0 - mx * h2)) * inv;
+        const double wz = (h2 + al * (mx * h1 - my * h0)) * inv;
+        const double wn = sqrt(wx * wx + wy * wy + wz * wz);
+        double nx, ny, nz;
+        if (wn == 0.0) {
+            nx = sx;
+            ny = sy;
+            nz = sz;
+        } else {
+            const double th = wn * tau;
+            double sn, cs, omc;
+            if (fabs(th) < 1e-8) {
+                sn = th - th * th * th / 6.0;
+                cs = 1.0 - th * th / 2.0;
+                omc = th * th / 2.0;
+            } else {
+                sincos(th, &sn, &cs);
+                omc = 1.0 - cs;
+            }
+            const double ux = wx / wn, uy = wy / wn, uz = wz / wn;
+            const double us = ux * sx + uy * sy + uz * sz;
+            nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
+            ny = sy * cs + (uz * sx - ux * sz) * sn + uy * us * omc;
+            nz = sz * cs + (ux * sy - uy * sx) * sn + uz * us * omc;
+        }
+        const double diff = fmax(fabs(nx - yx), fmax(fabs(ny - yy), fabs(nz - yz)));
+        yx = nx;
+        yy = ny;
+        yz = nz;
+        if (diff <= R.mid_tol) break;
+    }
+    d4 out = {yx, yy, yz, 0.0};
+    S.spin[i] = out;
+}
+
+__global__ void k_step_end(Sys S) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= S.n_rep) return;
+    RepDev &R = S.rep[r];
+    if (!R.active) return;
+    R.step += 1;
+    if (R.step >= R.step_end) R.active = 0;
+}
+
+// per-chunk partial sums of the observables (fixed tree), then per replica
+template <typename real>
+__global__ void __launch_bounds__(256) k_obs_partial(Sys S, Work<real> W, const Chunk *chunks, double *partial) {
+    __shared__ double red[NOBS][256];
+    const Chunk c = chunks[blockIdx.x];
+    const int t = threadIdx.x;
+    double v[NOBS];
+#pragma unroll
+    for (int k = 0; k < NOBS; k++) v[k] = 0;
+    const int i = c.begin + t;
+    if (i < c.end) {
+        const RepDev &R = S.rep[c.rid];
+        const int fe = i < S.N_fe;
+        const d4 vel = S.vel[i], s = S.spin[i], H = S.field[i], p = S.pos[i], F = S.force[i];
+        const double m = mass_of(fe ? 0 : 1);
+        v[0] = (double)W.Ei[i];
+        v[1] = 0.5 * m * (vel.x * vel.x + vel.y * vel.y + vel.z * vel.z) / KAPPA;
+        if (fe) {
+            const double fr = ramp_frac(R), zs = R.mu_s * MUB;
+            v[2] = -zs * ((R.B0[0] + (R.B1[0] - R.B0[0]) * fr) * s.x + (R.B0[1] + (R.B1[1] - R.B0[1]) * fr) * s.y +
+                          (R.B0[2] + (R.B1[2] - R.B0[2]) * fr) * s.z);
+            const double cx = s.y * H.z - s.z * H.y, cy = s.z * H.x - s.x * H.z, cz = s.x * H.y - s.y * H.x;
+            v[3] = cx * cx + cy * cy + cz * cz;
+            v[4] = s.x * H.x + s.y * H.y + s.z * H.z;
+            v[5] = s.x;
+            v[6] = s.y;
+            v[7] = s.z;
+        }
+        const double chk = p.x + p.y + p.z + vel.x + vel.y + vel.z + s.x + s.y + s.z + F.x + F.y + F.z + v[0];
+        v[8] = isfinite(chk) ? 0.0 : 1.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NOBS; k++) red[k][t] = v[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int k = 0; k < NOBS; k++) red[k][t] += red[k][t + off];
+        __syncthreads();
+    }
+    if (t < NOBS) partial[(size_t)blockIdx.x * NOBS + t] = red[t][0];
+}
+
+__global__ void k_obs_final(Sys S, const int *chunk_ptr, const double *partial, double *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= S.n_rep) return;
+    double v[NOBS];
+#pragma unroll
+    for (int k = 0; k < NOBS; k++) v[k] = 0;
+    for (int c = chunk_ptr[r]; c < chunk_ptr[r + 1]; c++)
+#pragma unroll
+        for (int k = 0; k < NOBS; k++) v[k] += partial[(size_t)c * NOBS + k];
+#pragma unroll
+    for (int k = 0; k < NOBS; k++) out[(size_t)r * NOBS + k] = v[k];
+}
+
+}  // namespace
+
+void launch_kick(const Sys &S, hipStream_t st) {
+    if (S.N) hipLaunchKernelGGL(k_kick, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+}
+void launch_drift(const Sys &S, hipStream_t st) {
+    if (S.N) hipLaunchKernelGGL(k_drift, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+}
+void launch_langevin(const Sys &S, hipStream_t st) {
+    if (S.N) hipLaunchKernelGGL(k_langevin, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+}
+void launch_spin_prep(const Sys &S, hipStream_t st) {
+    if (S.N_fe) hipLaunchKernelGGL(k_spin_prep, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S);
+}
+void launch_spin_restore(const Sys &S, hipStream_t st) {
+    if (S.N_fe) hipLaunchKernelGGL(k_spin_restore, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S);
+}
+void launch_spin_mid(const Sys &S, hipStream_t st) {
+    if (S.N_fe) hipLaunchKernelGGL(k_spin_mid, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S);
+}
+void launch_step_end(const Sys &S, hipStream_t st) {
+    if (S.n_rep) hipLaunchKernelGGL(k_step_end, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S);
+}
+
+template <typename real>
+void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, const int *col_idx,
+                  int n_colours, hipStream_t st) {
+    for (int pass = 0; pass < 2; pass++)
+        for (int cc = 0; cc < n_colours; cc++) {
+            const int c = pass == 0 ? cc : n_colours - 1 - cc;
+            const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
+            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256)), dim3(256), 0, st, S, W, col_idx + b, n);
+        }
+}
+
+template <typename real>
+void launch_observe(const Sys &S, const Work<real> &W, const Chunk *chunks, int n_chunks,
+                    const int *chunk_ptr, double *partial, double *out, hipStream_t st) {
+    if (n_chunks == 0) return;
+    hipLaunchKernelGGL(k_obs_partial<real>, dim3(n_chunks), dim3(256), 0, st, S, W, chunks, partial);
+    hipLaunchKernelGGL(k_obs_final, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S, chunk_ptr, partial, out);
+}
+
+template void launch_sweep<double>(const Sys &, const Work<double> &, const int *, const int *, int, hipStream_t);
+template void launch_sweep<float>(const Sys &, const Work<float> &, const int *, const int *, int, hipStream_t);
+template void launch_observe<double>(const Sys &, const Work<double> &, const Chunk *, int, const int *, double *,
+                                     double *, hipStream_t);
+template void launch_observe<float>(const Sys &, const Work<float> &, const Chunk *, int, const int *, double *,
+                                    double *, hipStream_t);
+
+}  // namespace nep

@@ -1,0 +1,869 @@
+// kernels_nep.hip -- the spin-aware NEP on the device: descriptor, per-species
+// read-out, backward pass (forces and effective fields) and the bilinear spin
+// couplings of the frozen-Fp magnetic energy.
+//
+// Mapping. Radial-set work (radial, exchange, DMI, anisotropic, single-ion
+// channels over the 6 A list) runs one lane per atom. Angular-set work
+// (angular and spin-angular channels over the 4.5 A list) runs eight lanes
+// per atom, lane n owning the 24 harmonic accumulators A_nlm and B_nlm of
+// radial function n. Spin-carrying atoms occupy the leading index range and
+// every grid is split so that a wavefront never mixes species; neighbour
+// rows list spin carriers first, so the pair type tau, and with it every
+// coefficient address, is uniform across the wavefront inside each loop.
+// Sums over neighbours run in list order (ascending atom index): results are
+// deterministic and independent of how replicas are batched.
+//
+// Gather without atomics: the backward pass writes, per listed pair (i,j),
+// dE_i/dd_ij and dE_i/ds_j into a pair record; a gather kernel then forms
+// F_k = sum_j dE_k/dd_kj - sum_j dE_j/dd_jk and H_k = -(dE_k/ds_k + sum_j dE_j/ds_k)
+// by reading the partner's record at the reverse slot.
+#include "engine.h"
+
+namespace nep {
+
+namespace {
+
+// grid split: blocks [0, nbFe) take spin carriers, the rest the others
+__device__ inline int atom_of_block(const Sys &S, int per_block, int nbFe, int local, bool &fe) {
+    const int b = blockIdx.x;
+    if (b < nbFe) {
+        fe = true;
+        const int i = b * per_block + local;
+        return i < S.N_fe ? i : -1;
+    }
+    fe = false;
+    const int i = S.N_fe + (b - nbFe) * per_block + local;
+    return i < S.N ? i : -1;
+}
+
+template <typename real>
+__device__ inline void load_spin(const d4 *sp, int j, real s[3]) {
+    const d4 v = sp[j];
+    s[0] = (real)v.x;
+    s[1] = (real)v.y;
+    s[2] = (real)v.z;
+}
+
+// displacement in FP64, then cast
+template <typename real>
+__device__ inline real geom(const Sys &S, const RepDev &R, const d4 &pi, int j, real d[3]) {
+    double dx, dy, dz;
+    min_image(R, pi, S.pos[j], dx, dy, dz);
+    d[0] = (real)dx;
+    d[1] = (real)dy;
+    d[2] = (real)dz;
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+// C[k] = sum_n Fp[n] c[n][k]  (coefficients wave-uniform)
+template <typename real>
+__device__ inline void contract(const real *c, const real *Fp, int nn, real C[NB]) {
+#pragma unroll
+    for (int k = 0; k < NB; k++) C[k] = 0;
+    for (int n = 0; n < nn; n++) {
+        const real f = Fp[n];
+#pragma unroll
+        for (int k = 0; k < NB; k++) C[k] += f * c[n * NB + k];
+    }
+}
+
+template <typename real>
+__device__ inline real dotk(const real C[NB], const real f[NB]) {
+    real s = 0;
+#pragma unroll
+    for (int k = 0; k < NB; k++) s += C[k] * f[k];
+    return s;
+}
+
+template <typename real>
+__device__ inline real xor_sum8(real v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    return v;
+}
+
+// -------------------------------------------------------------------------
+// forward: radial set (lane per atom)
+// -------------------------------------------------------------------------
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Work<real> W, const d4 *spin,
+                                                     int nbFe) {
+    bool fe;
+    const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
+    if (i < 0) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_R, rc2 = rc * rc;
+    const int cnt = S.cntR[i], nfe = S.cntFeR[i];
+    const size_t ld = S.N;
+    real *q = W.q + (size_t)i * DP;
+    real qR[NR], qE[NR], qD[NR], qA[NR], qS[NR];
+#pragma unroll
+    for (int n = 0; n < NR; n++) qR[n] = qE[n] = qD[n] = qA[n] = qS[n] = 0;
+    real si[3];
+    load_spin(spin, i, si);
+    if (fe) {
+        real FR[NB], FE[NB], FD[NB], FA[NB], FS[NB];
+#pragma unroll
+        for (int k = 0; k < NB; k++) FR[k] = FE[k] = FD[k] = FA[k] = FS[k] = 0;
+        for (int s = 0; s < nfe; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            const real r = dsqrt(r2), ir = real(1) / r;
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB];
+            radial_basis(r, rc, f);
+            real sj[3];
+            load_spin(spin, j, sj);
+            const real ss = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+            const real cx = si[1] * sj[2] - si[2] * sj[1], cy = si[2] * sj[0] - si[0] * sj[2],
+                       cz = si[0] * sj[1] - si[1] * sj[0];
+            const real dm = rh[0] * cx + rh[1] * cy + rh[2] * cz;
+            const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
+            const real b = sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2];
+            const real ab = a * b, aa = a * a;
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                FR[k] += f[k];
+                FE[k] += f[k] * ss;
+                FD[k] += f[k] * dm;
+                FA[k] += f[k] * ab;
+                FS[k] += f[k] * aa;
+            }
+        }
+        // contract with tau = (Fe, Fe) coefficients
+        for (int n = 0; n < NR; n++) {
+            const int o = (0 * NR + n) * NB;
+            real r_ = 0, e_ = 0, d_ = 0, a_ = 0, s_ = 0;
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                r_ += M.cR[o + k] * FR[k];
+                e_ += M.cEX[o + k] * FE[k];
+                d_ += M.cDM[o + k] * FD[k];
+                a_ += M.cAN[o + k] * FA[k];
+                s_ += M.cSI[o + k] * FS[k];
+            }
+            qR[n] = r_;
+            qE[n] = e_;
+            qD[n] = d_;
+            qA[n] = a_;
+            qS[n] = s_;
+        }
+        // non-magnetic neighbours: only the radial and single-ion channels survive
+#pragma unroll
+        for (int k = 0; k < NB; k++) FR[k] = FS[k] = 0;
+        for (int s = nfe; s < cnt; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            const real r = dsqrt(r2), ir = real(1) / r;
+            real f[NB];
+            radial_basis(r, rc, f);
+            const real a = (si[0] * d[0] + si[1] * d[1] + si[2] * d[2]) * ir;
+            const real aa = a * a;
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                FR[k] += f[k];
+                FS[k] += f[k] * aa;
+            }
+        }
+        for (int n = 0; n < NR; n++) {
+            const int o = (1 * NR + n) * NB;
+            real r_ = 0, s_ = 0;
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                r_ += M.cR[o + k] * FR[k];
+                s_ += M.cSI[o + k] * FS[k];
+            }
+            qR[n] += r_;
+            qS[n] += s_;
+        }
+        q[D_OS] = si[0] * si[0] + si[1] * si[1] + si[2] * si[2];
+    } else {
+        for (int part = 0; part < 2; part++) {
+            real FR[NB];
+#pragma unroll
+            for (int k = 0; k < NB; k++) FR[k] = 0;
+            const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            for (int s = b; s < e; s++) {
+                const int j = S.nbrR[s * ld + i];
+                real d[3];
+                const real r2 = geom(S, R, pi, j, d);
+                if (r2 >= rc2) continue;
+                real f[NB];
+                radial_basis(dsqrt(r2), rc, f);
+#pragma unroll
+                for (int k = 0; k < NB; k++) FR[k] += f[k];
+            }
+            const int tau = 2 + part;
+            for (int n = 0; n < NR; n++) {
+                const int o = (tau * NR + n) * NB;
+                real r_ = 0;
+#pragma unroll
+                for (int k = 0; k < NB; k++) r_ += M.cR[o + k] * FR[k];
+                qR[n] += r_;
+            }
+        }
+        q[D_OS] = 0;
+    }
+#pragma unroll
+    for (int n = 0; n < NR; n++) {
+        q[D_R + n] = qR[n];
+        q[D_EX + n] = qE[n];
+        q[D_DM + n] = qD[n];
+        q[D_AN + n] = qA[n];
+        q[D_SI + n] = qS[n];
+    }
+}
+
+// -------------------------------------------------------------------------
+// forward: angular set (eight lanes per atom, lane n < 7 owns function n)
+// -------------------------------------------------------------------------
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, Work<real> W, const d4 *spin,
+                                                      int nbFe) {
+    const int lane = threadIdx.x & 7;
+    bool fe;
+    const int i = atom_of_block(S, 32, nbFe, threadIdx.x >> 3, fe);
+    if (i < 0) return;
+    const int n = lane < NA ? lane : NA - 1;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_A, rc2 = rc * rc;
+    const int cnt = S.cntA[i], nfe = S.cntFeA[i];
+    const size_t ld = S.N;
+    real si[3];
+    load_spin(spin, i, si);
+    real A[NLM], B[NLM];
+#pragma unroll
+    for (int m = 0; m < NLM; m++) A[m] = B[m] = 0;
+    const int tc = fe ? 0 : 2;
+    for (int part = 0; part < 2; part++) {
+        const int tau = tc + part;
+        real cA[NB], cS[NB];
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            cA[k] = M.cA[(tau * NA + n) * NB + k];
+            cS[k] = M.cSA[(tau * NA + n) * NB + k];
+        }
+        const bool spins = fe && part == 0;
+        const int b = part ? nfe : 0, e = part ? cnt : nfe;
+        for (int s = b; s < e; s++) {
+            const int j = S.nbrA[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            const real r = dsqrt(r2), ir = real(1) / r;
+            real f[NB];
+            radial_basis(r, rc, f);
+            const real gA = dotk(cA, f);
+            real gS = 0;
+            if (spins) {
+                real sj[3];
+                load_spin(spin, j, sj);
+                gS = dotk(cS, f) * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
+            }
+            real Y[NLM];
+            harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+#pragma unroll
+            for (int m = 0; m < NLM; m++) {
+                A[m] += gA * Y[m];
+                B[m] += gS * Y[m];
+            }
+        }
+    }
+    if (lane >= NA) return;
+    real qa[4] = {0, 0, 0, 0}, qs[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < NLM; m++) {
+        qa[l_of_lm(m) - 1] += A[m] * A[m];
+        qs[l_of_lm(m) - 1] += A[m] * B[m];
+    }
+    real *q = W.q + (size_t)i * DP;
+#pragma unroll
+    for (int l = 0; l < 4; l++) {
+        q[D_A + 4 * n + l] = qa[l];
+        q[D_SA + 4 * n + l] = qs[l];
+    }
+    real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+#pragma unroll
+    for (int m = 0; m < NLM; m++) {
+        ab[m] = A[m];
+        ab[NLM + m] = B[m];
+    }
+}
+
+// -------------------------------------------------------------------------
+// per-species read-out (lane per atom; weights wave-uniform)
+// -------------------------------------------------------------------------
+
+__device__ inline float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(128) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
+    bool fe;
+    const int i = atom_of_block(S, 128, nbFe, threadIdx.x, fe);
+    if (i < 0) return;
+    const int t = fe ? 0 : 1;
+    const real *W0 = M.W0 + (size_t)t * DP * NH;   // [d][h]
+    const real *q = W.q + (size_t)i * DP;
+    real z[NH];
+#pragma unroll
+    for (int h = 0; h < NH; h++) z[h] = M.b0[t * NH + h];
+    if (W.bf16) {
+        const float *Wb = M.W0bf + (size_t)t * DP * NH;
+        for (int d = 0; d < ND; d++) {
+            const real qd = (real)bf16_round((float)q[d]);
+#pragma unroll
+            for (int h = 0; h < NH; h++) z[h] += (real)Wb[d * NH + h] * qd;
+        }
+    } else {
+        for (int d = 0; d < ND; d++) {
+            const real qd = q[d];
+#pragma unroll
+            for (int h = 0; h < NH; h++) z[h] += W0[d * NH + h] * qd;
+        }
+    }
+    real E = M.b1[t];
+#pragma unroll
+    for (int h = 0; h < NH; h++) {
+        const real a = dtanh(z[h]);
+        const real w = M.w1[t * NH + h];
+        E += w * a;
+        z[h] = w * (real(1) - a * a);
+    }
+    real *Fp = W.Fp + (size_t)i * DP;
+    for (int d = 0; d < ND; d++) {
+        real s = 0;
+#pragma unroll
+        for (int h = 0; h < NH; h++) s += W0[d * NH + h] * z[h];
+        Fp[d] = s;
+    }
+    W.Ei[i] = E;
+}
+
+// -------------------------------------------------------------------------
+// backward: radial set (lane per atom)
+// -------------------------------------------------------------------------
+
+template <typename real>
+__device__ inline void put_pair(real *pb, size_t idx, const real G[3], const real h[3]) {
+    real *p = pb + idx * 6;
+    p[0] = G[0];
+    p[1] = G[1];
+    p[2] = G[2];
+    p[3] = h[0];
+    p[4] = h[1];
+    p[5] = h[2];
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
+    bool fe;
+    const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
+    if (i < 0) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_R, rc2 = rc * rc;
+    const int cnt = S.cntR[i], nfe = S.cntFeR[i];
+    const size_t ld = S.N;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    const real zero3[3] = {0, 0, 0};
+    real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    if (fe) {
+        real si[3];
+        load_spin(S.spin, i, si);
+        const real os2 = real(2) * Fp[D_OS];
+        h[0] = os2 * si[0];
+        h[1] = os2 * si[1];
+        h[2] = os2 * si[2];
+        {
+            real CR[NB], CE[NB], CD[NB], CA[NB], CS[NB];
+            contract(M.cR, Fp + D_R, NR, CR);
+            contract(M.cEX, Fp + D_EX, NR, CE);
+            contract(M.cDM, Fp + D_DM, NR, CD);
+            contract(M.cAN, Fp + D_AN, NR, CA);
+            contract(M.cSI, Fp + D_SI, NR, CS);
+            for (int s = 0; s < nfe; s++) {
+                const int j = S.nbrR[s * ld + i];
+                real d[3];
+                const real r2 = geom(S, R, pi, j, d);
+                if (r2 >= rc2) {
+                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    continue;
+                }
+                const real r = dsqrt(r2), ir = real(1) / r;
+                const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+                real f[NB], df[NB];
+                radial_basis_d(r, rc, f, df);
+                real sj[3];
+                load_spin(S.spin, j, sj);
+                const real dgR = dotk(CR, df);
+                const real gE = dotk(CE, f), dgE = dotk(CE, df);
+                const real gD = dotk(CD, f), dgD = dotk(CD, df);
+                const real gA = dotk(CA, f), dgA = dotk(CA, df);
+                const real gS = dotk(CS, f), dgS = dotk(CS, df);
+                const real ss = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+                const real c[3] = {si[1] * sj[2] - si[2] * sj[1], si[2] * sj[0] - si[0] * sj[2],
+                                   si[0] * sj[1] - si[1] * sj[0]};
+                const real w = rh[0] * c[0] + rh[1] * c[1] + rh[2] * c[2];
+                const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
+                const real b = sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2];
+                const real radial = dgR + dgE * ss + dgD * w + dgA * a * b + dgS * a * a;
+                const real sjxr[3] = {sj[1] * rh[2] - sj[2] * rh[1], sj[2] * rh[0] - sj[0] * rh[2],
+                                      sj[0] * rh[1] - sj[1] * rh[0]};
+                real G[3], hq[3];
+                const real kd = gD * ir, ka = gA * ir, ks = real(2) * gS * a * ir;
+#pragma unroll
+                for (int x = 0; x < 3; x++) {
+                    const real pa = si[x] - a * rh[x], pb = sj[x] - b * rh[x];
+                    G[x] = radial * rh[x] + kd * (c[x] - w * rh[x]) + ka * (b * pa + a * pb) + ks * pa;
+                    h[x] += gE * sj[x] + gD * sjxr[x] + (gA * b + real(2) * gS * a) * rh[x];
+                    hq[x] = gE * si[x] + gA * a * rh[x];
+                    F[x] += G[x];
+                }
+                // dE_i/ds_j of the DMI term: g (rhat x s_i)
+                hq[0] += gD * (rh[1] * si[2] - rh[2] * si[1]);
+                hq[1] += gD * (rh[2] * si[0] - rh[0] * si[2]);
+                hq[2] += gD * (rh[0] * si[1] - rh[1] * si[0]);
+                put_pair(W.pbR, s * ld + i, G, hq);
+            }
+        }
+        {
+            real CR[NB], CS[NB];
+            contract(M.cR + 1 * NR * NB, Fp + D_R, NR, CR);
+            contract(M.cSI + 1 * NR * NB, Fp + D_SI, NR, CS);
+            for (int s = nfe; s < cnt; s++) {
+                const int j = S.nbrR[s * ld + i];
+                real d[3];
+                const real r2 = geom(S, R, pi, j, d);
+                if (r2 >= rc2) {
+                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    continue;
+                }
+                const real r = dsqrt(r2), ir = real(1) / r;
+                const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+                real f[NB], df[NB];
+                radial_basis_d(r, rc, f, df);
+                const real dgR = dotk(CR, df);
+                const real gS = dotk(CS, f), dgS = dotk(CS, df);
+                const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
+                const real radial = dgR + dgS * a * a;
+                const real ks = real(2) * gS * a * ir;
+                real G[3];
+#pragma unroll
+                for (int x = 0; x < 3; x++) {
+                    G[x] = radial * rh[x] + ks * (si[x] - a * rh[x]);
+                    h[x] += real(2) * gS * a * rh[x];
+                    F[x] += G[x];
+                }
+                put_pair(W.pbR, s * ld + i, G, zero3);
+            }
+        }
+    } else {
+        for (int part = 0; part < 2; part++) {
+            real CR[NB];
+            contract(M.cR + (2 + part) * NR * NB, Fp + D_R, NR, CR);
+            const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            for (int s = b; s < e; s++) {
+                const int j = S.nbrR[s * ld + i];
+                real d[3];
+                const real r2 = geom(S, R, pi, j, d);
+                if (r2 >= rc2) {
+                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    continue;
+                }
+                const real r = dsqrt(r2), ir = real(1) / r;
+                real f[NB], df[NB];
+                radial_basis_d(r, rc, f, df);
+                const real g = dotk(CR, df) * ir;
+                const real G[3] = {g * d[0], g * d[1], g * d[2]};
+                F[0] += G[0];
+                F[1] += G[1];
+                F[2] += G[2];
+                put_pair(W.pbR, s * ld + i, G, zero3);
+            }
+        }
+    }
+    put_pair(W.ownR, (size_t)i, F, h);
+}
+
+// -------------------------------------------------------------------------
+// backward: angular set (eight lanes per atom)
+//   q^A_nl = sum_m A_nlm^2, q^sa_nl = sum_m A_nlm B_nlm with
+//   A_nlm = sum_j g^A_n Y_lm(rhat_ij), B_nlm = sum_j g^sa_n (s_i.s_j) Y_lm(rhat_ij)
+//   dE/dd_ij = sum_lm [QA_lm d(g^A Y)/dd + (s_i.s_j) QS_lm d(g^sa Y)/dd],
+//   QA = 2 Fp^A A + Fp^sa B, QS = Fp^sa A;  dE_i/ds_j = (sum_lm QS Y) g^sa s_i
+// -------------------------------------------------------------------------
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_bwd_angular(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
+    const int lane = threadIdx.x & 7;
+    bool fe;
+    const int i = atom_of_block(S, 32, nbFe, threadIdx.x >> 3, fe);
+    if (i < 0) return;
+    const bool live = lane < NA;
+    const int n = live ? lane : NA - 1;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_A, rc2 = rc * rc;
+    const int cnt = S.cntA[i], nfe = S.cntFeA[i];
+    const size_t ld = S.N;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    real si[3];
+    load_spin(S.spin, i, si);
+    real QA[NLM], QS[NLM];
+    {
+        const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+        real fa[4], fs[4];
+#pragma unroll
+        for (int l = 0; l < 4; l++) {
+            fa[l] = live ? Fp[D_A + 4 * n + l] : real(0);
+            fs[l] = live ? Fp[D_SA + 4 * n + l] : real(0);
+        }
+#pragma unroll
+        for (int m = 0; m < NLM; m++) {
+            const int l = l_of_lm(m) - 1;
+            const real a = ab[m], b = ab[NLM + m];
+            QA[m] = real(2) * fa[l] * a + fs[l] * b;
+            QS[m] = fs[l] * a;
+        }
+    }
+    const real zero3[3] = {0, 0, 0};
+    real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    const int tc = fe ? 0 : 2;
+    for (int part = 0; part < 2; part++) {
+        const int tau = tc + part;
+        real cA[NB], cS[NB];
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            cA[k] = M.cA[(tau * NA + n) * NB + k];
+            cS[k] = M.cSA[(tau * NA + n) * NB + k];
+        }
+        const bool spins = fe && part == 0;
+        const int b = part ? nfe : 0, e = part ? cnt : nfe;
+        for (int s = b; s < e; s++) {
+            const int j = S.nbrA[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) {
+                if (lane == 0) put_pair(W.pbA, s * ld + i, zero3, zero3);
+                continue;
+            }
+            const real r = dsqrt(r2), ir = real(1) / r;
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB], df[NB];
+            radial_basis_d(r, rc, f, df);
+            const real gA = dotk(cA, f), dgA = dotk(cA, df);
+            real sj[3] = {0, 0, 0}, sig = 0, gS = 0, dgS = 0;
+            if (spins) {
+                load_spin(S.spin, j, sj);
+                sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+                gS = dotk(cS, f);
+                dgS = dotk(cS, df);
+            }
+            real Y[NLM], G[NLM][3];
+            harmonics(rh[0], rh[1], rh[2], Y);
+            harmonics_grad(rh[0], rh[1], rh[2], G);
+            real sv = 0, sl = 0, w = 0, su[3] = {0, 0, 0};
+            const real sgS = sig * gS, sdgS = sig * dgS;
+#pragma unroll
+            for (int m = 0; m < NLM; m++) {
+                const real u = QA[m] * gA + QS[m] * sgS;
+                const real v = QA[m] * dgA + QS[m] * sdgS;
+                sv += v * Y[m];
+                sl += real(l_of_lm(m)) * u * Y[m];
+                w += QS[m] * Y[m];
+                su[0] += u * G[m][0];
+                su[1] += u * G[m][1];
+                su[2] += u * G[m][2];
+            }
+            real g3[3];
+#pragma unroll
+            for (int x = 0; x < 3; x++) g3[x] = xor_sum8(sv * rh[x] + (su[x] - sl * rh[x]) * ir);
+            const real hs = xor_sum8(w * gS);
+            F[0] += g3[0];
+            F[1] += g3[1];
+            F[2] += g3[2];
+            h[0] += hs * sj[0];
+            h[1] += hs * sj[1];
+            h[2] += hs * sj[2];
+            if (lane == 0) {
+                const real hq[3] = {hs * si[0], hs * si[1], hs * si[2]};
+                put_pair(W.pbA, s * ld + i, g3, hq);
+            }
+        }
+    }
+    if (lane == 0) put_pair(W.ownA, (size_t)i, F, h);
+}
+
+// -------------------------------------------------------------------------
+// gather: forces and fields
+// -------------------------------------------------------------------------
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= S.N) return;
+    const size_t ld = S.N;
+    real F[3], h[3];
+    {
+        const real *a = W.ownR + (size_t)k * 6, *b = W.ownA + (size_t)k * 6;
+        F[0] = a[0] + b[0];
+        F[1] = a[1] + b[1];
+        F[2] = a[2] + b[2];
+        h[0] = a[3] + b[3];
+        h[1] = a[4] + b[4];
+        h[2] = a[5] + b[5];
+    }
+    const int nr = S.cntR[k], na = S.cntA[k];
+    for (int s = 0; s < nr; s++) {
+        const int j = S.nbrR[s * ld + k];
+        const int t = S.revR[s * ld + k];
+        const real *p = W.pbR + ((size_t)t * ld + j) * 6;
+        F[0] -= p[0];
+        F[1] -= p[1];
+        F[2] -= p[2];
+        h[0] += p[3];
+        h[1] += p[4];
+        h[2] += p[5];
+    }
+    for (int s = 0; s < na; s++) {
+        const int j = S.nbrA[s * ld + k];
+        const int t = S.revA[s * ld + k];
+        const real *p = W.pbA + ((size_t)t * ld + j) * 6;
+        F[0] -= p[0];
+        F[1] -= p[1];
+        F[2] -= p[2];
+        h[0] += p[3];
+        h[1] += p[4];
+        h[2] += p[5];
+    }
+    d4 f4 = {(double)F[0], (double)F[1], (double)F[2], 0.0};
+    S.force[k] = f4;
+    d4 h4 = {0, 0, 0, 0};
+    if (k < S.N_fe) {
+        const RepDev &R = S.rep[S.rid[k]];
+        const double fr = ramp_frac(R), zs = R.mu_s * MUB;
+        h4.x = -(double)h[0] + zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr);
+        h4.y = -(double)h[1] + zs * (R.B0[1] + (R.B1[1] - R.B0[1]) * fr);
+        h4.z = -(double)h[2] + zs * (R.B0[2] + (R.B1[2] - R.B0[2]) * fr);
+    }
+    S.field[k] = h4;
+}
+
+// -------------------------------------------------------------------------
+// spin couplings of the frozen-Fp magnetic energy
+//   E_lin = sum_i sum_j [a_ij s_i.s_j + d_ij rhat_ij.(s_i x s_j) + b_ij (s_i.rhat)(s_j.rhat)]
+//           + sum_i s_i^T A_i s_i + o_i |s_i|^2  (+ Zeeman)
+// -------------------------------------------------------------------------
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M, Work<real> W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_R, rc2 = rc * rc;
+    const int cnt = S.cntR[i], nfe_all = S.cntFeR[i], nfe = min(nfe_all, MAXFE);
+    const size_t ld = S.N, lf = S.N_fe;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    real Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
+    {
+        real CE[NB], CD[NB], CA[NB], CS[NB];
+        contract(M.cEX, Fp + D_EX, NR, CE);
+        contract(M.cDM, Fp + D_DM, NR, CD);
+        contract(M.cAN, Fp + D_AN, NR, CA);
+        contract(M.cSI, Fp + D_SI, NR, CS);
+        for (int s = 0; s < nfe; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            real *c = W.craw + ((size_t)s * lf + i) * 3;
+            if (r2 >= rc2) {
+                c[0] = c[1] = c[2] = 0;
+                continue;
+            }
+            const real r = dsqrt(r2), ir = real(1) / r;
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB];
+            radial_basis(r, rc, f);
+            c[0] = dotk(CE, f);
+            c[1] = dotk(CD, f);
+            c[2] = dotk(CA, f);
+            const real g = dotk(CS, f);
+            Axx += g * rh[0] * rh[0];
+            Ayy += g * rh[1] * rh[1];
+            Azz += g * rh[2] * rh[2];
+            Axy += g * rh[0] * rh[1];
+            Axz += g * rh[0] * rh[2];
+            Ayz += g * rh[1] * rh[2];
+        }
+    }
+    {
+        real CS[NB];
+        contract(M.cSI + 1 * NR * NB, Fp + D_SI, NR, CS);
+        for (int s = nfe_all; s < cnt; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            const real r = dsqrt(r2), ir = real(1) / r;
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB];
+            radial_basis(r, rc, f);
+            const real g = dotk(CS, f);
+            Axx += g * rh[0] * rh[0];
+            Ayy += g * rh[1] * rh[1];
+            Azz += g * rh[2] * rh[2];
+            Axy += g * rh[0] * rh[1];
+            Axz += g * rh[0] * rh[2];
+            Ayz += g * rh[1] * rh[2];
+        }
+    }
+    real *o = W.selfc + (size_t)i * 8;
+    o[0] = Axx;
+    o[1] = Ayy;
+    o[2] = Azz;
+    o[3] = Axy;
+    o[4] = Axz;
+    o[5] = Ayz;
+    o[6] = Fp[D_OS];
+    o[7] = 0;
+}
+
+// spin-angular part of a_ij: sum_n g^sa_n(r_ij) sum_lm Fp^sa_nl A_nlm Y_lm(rhat_ij)
+template <typename real>
+__global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> M, Work<real> W) {
+    const int lane = threadIdx.x & 7;
+    const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+    if (i >= S.N_fe) return;
+    const bool live = lane < NA;
+    const int n = live ? lane : NA - 1;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_A, rc2 = rc * rc;
+    const int nfe = S.cntFeA[i];
+    const size_t ld = S.N, lf = S.N_fe;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    real P[NLM];
+    {
+        const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+#pragma unroll
+        for (int m = 0; m < NLM; m++) P[m] = live ? Fp[D_SA + 4 * n + l_of_lm(m) - 1] * ab[m] : real(0);
+    }
+    real cS[NB];
+#pragma unroll
+    for (int k = 0; k < NB; k++) cS[k] = M.cSA[(0 * NA + n) * NB + k];
+    for (int s = 0; s < nfe; s++) {
+        const int j = S.nbrA[s * ld + i];
+        real d[3];
+        const real r2 = geom(S, R, pi, j, d);
+        if (r2 >= rc2) continue;
+        const real r = dsqrt(r2), ir = real(1) / r;
+        real f[NB];
+        radial_basis(r, rc, f);
+        real Y[NLM];
+        harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+        real w = 0;
+#pragma unroll
+        for (int m = 0; m < NLM; m++) w += P[m] * Y[m];
+        const real a = xor_sum8(w * dotk(cS, f));
+        const int sr = S.a2r[s * ld + i];
+        if (lane == 0 && sr < MAXFE) W.craw[((size_t)sr * lf + i) * 3] += a;
+    }
+}
+
+// J_ij = a_ij + a_ji, D_ij = d_ij + d_ji, K_ij = b_ij + b_ji, with rhat_ij
+template <typename real>
+__global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    const int nfe = min(S.cntFeR[i], MAXFE);
+    const size_t ld = S.N, lf = S.N_fe;
+    for (int s = 0; s < nfe; s++) {
+        const int j = S.nbrR[s * ld + i];
+        const int t = min(S.revR[s * ld + i], MAXFE - 1);
+        const real *a = W.craw + ((size_t)s * lf + i) * 3;
+        const real *b = W.craw + ((size_t)t * lf + j) * 3;
+        real d[3];
+        const real r = dsqrt(geom(S, R, pi, j, d));
+        const real ir = real(1) / r;
+        real *c = W.cpl + ((size_t)s * lf + i) * 6;
+        c[0] = a[0] + b[0];
+        c[1] = a[1] + b[1];
+        c[2] = a[2] + b[2];
+        c[3] = d[0] * ir;
+        c[4] = d[1] * ir;
+        c[5] = d[2] * ir;
+    }
+}
+
+inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+template <typename real>
+void launch_forward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin,
+                    hipStream_t st) {
+    if (S.N == 0) return;
+    const int ge = S.N - S.N_fe;
+    {
+        const int a = nblk(S.N_fe, 256), b = nblk(ge, 256);
+        hipLaunchKernelGGL(k_desc_radial<real>, dim3(a + b), dim3(256), 0, st, S, M, W, spin, a);
+    }
+    {
+        const int a = nblk(S.N_fe, 32), b = nblk(ge, 32);
+        hipLaunchKernelGGL(k_desc_angular<real>, dim3(a + b), dim3(256), 0, st, S, M, W, spin, a);
+    }
+    {
+        const int a = nblk(S.N_fe, 128), b = nblk(ge, 128);
+        hipLaunchKernelGGL(k_mlp<real>, dim3(a + b), dim3(128), 0, st, S, M, W, a);
+    }
+}
+
+template <typename real>
+void launch_backward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N == 0) return;
+    const int ge = S.N - S.N_fe;
+    {
+        const int a = nblk(S.N_fe, 256), b = nblk(ge, 256);
+        hipLaunchKernelGGL(k_bwd_radial<real>, dim3(a + b), dim3(256), 0, st, S, M, W, a);
+    }
+    {
+        const int a = nblk(S.N_fe, 32), b = nblk(ge, 32);
+        hipLaunchKernelGGL(k_bwd_angular<real>, dim3(a + b), dim3(256), 0, st, S, M, W, a);
+    }
+    hipLaunchKernelGGL(k_gather<real>, dim3(nblk(S.N, 256)), dim3(256), 0, st, S, W);
+}
+
+template <typename real>
+void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N_fe == 0) return;
+    hipLaunchKernelGGL(k_assemble_radial<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M, W);
+    hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, 32)), dim3(256), 0, st, S, M, W);
+    hipLaunchKernelGGL(k_assemble_sym<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, W);
+}
+
+template void launch_forward<double>(const Sys &, const ModelDev<double> &, const Work<double> &, const d4 *,
+                                     hipStream_t);
+template void launch_forward<float>(const Sys &, const ModelDev<float> &, const Work<float> &, const d4 *,
+                                    hipStream_t);
+template void launch_backward<double>(const Sys &, const ModelDev<double> &, const Work<double> &, hipStream_t);
+template void launch_backward<float>(const Sys &, const ModelDev<float> &, const Work<float> &, hipStream_t);
+template void launch_assemble<double>(const Sys &, const ModelDev<double> &, const Work<double> &, hipStream_t);
+template void launch_assemble<float>(const Sys &, const ModelDev<float> &, const Work<float> &, hipStream_t);
+
+}  // namespace nep

@@ -1,0 +1,272 @@
+// kernels_nlist.hip -- Verlet cell/neighbour lists on the device.
+//
+// Atoms are binned into cells at least r_list = rc + skin wide; every atom
+// scans its (up to) 27 surrounding cells, keeps candidates within r_list by
+// minimum image and stores a full list (both i->j and j->i) sorted by atom
+// index, so the order of every later neighbour sum is fixed and independent
+// of thread timing. Lists are rebuilt only when some atom moved more than
+// skin/2 since the last build (the rebuild flag is raised on the device and
+// every rebuild kernel exits at once when it is clear).
+#include "engine.h"
+
+namespace nep {
+
+namespace {
+
+constexpr int BLK = 64;
+
+__device__ inline int cell_coord(double x, const RepDev &R, int a) {
+    double u = x - R.cell_lo[a];
+    if (R.pbc[a]) u -= R.box[a] * floor(u / R.box[a]);
+    int c = (int)floor(u / R.cell_w[a]);
+    if (c < 0) c = 0;
+    if (c >= R.nc[a]) c = R.nc[a] - 1;
+    return c;
+}
+
+__global__ void k_skin(Sys S) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    double dx, dy, dz;
+    min_image(R, S.pos_ref[i], S.pos[i], dx, dy, dz);
+    const double h = 0.5 * R.skin;
+    if (dx * dx + dy * dy + dz * dz > h * h) atomicOr(&S.flags[F_REBUILD], 1);
+}
+
+__global__ void k_cells_zero(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < S.n_cells; c += gridDim.x * blockDim.x) {
+        S.cell_cnt[c] = 0;
+        S.cell_fill[c] = 0;
+    }
+}
+
+__global__ void k_cells_count(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 p = S.pos[i];
+    const int c = R.cell_base + (cell_coord(p.x, R, 0) * R.nc[1] + cell_coord(p.y, R, 1)) * R.nc[2] +
+                  cell_coord(p.z, R, 2);
+    S.cell_of[i] = c;
+    atomicAdd(&S.cell_cnt[c], 1);
+}
+
+// exclusive scan of the cell counts by one workgroup of 1024 threads
+__global__ void __launch_bounds__(1024) k_cells_scan(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    __shared__ int part[1024];
+    const int t = threadIdx.x, n = S.n_cells;
+    const int per = (n + 1023) / 1024;
+    const int b = t * per, e = min(n, b + per);
+    int s = 0;
+    for (int c = b; c < e; c++) s += S.cell_cnt[c];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int c = b; c < e; c++) {
+        S.cell_start[c] = run;
+        run += S.cell_cnt[c];
+    }
+}
+
+__global__ void k_cells_fill(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const int c = S.cell_of[i];
+    const int k = atomicAdd(&S.cell_fill[c], 1);
+    S.cell_atoms[S.cell_start[c] + k] = i;
+}
+
+// ascending atom order inside every cell (insertion sort, ~20 atoms a cell)
+__global__ void k_cells_sort(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= S.n_cells) return;
+    int *a = S.cell_atoms + S.cell_start[c];
+    const int n = S.cell_cnt[c];
+    for (int x = 1; x < n; x++) {
+        int v = a[x], y = x - 1;
+        while (y >= 0 && a[y] > v) {
+            a[y + 1] = a[y];
+            y--;
+        }
+        a[y + 1] = v;
+    }
+}
+
+__device__ inline void axis_offsets(const RepDev &R, int a, int c, int off[3], int &n) {
+    n = 0;
+    if (R.pbc[a]) {
+        const int m = R.nc[a];
+        if (m >= 3) {
+            off[n++] = (c + m - 1) % m;
+            off[n++] = c;
+            off[n++] = (c + 1) % m;
+        } else if (m == 2) {
+            off[n++] = c;
+            off[n++] = 1 - c;
+        } else {
+            off[n++] = c;
+        }
+    } else {
+        for (int d = -1; d <= 1; d++)
+            if (c + d >= 0 && c + d < R.nc[a]) off[n++] = c + d;
+    }
+}
+
+__device__ inline void sort_row(int *row, int n) {
+    // row is k-major in LDS: element k at row[k * BLK]
+    for (int x = 1; x < n; x++) {
+        int v = row[x * BLK], y = x - 1;
+        while (y >= 0 && row[y * BLK] > v) {
+            row[(y + 1) * BLK] = row[y * BLK];
+            y--;
+        }
+        row[(y + 1) * BLK] = v;
+    }
+}
+
+__global__ void __launch_bounds__(BLK) k_build(Sys S, double rl2R, double rl2A) {
+    if (S.flags[F_REBUILD] == 0) return;
+    __shared__ int rowR[MAXR * BLK];
+    __shared__ int rowA[MAXA * BLK];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * BLK + t;
+    if (i >= S.N) return;
+    const RepDev &R = S.rep[S.rid[i]];
+    const d4 pi = S.pos[i];
+    int cx = cell_coord(pi.x, R, 0), cy = cell_coord(pi.y, R, 1), cz = cell_coord(pi.z, R, 2);
+    int ox[3], oy[3], oz[3], nx, ny, nz;
+    axis_offsets(R, 0, cx, ox, nx);
+    axis_offsets(R, 1, cy, oy, ny);
+    axis_offsets(R, 2, cz, oz, nz);
+    int nr = 0, na = 0;
+    for (int a = 0; a < nx; a++)
+        for (int b = 0; b < ny; b++)
+            for (int c = 0; c < nz; c++) {
+                const int cell = R.cell_base + (ox[a] * R.nc[1] + oy[b]) * R.nc[2] + oz[c];
+                const int beg = S.cell_start[cell], cnt = S.cell_cnt[cell];
+                for (int q = 0; q < cnt; q++) {
+                    const int j = S.cell_atoms[beg + q];
+                    if (j == i) continue;
+                    double dx, dy, dz;
+                    min_image(R, pi, S.pos[j], dx, dy, dz);
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 < rl2R) {
+                        if (nr < MAXR) rowR[nr * BLK + t] = j;
+                        nr++;
+                    }
+                    if (r2 < rl2A) {
+                        if (na < MAXA) rowA[na * BLK + t] = j;
+                        na++;
+                    }
+                }
+            }
+    if (nr > MAXR || na > MAXA) {
+        atomicOr(&S.flags[F_OVERFLOW], 1);
+        nr = min(nr, MAXR);
+        na = min(na, MAXA);
+    }
+    sort_row(rowR + t, nr);
+    sort_row(rowA + t, na);
+    int fe = 0;
+    for (int s = 0; s < nr; s++) {
+        const int j = rowR[s * BLK + t];
+        S.nbrR[(size_t)s * S.N + i] = j;
+        fe += j < S.N_fe;
+    }
+    S.cntR[i] = nr;
+    S.cntFeR[i] = fe;
+    if (i < S.N_fe && fe > MAXFE) atomicOr(&S.flags[F_OVERFLOW], 1);
+    fe = 0;
+    for (int s = 0; s < na; s++) {
+        const int j = rowA[s * BLK + t];
+        S.nbrA[(size_t)s * S.N + i] = j;
+        fe += j < S.N_fe;
+    }
+    S.cntA[i] = na;
+    S.cntFeA[i] = fe;
+    S.pos_ref[i] = pi;
+}
+
+__device__ inline int find_sorted(const int *nbr, int N, int row, int n, int key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = nbr[(size_t)mid * N + row];
+        if (v < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && nbr[(size_t)lo * N + row] == key) ? lo : -1;
+}
+
+// reverse slots (where i sits in j's list), angular->radial slot map, and the
+// colouring check: no two same-colour spins inside r_list
+__global__ void k_rev(Sys S) {
+    if (S.flags[F_REBUILD] == 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const int nr = S.cntR[i], na = S.cntA[i];
+    int bad = 0;
+    for (int s = 0; s < nr; s++) {
+        const int j = S.nbrR[(size_t)s * S.N + i];
+        const int r = find_sorted(S.nbrR, S.N, j, S.cntR[j], i);
+        bad |= r < 0;
+        S.revR[(size_t)s * S.N + i] = r < 0 ? 0 : r;
+    }
+    for (int s = 0; s < na; s++) {
+        const int j = S.nbrA[(size_t)s * S.N + i];
+        const int r = find_sorted(S.nbrA, S.N, j, S.cntA[j], i);
+        const int m = find_sorted(S.nbrR, S.N, i, nr, j);
+        bad |= (r < 0) | (m < 0);
+        S.revA[(size_t)s * S.N + i] = r < 0 ? 0 : r;
+        S.a2r[(size_t)s * S.N + i] = m < 0 ? 0 : m;
+    }
+    if (bad) atomicOr(&S.flags[F_OVERFLOW], 2);
+    if (S.colour && i < S.N_fe && S.colour[i] >= 0) {
+        const int ci = S.colour[i];
+        const int nfe = S.cntFeR[i];
+        for (int s = 0; s < nfe; s++) {
+            const int j = S.nbrR[(size_t)s * S.N + i];
+            if (S.colour[j] == ci) atomicOr(&S.flags[F_COLOUR], 1);
+        }
+    }
+}
+
+__global__ void k_rebuild_done(Sys S) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) S.flags[F_REBUILD] = 0;
+}
+
+inline int nblk(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+void launch_skin_check(const Sys &S, hipStream_t st) {
+    if (S.N == 0) return;
+    hipLaunchKernelGGL(k_skin, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+}
+
+void launch_rebuild(const Sys &S, double r_listR, double r_listA, hipStream_t st) {
+    if (S.N == 0) return;
+    hipLaunchKernelGGL(k_cells_zero, dim3(std::min(nblk(S.n_cells, 256), 1024)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_cells_count, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_cells_scan, dim3(1), dim3(1024), 0, st, S);
+    hipLaunchKernelGGL(k_cells_fill, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_cells_sort, dim3(nblk(S.n_cells, 256)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_build, dim3(nblk(S.N, BLK)), dim3(BLK), 0, st, S, r_listR * r_listR,
+                       r_listA * r_listA);
+    hipLaunchKernelGGL(k_rev, dim3(nblk(S.N, 256)), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_rebuild_done, dim3(1), dim3(64), 0, st, S);
+}
+
+}  // namespace nep

@@ -1,0 +1,56 @@
+"""Shared test helpers: error norms and local-cluster oracle evaluations."""
+import numpy as np
+
+
+def rel_inf(a, b):
+    """||a - b||_inf / ||b||_inf"""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max() if a.size else 0.0)
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+def min_image_delta(a, b, box, pbc):
+    d = np.asarray(a) - np.asarray(b)
+    for x in range(3):
+        if pbc[x]:
+            d[..., x] -= box[x] * np.rint(d[..., x] / box[x])
+    return d
+
+
+def cluster_around(types, pos, spin, box, pbc, k, radius):
+    """Atoms within `radius` of atom k, unwrapped by minimum image into a free
+    cluster; returns (types, pos, spin, index of k in the cluster)."""
+    d = min_image_delta(pos, pos[k], box, pbc)
+    sel = np.nonzero((d * d).sum(axis=1) < radius * radius)[0]
+    cpos = pos[k] + d[sel] + 1000.0
+    return types[sel], cpos, spin[sel], int(np.nonzero(sel == k)[0][0])
+
+
+def oracle_local(oracle, types, pos, spin, box, pbc, params, atoms, *, B=(0, 0, 0), mu_s=1.0):
+    """Per-atom E_i, F_i, H_i of selected atoms of a large system, each from a
+    free cluster of radius 2 rc + 1 A around it (everything that reaches it)."""
+    Ei, F, H = [], [], []
+    for k in atoms:
+        ct, cp, cs, kk = cluster_around(types, pos, spin, box, pbc, k, 13.0)
+        o = oracle.evaluate(ct, cp, cs, np.array([1e5] * 3), np.zeros(3, np.int32), params, B=B, mu_s=mu_s,
+                            want=("E", "F", "H", "Ei"))
+        Ei.append(o["Ei"][kk])
+        F.append(o["F"][kk])
+        H.append(o["H"][kk])
+    return np.array(Ei), np.array(F), np.array(H)
+
+
+def gpu_available():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
