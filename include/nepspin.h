@@ -224,6 +224,21 @@ int sl_set_state(sl_sim *s, const double *pos, const double *vel, const double *
 
 int sl_destroy(sl_sim *s);
 
+/* Kernel timing for measurement. When enabled for a kernel group, every
+ * launch of that group inside sl_integrate_steps is bracketed by HIP events
+ * on the simulation's stream; totals accumulate until read. Groups:
+ *   0 descriptor (radial set)   1 descriptor (angular set)   2 read-out
+ *   3 backward (radial set)     4 backward (angular set)     5 gather
+ *   6 spin couplings            7 colour sweep               8 neighbour lists
+ *   9 lattice half-steps, baths and reductions
+ * mask: bit g enables group g (0 disables timing). */
+#define SL_NPROF 10
+int sl_profile_enable(sl_sim *s, unsigned mask);
+
+/* ms_total[SL_NPROF]: summed event time per group (ms); launches[SL_NPROF]:
+ * number of timed launch groups. Either may be NULL. Resets the totals. */
+int sl_profile_read(sl_sim *s, double *ms_total, int64_t *launches);
+
 /* ---------------------------------------------------------------------- */
 /* Replica serving                                                        */
 /* ---------------------------------------------------------------------- */

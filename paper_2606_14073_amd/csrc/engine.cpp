@@ -166,7 +166,7 @@ static size_t bytes_per_atom(sl_precision prec) {
     const size_t rs = prec == SL_FP64 ? 8 : 4;
     size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
     b += rs * (2 * DP + 1 + NA * NAB + 12 + 6 * MAXR + 6 * MAXA);
-    b += rs * (MAXFE * 9 + 8) / 2 + 64;
+    b += (rs * (MAXFE * 9 + 8) + 4 * (MAXFE + 3)) / 2 + 64;
     return b;
 }
 
@@ -195,11 +195,58 @@ struct Engine {
     Work<double> w64{};
     Work<float> w32{};
     Chunk *chunks = nullptr;
-    int *chunk_ptr = nullptr, *col_idx = nullptr;
+    int *chunk_ptr = nullptr, *col_idx = nullptr, *colpos = nullptr, *cpl_j = nullptr, *cpl_n = nullptr;
     double *partial = nullptr, *obs = nullptr;
     size_t cap_obs = 0, cap_col = 0;
     int n_chunks = 0;
     std::vector<int> col_ptr;
+
+    // kernel-group timing (sl_profile_enable)
+    unsigned prof_mask = 0;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_open;
+    size_t prof_used = 0;
+    double prof_ms[SL_NPROF] = {0};
+    int64_t prof_n[SL_NPROF] = {0};
+
+    hipEvent_t prof_event() {
+        if (prof_used == prof_pool.size()) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            prof_pool.push_back(e);
+        }
+        return prof_pool[prof_used++];
+    }
+    struct ProfScope {
+        Engine *e;
+        int g;
+        hipEvent_t a{}, b{};
+        ProfScope(Engine *e_, int g_) : e(e_), g(g_) {
+            if (e->prof_mask & (1u << g)) {
+                a = e->prof_event();
+                b = e->prof_event();
+                (void)hipEventRecord(a, e->st);
+            }
+        }
+        ~ProfScope() {
+            if (e->prof_mask & (1u << g)) {
+                (void)hipEventRecord(b, e->st);
+                e->prof_open.push_back({g, {a, b}});
+            }
+        }
+    };
+    // after a stream synchronisation: fold the recorded pairs into the totals
+    void prof_collect() {
+        for (auto &x : prof_open) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+                prof_ms[x.first] += ms;
+                prof_n[x.first] += 1;
+            }
+        }
+        prof_open.clear();
+        prof_used = 0;
+    }
 
     ~Engine() { release(); }
 
@@ -210,10 +257,13 @@ struct Engine {
         dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
         dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
         dfree(cell_of); dfree(cell_cnt); dfree(cell_start); dfree(cell_fill); dfree(cell_atoms);
-        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(partial); dfree(obs);
+        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(colpos); dfree(cpl_j); dfree(cpl_n);
+        dfree(partial); dfree(obs);
         if (work) (void)hipFree(work);
         work = nullptr;
         cap = cap_fe = cap_cells = cap_rep = cap_chunks = cap_obs = cap_col = 0;
+        for (auto e : prof_pool) (void)hipEventDestroy(e);
+        prof_pool.clear();
         if (own_stream && st) (void)hipStreamDestroy(st);
         st = nullptr;
         own_stream = false;
@@ -231,6 +281,8 @@ struct Engine {
         S.pos = pos; S.vel = vel; S.spin = spin; S.force = force; S.field = field; S.pos_ref = pos_ref;
         S.spin_n = spin_n; S.spin_hat = spin_hat; S.eta = eta;
         S.colour = colour;
+        S.col_idx = col_idx;
+        S.colpos = colpos;
         S.nbrR = nbrR; S.cntR = cntR; S.cntFeR = cntFeR; S.revR = revR;
         S.nbrA = nbrA; S.cntA = cntA; S.cntFeA = cntFeA; S.revA = revA; S.a2r = a2r;
         S.cell_of = cell_of; S.cell_cnt = cell_cnt; S.cell_start = cell_start; S.cell_fill = cell_fill;
@@ -267,6 +319,8 @@ struct Engine {
         w.craw = take((size_t)MAXFE * cf * 3);
         w.cpl = take((size_t)MAXFE * cf * 6);
         w.selfc = take(cf * 8);
+        w.cpl_j = cpl_j;
+        w.cpl_n = cpl_n;
         w.bf16 = prec == SL_FP32_BF16H;
     }
 
@@ -287,7 +341,7 @@ struct Engine {
             dfree(spin_n); dfree(spin_hat); dfree(eta);
             dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
             dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
-            dfree(cell_of); dfree(cell_atoms);
+            dfree(cell_of); dfree(cell_atoms); dfree(cpl_j); dfree(cpl_n);
             if (work) (void)hipFree(work);
             work = nullptr;
             cap = cap_fe = 0;
@@ -299,7 +353,8 @@ struct Engine {
                 (rc = dalloc(&revR, (size_t)MAXR * c)) || (rc = dalloc(&nbrA, (size_t)MAXA * c)) ||
                 (rc = dalloc(&cntA, c)) || (rc = dalloc(&cntFeA, c)) || (rc = dalloc(&revA, (size_t)MAXA * c)) ||
                 (rc = dalloc(&a2r, (size_t)MAXA * c)) || (rc = dalloc(&cell_of, c)) ||
-                (rc = dalloc(&cell_atoms, c)))
+                (rc = dalloc(&cell_atoms, c)) || (rc = dalloc(&cpl_j, (size_t)MAXFE * cf)) ||
+                (rc = dalloc(&cpl_n, cf)))
                 return rc;
             const size_t rs = prec == SL_FP64 ? 8 : 4;
             work_bytes = work_count(c, cf) * rs;
@@ -340,7 +395,8 @@ struct Engine {
         }
         if (!col_idx || cap_col < cap_fe) {
             dfree(col_idx);
-            if ((rc = dalloc(&col_idx, cap_fe))) return rc;
+            dfree(colpos);
+            if ((rc = dalloc(&col_idx, cap_fe)) || (rc = dalloc(&colpos, cap_fe))) return rc;
             cap_col = cap_fe;
         }
         return SL_OK;
@@ -477,6 +533,12 @@ struct Engine {
                     if (!r->colour_fe.empty() && r->colour_fe[a] == c) h_colidx.push_back(r->fe_off + (int)a);
         }
         col_ptr[cmax] = (int)h_colidx.size();
+        // spin carriers without a colour (evaluation only) keep their own index
+        std::vector<int> h_colpos(nfe);
+        for (size_t q = 0; q < nfe; q++) h_colpos[q] = (int)q;
+        if (h_colidx.size() == nfe)
+            for (size_t q = 0; q < nfe; q++) h_colpos[h_colidx[q]] = (int)q;
+        if (nfe) HIPCHK(hipMemcpyAsync(colpos, h_colpos.data(), nfe * 4, hipMemcpyHostToDevice, st));
         if (n) {
             HIPCHK(hipMemcpyAsync(rid, h_rid.data(), n * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(orig, h_orig.data(), n * 4, hipMemcpyHostToDevice, st));
@@ -524,9 +586,10 @@ struct Engine {
                 }
             }
         }
-        // force a neighbour rebuild, then F and H of the current state
-        int one = 1;
-        HIPCHK(hipMemcpyAsync(flags + F_REBUILD, &one, 4, hipMemcpyHostToDevice, st));
+        // clear the error flags, force a neighbour rebuild, then F and H
+        int hflags[NFLAGS] = {0};
+        hflags[F_REBUILD] = 1;
+        HIPCHK(hipMemcpyAsync(flags, hflags, sizeof(hflags), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         if (N) {
             const Sys S = sys();
@@ -545,18 +608,34 @@ struct Engine {
     }
 
     // forward + backward at the current positions and the given spins
-    void evaluate(const d4 *spins) {
+    template <typename real>
+    void forward(const ModelDev<real> &m, const Work<real> &w, const d4 *spins) {
         const Sys S = sys();
+        { ProfScope p(this, 0); launch_desc_radial(S, m, w, spins, st); }
+        { ProfScope p(this, 1); launch_desc_angular(S, m, w, spins, st); }
+        { ProfScope p(this, 2); launch_mlp(S, m, w, st); }
+    }
+
+    template <typename real>
+    void backward(const ModelDev<real> &m, const Work<real> &w) {
+        const Sys S = sys();
+        { ProfScope p(this, 3); launch_bwd_radial(S, m, w, st); }
+        { ProfScope p(this, 4); launch_bwd_angular(S, m, w, st); }
+        { ProfScope p(this, 5); launch_gather(S, w, st); }
+    }
+
+    void evaluate(const d4 *spins) {
         if (prec == SL_FP64) {
-            launch_forward(S, M->m64, w64, spins, st);
-            launch_backward(S, M->m64, w64, st);
+            forward(M->m64, w64, spins);
+            backward(M->m64, w64);
         } else {
-            launch_forward(S, M->m32, w32, spins, st);
-            launch_backward(S, M->m32, w32, st);
+            forward(M->m32, w32, spins);
+            backward(M->m32, w32);
         }
     }
 
     void rebuild_if_needed() {
+        ProfScope p(this, 8);
         const Sys S = sys();
         launch_skin_check(S, st);
         launch_rebuild(S, RC_R + max_skin(), RC_A + max_skin(), st);
@@ -565,28 +644,31 @@ struct Engine {
     template <typename real>
     void spin_step(const ModelDev<real> &m, const Work<real> &w) {
         const Sys S = sys();
-        launch_spin_prep(S, st);
+        { ProfScope q(this, 9); launch_spin_prep(S, st); }
         for (int p = 0; p <= K_corr; p++) {
-            launch_forward(S, m, w, spin_hat, st);
-            launch_assemble(S, m, w, st);
-            if (p > 0) launch_spin_restore(S, st);
-            launch_sweep(S, w, col_ptr.data(), col_idx, (int)col_ptr.size() - 1, st);
-            if (p < K_corr) launch_spin_mid(S, st);
+            forward(m, w, spin_hat);
+            { ProfScope q(this, 6); launch_assemble(S, m, w, st); }
+            {
+                ProfScope q(this, 7);
+                if (p > 0) launch_spin_restore(S, st);
+                launch_sweep(S, w, col_ptr.data(), (int)col_ptr.size() - 1, st);
+                if (p < K_corr) launch_spin_mid(S, st);
+            }
         }
     }
 
     // one B A O S A B step of every active replica; observables to obs_out[n_rep][NOBS]
     void step(double *obs_out) {
         const Sys S = sys();
-        launch_kick(S, st);
-        launch_drift(S, st);
+        { ProfScope p(this, 9); launch_kick(S, st); launch_drift(S, st); }
         rebuild_if_needed();
-        launch_langevin(S, st);
+        { ProfScope p(this, 9); launch_langevin(S, st); }
         if (prec == SL_FP64) spin_step(M->m64, w64);
         else spin_step(M->m32, w32);
-        launch_drift(S, st);
+        { ProfScope p(this, 9); launch_drift(S, st); }
         rebuild_if_needed();
         evaluate(spin);
+        ProfScope p(this, 9);
         launch_kick(S, st);
         if (prec == SL_FP64) launch_observe(S, w64, chunks, n_chunks, chunk_ptr, partial, obs_out, st);
         else launch_observe(S, w32, chunks, n_chunks, chunk_ptr, partial, obs_out, st);
@@ -1059,6 +1141,7 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(h.data(), e.obs, k * NOBS * 8, hipMemcpyDeviceToHost, e.st));
         HIPCHK(hipStreamSynchronize(e.st));
+        e.prof_collect();
         if ((rc = e.check_flags())) return rc;
         for (int64_t q = 0; q < k; q++) {
             double o[NOBS + 1];
@@ -1105,6 +1188,23 @@ extern "C" int sl_set_state(sl_sim *s, const double *pos, const double *vel, con
     int rc = s->eng.set_layout({&r});
     if (rc) return rc;
     return s->eng.check_flags();
+}
+
+extern "C" int sl_profile_enable(sl_sim *s, unsigned mask) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    s->eng.prof_mask = mask & ((1u << SL_NPROF) - 1);
+    return SL_OK;
+}
+
+extern "C" int sl_profile_read(sl_sim *s, double *ms_total, int64_t *launches) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    for (int g = 0; g < SL_NPROF; g++) {
+        if (ms_total) ms_total[g] = s->eng.prof_ms[g];
+        if (launches) launches[g] = s->eng.prof_n[g];
+        s->eng.prof_ms[g] = 0;
+        s->eng.prof_n[g] = 0;
+    }
+    return SL_OK;
 }
 
 extern "C" int sl_destroy(sl_sim *s) {

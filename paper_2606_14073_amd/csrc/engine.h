@@ -20,6 +20,8 @@ struct Sys {
     RepDev *rep;           // [n_rep]
     d4 *pos, *vel, *spin, *force, *field, *pos_ref, *spin_n, *spin_hat, *eta;
     const int *colour;     // [N] colour on spin carriers, -1 elsewhere
+    const int *col_idx;    // [N_fe] spin carriers grouped by colour
+    const int *colpos;     // [N_fe] position of each spin carrier in col_idx
     int *nbrR, *cntR, *cntFeR, *revR;
     int *nbrA, *cntA, *cntFeA, *revA, *a2r;
     int *cell_of, *cell_cnt, *cell_start, *cell_fill, *cell_atoms;
@@ -39,9 +41,11 @@ struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
     real *pbR, *pbA;            // pair records [MAXR|MAXA][N][6]: dE_i/dd_ij, dE_i/ds_j
     real *ownR, *ownA;          // [N][6]: sum_j dE_i/dd_ij, dE_i/ds_i
-    real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij
-    real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat
-    real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i
+    real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij (atom order)
+    real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat (colour-list order)
+    real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i (colour-list order)
+    int *cpl_j;                 // [MAXFE][N_fe]: neighbour of each coupling (colour-list order)
+    int *cpl_n;                 // [N_fe]: couplings inside rc_R per spin (colour-list order)
     int bf16;                   // read-out input->hidden contraction in BF16
 };
 
@@ -50,15 +54,21 @@ void launch_skin_check(const Sys &S, hipStream_t st);
 void launch_rebuild(const Sys &S, double r_listR, double r_listA, hipStream_t st);
 
 template <typename real>
-void launch_forward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin,
-                    hipStream_t st);
+void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st);
 template <typename real>
-void launch_backward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st);
+template <typename real>
+void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st);
 template <typename real>
 void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
 template <typename real>
-void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, const int *col_idx,
-                  int n_colours, hipStream_t st);
+void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, int n_colours, hipStream_t st);
 
 void launch_kick(const Sys &S, hipStream_t st);
 void launch_drift(const Sys &S, hipStream_t st);

@@ -99,22 +99,55 @@ __global__ void k_spin_mid(Sys S) {
     S.spin_hat[i] = h;
 }
 
+// sin(t) and 1 - cos(t) from their Taylor series (coefficients +-1/n!), for
+// |t| <= 1 where the truncation error is below 1e-19; no cancellation in 1 - cos.
+__device__ inline void sin_omc_taylor(double t, double &sn, double &omc) {
+    const double t2 = t * t;
+    double ps = 1.0 / 121645100408832000.0;              // 1/19!
+    ps = ps * -t2 + 1.0 / 355687428096000.0;             // 1/17!
+    ps = ps * -t2 + 1.0 / 1307674368000.0;               // 1/15!
+    ps = ps * -t2 + 1.0 / 6227020800.0;                  // 1/13!
+    ps = ps * -t2 + 1.0 / 39916800.0;                    // 1/11!
+    ps = ps * -t2 + 1.0 / 362880.0;                      // 1/9!
+    ps = ps * -t2 + 1.0 / 5040.0;                        // 1/7!
+    ps = ps * -t2 + 1.0 / 120.0;                         // 1/5!
+    ps = ps * -t2 + 1.0 / 6.0;                           // 1/3!
+    ps = ps * -t2 + 1.0;
+    sn = t * ps;
+    double pc = 1.0 / 2432902008176640000.0;             // 1/20!
+    pc = pc * -t2 + 1.0 / 6402373705728000.0;            // 1/18!
+    pc = pc * -t2 + 1.0 / 20922789888000.0;              // 1/16!
+    pc = pc * -t2 + 1.0 / 87178291200.0;                 // 1/14!
+    pc = pc * -t2 + 1.0 / 479001600.0;                   // 1/12!
+    pc = pc * -t2 + 1.0 / 3628800.0;                     // 1/10!
+    pc = pc * -t2 + 1.0 / 40320.0;                       // 1/8!
+    pc = pc * -t2 + 1.0 / 720.0;                         // 1/6!
+    pc = pc * -t2 + 1.0 / 24.0;                          // 1/4!
+    pc = pc * -t2 + 0.5;                                 // 1/2!
+    omc = t2 * pc;
+}
+
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
+// Eight lanes share a spin: they split the neighbour gather (couplings stored
+// in colour-list order, so a wavefront reads contiguous records), reduce, and
+// then run the midpoint iteration in lockstep; lane 0 stores the result.
 template <typename real>
-__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, const int *idx, int count) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count) {
+    const int lane = threadIdx.x & 7;
+    const int t = blockIdx.x * 32 + (threadIdx.x >> 3);
     if (t >= count) return;
-    const int i = idx[t];
+    const int p = base + t;
+    const int i = S.col_idx[p];
     const RepDev &R = S.rep[S.rid[i]];
     if (!R.active) return;
-    const size_t ld = S.N, lf = S.N_fe;
-    const int nfe = min(S.cntFeR[i], MAXFE);
+    const size_t lf = S.N_fe;
+    const int nc = W.cpl_n[p];
     double hx = 0, hy = 0, hz = 0;
-    for (int s = 0; s < nfe; s++) {
-        const int j = S.nbrR[s * ld + i];
-        const real *c = W.cpl + ((size_t)s * lf + i) * 6;
+    for (int s = lane; s < nc; s += 8) {
+        const int j = W.cpl_j[(size_t)s * lf + p];
+        const real *c = W.cpl + ((size_t)s * lf + p) * 6;
         const double J = c[0], D = c[1], K = c[2], rx = c[3], ry = c[4], rz = c[5];
         const d4 sj = S.spin[j];
         const double sr = sj.x * rx + sj.y * ry + sj.z * rz;
@@ -122,7 +155,13 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, const int *i
         hy -= J * sj.y + D * (sj.z * rx - sj.x * rz) + K * sr * ry;
         hz -= J * sj.z + D * (sj.x * ry - sj.y * rx) + K * sr * rz;
     }
-    const real *o = W.selfc + (size_t)i * 8;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        hx += __shfl_xor(hx, m);
+        hy += __shfl_xor(hy, m);
+        hz += __shfl_xor(hz, m);
+    }
+    const real *o = W.selfc + (size_t)p * 8;
     const double Axx = o[0], Ayy = o[1], Azz = o[2], Axy = o[3], Axz = o[4], Ayz = o[5], os = o[6];
     const double fr = ramp_frac(R), zs = R.mu_s * MUB;
     const d4 e = S.eta[i];
@@ -156,13 +195,17 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, const int *i
             double sn, cs, omc;
             if (fabs(th) < 1e-8) {
                 sn = th - th * th * th / 6.0;
-                cs = 1.0 - th * th / 2.0;
                 omc = th * th / 2.0;
+                cs = 1.0 - omc;
+            } else if (fabs(th) <= 1.0) {
+                sin_omc_taylor(th, sn, omc);
+                cs = 1.0 - omc;
             } else {
                 sincos(th, &sn, &cs);
                 omc = 1.0 - cs;
             }
-            const double ux = wx / wn, uy = wy / wn, uz = wz / wn;
+            const double iw = 1.0 / wn;
+            const double ux = wx * iw, uy = wy * iw, uz = wz * iw;
             const double us = ux * sx + uy * sy + uz * sz;
             nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
             ny = sy * cs + (uz * sx - ux * sz) * sn + uy * us * omc;
@@ -174,8 +217,10 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, const int *i
         yz = nz;
         if (diff <= R.mid_tol) break;
     }
-    d4 out = {yx, yy, yz, 0.0};
-    S.spin[i] = out;
+    if (lane == 0) {
+        d4 out = {yx, yy, yz, 0.0};
+        S.spin[i] = out;
+    }
 }
 
 __global__ void k_step_end(Sys S) {
@@ -230,17 +275,27 @@ __global__ void __launch_bounds__(256) k_obs_partial(Sys S, Work<real> W, const 
     if (t < NOBS) partial[(size_t)blockIdx.x * NOBS + t] = red[t][0];
 }
 
-__global__ void k_obs_final(Sys S, const int *chunk_ptr, const double *partial, double *out) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= S.n_rep) return;
+// one workgroup per replica: thread t sums chunks t, t+256, ... in order,
+// then a fixed tree; the result depends only on the replica's own chunks
+__global__ void __launch_bounds__(256) k_obs_final(Sys S, const int *chunk_ptr, const double *partial, double *out) {
+    __shared__ double red[NOBS][256];
+    const int r = blockIdx.x, t = threadIdx.x;
     double v[NOBS];
 #pragma unroll
     for (int k = 0; k < NOBS; k++) v[k] = 0;
-    for (int c = chunk_ptr[r]; c < chunk_ptr[r + 1]; c++)
+    for (int c = chunk_ptr[r] + t; c < chunk_ptr[r + 1]; c += 256)
 #pragma unroll
         for (int k = 0; k < NOBS; k++) v[k] += partial[(size_t)c * NOBS + k];
 #pragma unroll
-    for (int k = 0; k < NOBS; k++) out[(size_t)r * NOBS + k] = v[k];
+    for (int k = 0; k < NOBS; k++) red[k][t] = v[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int k = 0; k < NOBS; k++) red[k][t] += red[k][t + off];
+        __syncthreads();
+    }
+    if (t < NOBS) out[(size_t)r * NOBS + t] = red[t][0];
 }
 
 }  // namespace
@@ -268,13 +323,12 @@ void launch_step_end(const Sys &S, hipStream_t st) {
 }
 
 template <typename real>
-void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, const int *col_idx,
-                  int n_colours, hipStream_t st) {
+void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, int n_colours, hipStream_t st) {
     for (int pass = 0; pass < 2; pass++)
         for (int cc = 0; cc < n_colours; cc++) {
             const int c = pass == 0 ? cc : n_colours - 1 - cc;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
-            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256)), dim3(256), 0, st, S, W, col_idx + b, n);
+            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 32)), dim3(256), 0, st, S, W, b, n);
         }
 }
 
@@ -283,11 +337,11 @@ void launch_observe(const Sys &S, const Work<real> &W, const Chunk *chunks, int 
                     const int *chunk_ptr, double *partial, double *out, hipStream_t st) {
     if (n_chunks == 0) return;
     hipLaunchKernelGGL(k_obs_partial<real>, dim3(n_chunks), dim3(256), 0, st, S, W, chunks, partial);
-    hipLaunchKernelGGL(k_obs_final, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S, chunk_ptr, partial, out);
+    hipLaunchKernelGGL(k_obs_final, dim3(S.n_rep), dim3(256), 0, st, S, chunk_ptr, partial, out);
 }
 
-template void launch_sweep<double>(const Sys &, const Work<double> &, const int *, const int *, int, hipStream_t);
-template void launch_sweep<float>(const Sys &, const Work<float> &, const int *, const int *, int, hipStream_t);
+template void launch_sweep<double>(const Sys &, const Work<double> &, const int *, int, hipStream_t);
+template void launch_sweep<float>(const Sys &, const Work<float> &, const int *, int, hipStream_t);
 template void launch_observe<double>(const Sys &, const Work<double> &, const Chunk *, int, const int *, double *,
                                      double *, hipStream_t);
 template void launch_observe<float>(const Sys &, const Work<float> &, const Chunk *, int, const int *, double *,

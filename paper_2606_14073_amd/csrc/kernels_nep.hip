@@ -300,7 +300,14 @@ __global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, W
 }
 
 // -------------------------------------------------------------------------
-// per-species read-out (lane per atom; weights wave-uniform)
+// per-species read-out on the matrix cores
+//   Z = Q W0^T + b0 (atoms x 64), E_i = b1 + w1 . tanh(Z_i),
+//   Fp = [(1 - tanh^2(Z)) * w1] W0 (atoms x 104)
+// One wavefront takes a tile of 16 atoms of one species; W0^T of that species
+// is staged in LDS once per workgroup. Operand layout of v_mfma_*_16x16x4:
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k. Accumulator element r of
+// lane l holds column l % 16 and row 4 (l / 16) + r for the FP32 and BF16
+// instructions, row (l / 16) + 4 r for the FP64 one (checked on gfx950).
 // -------------------------------------------------------------------------
 
 __device__ inline float bf16_round(float x) {
@@ -310,46 +317,133 @@ __device__ inline float bf16_round(float x) {
 }
 
 template <typename real>
-__global__ void __launch_bounds__(128) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
-    bool fe;
-    const int i = atom_of_block(S, 128, nbFe, threadIdx.x, fe);
-    if (i < 0) return;
+struct MF;
+template <>
+struct MF<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int kq, int r) { return kq + 4 * r; }
+};
+template <>
+struct MF<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int kq, int r) { return 4 * kq + r; }
+};
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int MLP_WAVES = 8;           // 8 wavefronts x 16 atoms per workgroup
+constexpr int MLP_ATOMS = 16 * MLP_WAVES;
+constexpr int DPT = 112;               // descriptor rows padded to 7 tiles of 16
+constexpr int WLD = NH + 2;            // LDS row of W0^T
+constexpr int GLD = NH + 1;            // LDS row of the per-wave hidden tile
+
+template <typename real>
+__global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
+    typedef typename MF<real>::acc_t acc_t;
+    __shared__ real sW[DPT * WLD];
+    __shared__ real sG[MLP_WAVES * 16 * GLD];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool fe = (int)blockIdx.x < nbFe;
     const int t = fe ? 0 : 1;
-    const real *W0 = M.W0 + (size_t)t * DP * NH;   // [d][h]
-    const real *q = W.q + (size_t)i * DP;
-    real z[NH];
+    const int end = fe ? S.N_fe : S.N;
+    const int a0 = (fe ? blockIdx.x * MLP_ATOMS : S.N_fe + (blockIdx.x - nbFe) * MLP_ATOMS) + wave * 16;
+    const real *W0 = M.W0 + (size_t)t * DP * NH;
+    for (int x = threadIdx.x; x < DPT * NH; x += blockDim.x) {
+        const int d = x / NH, h = x - d * NH;
+        sW[d * WLD + h] = d < DP ? W0[d * NH + h] : real(0);
+    }
+    __syncthreads();
+    const int i16 = lane & 15, kq = lane >> 4;
+    const int arow = a0 + i16;
+    const bool rv = arow < end;
+    const real *qrow = W.q + (size_t)(rv ? arow : 0) * DP;
+    acc_t acc[4];
 #pragma unroll
-    for (int h = 0; h < NH; h++) z[h] = M.b0[t * NH + h];
-    if (W.bf16) {
-        const float *Wb = M.W0bf + (size_t)t * DP * NH;
-        for (int d = 0; d < ND; d++) {
-            const real qd = (real)bf16_round((float)q[d]);
+    for (int jt = 0; jt < 4; jt++) {
+        const real b0 = M.b0[t * NH + jt * 16 + i16];
+        acc[jt] = acc_t{b0, b0, b0, b0};
+    }
+    bool done = false;
+    if constexpr (sizeof(real) == 4) {
+        if (W.bf16) {
+            // input->hidden contraction in BF16 (FP32 sums): 16x16x16 blocks,
+            // A[i][4kq..4kq+3] and B[4kq..4kq+3][j] packed four to a lane
+            const float *Wb = M.W0bf + (size_t)t * DP * NH;
+            for (int ks = 0; ks < DPT / 16; ks++) {
+                bf16x4_t a;
 #pragma unroll
-            for (int h = 0; h < NH; h++) z[h] += (real)Wb[d * NH + h] * qd;
+                for (int u = 0; u < 4; u++) {
+                    const int d = ks * 16 + 4 * kq + u;
+                    const float v = (rv && d < DP) ? bf16_round((float)qrow[d]) : 0.f;
+                    a[u] = (short)(__float_as_uint(v) >> 16);
+                }
+#pragma unroll
+                for (int jt = 0; jt < 4; jt++) {
+                    bf16x4_t b;
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const int d = ks * 16 + 4 * kq + u;
+                        const float v = d < DP ? Wb[d * NH + jt * 16 + i16] : 0.f;
+                        b[u] = (short)(__float_as_uint(v) >> 16);
+                    }
+                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[jt], 0, 0, 0);
+                }
+            }
+            done = true;
         }
-    } else {
-        for (int d = 0; d < ND; d++) {
-            const real qd = q[d];
+    }
+    if (!done) {
+        for (int ks = 0; ks < DP / 4; ks++) {
+            const real a = rv ? qrow[ks * 4 + kq] : real(0);
 #pragma unroll
-            for (int h = 0; h < NH; h++) z[h] += W0[d * NH + h] * qd;
+            for (int jt = 0; jt < 4; jt++) acc[jt] = MF<real>::mma(a, sW[(ks * 4 + kq) * WLD + jt * 16 + i16], acc[jt]);
         }
     }
-    real E = M.b1[t];
+    // activation, energy and the hidden-layer gradient
+    real e[4] = {0, 0, 0, 0};
+    real *g = sG + wave * 16 * GLD;
 #pragma unroll
-    for (int h = 0; h < NH; h++) {
-        const real a = dtanh(z[h]);
-        const real w = M.w1[t * NH + h];
-        E += w * a;
-        z[h] = w * (real(1) - a * a);
-    }
-    real *Fp = W.Fp + (size_t)i * DP;
-    for (int d = 0; d < ND; d++) {
-        real s = 0;
+    for (int jt = 0; jt < 4; jt++) {
+        const real w = M.w1[t * NH + jt * 16 + i16];
 #pragma unroll
-        for (int h = 0; h < NH; h++) s += W0[d * NH + h] * z[h];
-        Fp[d] = s;
+        for (int r = 0; r < 4; r++) {
+            const real a = dtanh<real>(acc[jt][r]);
+            e[r] += w * a;
+            g[MF<real>::row(kq, r) * GLD + jt * 16 + i16] = w * (real(1) - a * a);
+        }
     }
-    W.Ei[i] = E;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) e[r] += __shfl_xor(e[r], m);
+    }
+    if (i16 == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = a0 + MF<real>::row(kq, r);
+            if (row < end) W.Ei[row] = M.b1[t] + e[r];
+        }
+    }
+    __syncthreads();
+    // Fp = G W0: A[i][k] = G[i][k], B[k][j] = W0[k][j] = sW[j][k]
+    acc_t f[DPT / 16];
+#pragma unroll
+    for (int jt = 0; jt < DPT / 16; jt++) f[jt] = acc_t{0, 0, 0, 0};
+    for (int ks = 0; ks < NH / 4; ks++) {
+        const real a = g[i16 * GLD + ks * 4 + kq];
+#pragma unroll
+        for (int jt = 0; jt < DPT / 16; jt++) f[jt] = MF<real>::mma(a, sW[(jt * 16 + i16) * WLD + ks * 4 + kq], f[jt]);
+    }
+#pragma unroll
+    for (int jt = 0; jt < DPT / 16; jt++) {
+        const int col = jt * 16 + i16;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = a0 + MF<real>::row(kq, r);
+            if (row < end && col < DP) W.Fp[(size_t)row * DP + col] = f[jt][r];
+        }
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -731,7 +825,7 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
             Ayz += g * rh[1] * rh[2];
         }
     }
-    real *o = W.selfc + (size_t)i * 8;
+    real *o = W.selfc + (size_t)S.colpos[i] * 8;
     o[0] = Axx;
     o[1] = Ayy;
     o[2] = Azz;
@@ -784,7 +878,10 @@ __global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> 
     }
 }
 
-// J_ij = a_ij + a_ji, D_ij = d_ij + d_ji, K_ij = b_ij + b_ji, with rhat_ij
+// J_ij = a_ij + a_ji, D_ij = d_ij + d_ji, K_ij = b_ij + b_ji, with rhat_ij,
+// stored compactly for the pairs inside rc_R only (in list order), so the
+// sweep's split of a spin's couplings over lanes depends on the positions
+// alone and not on which farther atoms the Verlet list happens to hold
 template <typename real>
 __global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -793,59 +890,77 @@ __global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
     const d4 pi = S.pos[i];
     const int nfe = min(S.cntFeR[i], MAXFE);
     const size_t ld = S.N, lf = S.N_fe;
+    const int p = S.colpos[i];
+    const real rc2 = (real)(RC_R * RC_R);
+    int cs = 0;
     for (int s = 0; s < nfe; s++) {
         const int j = S.nbrR[s * ld + i];
+        real d[3];
+        const real r2 = geom(S, R, pi, j, d);
+        if (r2 >= rc2) continue;
         const int t = min(S.revR[s * ld + i], MAXFE - 1);
         const real *a = W.craw + ((size_t)s * lf + i) * 3;
         const real *b = W.craw + ((size_t)t * lf + j) * 3;
-        real d[3];
-        const real r = dsqrt(geom(S, R, pi, j, d));
-        const real ir = real(1) / r;
-        real *c = W.cpl + ((size_t)s * lf + i) * 6;
+        const real ir = real(1) / dsqrt(r2);
+        real *c = W.cpl + ((size_t)cs * lf + p) * 6;
         c[0] = a[0] + b[0];
         c[1] = a[1] + b[1];
         c[2] = a[2] + b[2];
         c[3] = d[0] * ir;
         c[4] = d[1] * ir;
         c[5] = d[2] * ir;
+        W.cpl_j[(size_t)cs * lf + p] = j;
+        cs++;
     }
+    W.cpl_n[p] = cs;
 }
 
 inline int nblk(int n, int b) { return (n + b - 1) / b; }
 
 }  // namespace
 
+#define NEP_SPLIT(per)                                  \
+    const int ge = S.N - S.N_fe;                        \
+    const int nb_fe = nblk(S.N_fe, per), nb_ge = nblk(ge, per);
+
 template <typename real>
-void launch_forward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin,
-                    hipStream_t st) {
+void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st) {
     if (S.N == 0) return;
-    const int ge = S.N - S.N_fe;
-    {
-        const int a = nblk(S.N_fe, 256), b = nblk(ge, 256);
-        hipLaunchKernelGGL(k_desc_radial<real>, dim3(a + b), dim3(256), 0, st, S, M, W, spin, a);
-    }
-    {
-        const int a = nblk(S.N_fe, 32), b = nblk(ge, 32);
-        hipLaunchKernelGGL(k_desc_angular<real>, dim3(a + b), dim3(256), 0, st, S, M, W, spin, a);
-    }
-    {
-        const int a = nblk(S.N_fe, 128), b = nblk(ge, 128);
-        hipLaunchKernelGGL(k_mlp<real>, dim3(a + b), dim3(128), 0, st, S, M, W, a);
-    }
+    NEP_SPLIT(256)
+    hipLaunchKernelGGL(k_desc_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, spin, nb_fe);
 }
 
 template <typename real>
-void launch_backward(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st) {
     if (S.N == 0) return;
-    const int ge = S.N - S.N_fe;
-    {
-        const int a = nblk(S.N_fe, 256), b = nblk(ge, 256);
-        hipLaunchKernelGGL(k_bwd_radial<real>, dim3(a + b), dim3(256), 0, st, S, M, W, a);
-    }
-    {
-        const int a = nblk(S.N_fe, 32), b = nblk(ge, 32);
-        hipLaunchKernelGGL(k_bwd_angular<real>, dim3(a + b), dim3(256), 0, st, S, M, W, a);
-    }
+    NEP_SPLIT(32)
+    hipLaunchKernelGGL(k_desc_angular<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, spin, nb_fe);
+}
+
+template <typename real>
+void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N == 0) return;
+    NEP_SPLIT(MLP_ATOMS)
+    hipLaunchKernelGGL(k_mlp<real>, dim3(nb_fe + nb_ge), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
+}
+
+template <typename real>
+void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N == 0) return;
+    NEP_SPLIT(256)
+    hipLaunchKernelGGL(k_bwd_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, nb_fe);
+}
+
+template <typename real>
+void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N == 0) return;
+    NEP_SPLIT(32)
+    hipLaunchKernelGGL(k_bwd_angular<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, nb_fe);
+}
+
+template <typename real>
+void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st) {
+    if (S.N == 0) return;
     hipLaunchKernelGGL(k_gather<real>, dim3(nblk(S.N, 256)), dim3(256), 0, st, S, W);
 }
 
@@ -857,13 +972,18 @@ void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W,
     hipLaunchKernelGGL(k_assemble_sym<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, W);
 }
 
-template void launch_forward<double>(const Sys &, const ModelDev<double> &, const Work<double> &, const d4 *,
-                                     hipStream_t);
-template void launch_forward<float>(const Sys &, const ModelDev<float> &, const Work<float> &, const d4 *,
-                                    hipStream_t);
-template void launch_backward<double>(const Sys &, const ModelDev<double> &, const Work<double> &, hipStream_t);
-template void launch_backward<float>(const Sys &, const ModelDev<float> &, const Work<float> &, hipStream_t);
-template void launch_assemble<double>(const Sys &, const ModelDev<double> &, const Work<double> &, hipStream_t);
-template void launch_assemble<float>(const Sys &, const ModelDev<float> &, const Work<float> &, hipStream_t);
+#define NEP_INST(real)                                                                                           \
+    template void launch_desc_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, const d4 *, \
+                                           hipStream_t);                                                         \
+    template void launch_desc_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, const d4 *,\
+                                            hipStream_t);                                                        \
+    template void launch_mlp<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);        \
+    template void launch_bwd_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t); \
+    template void launch_bwd_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
+    template void launch_gather<real>(const Sys &, const Work<real> &, hipStream_t);                             \
+    template void launch_assemble<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);
+
+NEP_INST(double)
+NEP_INST(float)
 
 }  // namespace nep

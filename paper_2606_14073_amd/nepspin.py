@@ -24,7 +24,10 @@ PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED, "bf16h": SL_FP32_BF16H}
 EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
            "sl_replica_submit", "sl_replica_poll", "sl_replica_fetch", "sl_server_drain", "sl_server_stats",
-           "sl_server_destroy"]
+           "sl_server_destroy", "sl_profile_enable", "sl_profile_read"]
+
+PROFILE_GROUPS = ["desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "gather", "couplings",
+                  "sweep", "nlist", "integrate"]
 
 
 class NepError(RuntimeError):
@@ -109,6 +112,8 @@ def load():
         L.sl_server_drain.argtypes = [P]
         L.sl_server_stats.argtypes = [P, ct.POINTER(I64), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double)]
         L.sl_server_destroy.argtypes = [P]
+        L.sl_profile_enable.argtypes = [P, ct.c_uint]
+        L.sl_profile_read.argtypes = [P, P, P]
         _lib = L
     return _lib
 
@@ -244,6 +249,19 @@ class Sim:
         st = ct.c_int64()
         _check(load().sl_get_state(self.h, _p(pos), _p(vel), _p(spin), ct.byref(st)))
         return pos, vel, spin, st.value
+
+    def profile(self, groups):
+        """time the named kernel groups (PROFILE_GROUPS) with HIP events"""
+        mask = 0
+        for g in groups:
+            mask |= 1 << PROFILE_GROUPS.index(g)
+        _check(load().sl_profile_enable(self.h, mask))
+
+    def profile_read(self):
+        ms = np.zeros(len(PROFILE_GROUPS))
+        n = np.zeros(len(PROFILE_GROUPS), np.int64)
+        _check(load().sl_profile_read(self.h, _p(ms), _p(n)))
+        return {g: (float(ms[k]), int(n[k])) for k, g in enumerate(PROFILE_GROUPS)}
 
     def set_state(self, pos, vel, spin, step):
         _check(load().sl_set_state(self.h, _p(_f64(pos)), _p(_f64(vel)), _p(_f64(spin)), int(step)))
