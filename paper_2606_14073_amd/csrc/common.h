@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace nep {
 
 // model sizes (descriptor layout of the spin-aware NEP, Sec. 5.1)
@@ -225,6 +227,100 @@ __device__ inline void harmonics_grad(real x, real y, real z, real G[NLM][3]) {
 }
 
 __host__ __device__ constexpr int l_of_lm(int lm) { return lm < 3 ? 1 : lm < 8 ? 2 : lm < 15 ? 3 : 4; }
+
+// one harmonic R_lm (same normalisation and order as harmonics()) and its
+// gradient; with lm a compile-time constant only that polynomial is formed
+template <int lm, typename real>
+__device__ inline void harmonic_one(real x, real y, real z, real &Y, real &gx, real &gy, real &gz) {
+    const real s3 = real(1.7320508075688772), s38 = real(0.61237243569579452),
+               s15h = real(1.9364916731037085), s15 = real(3.8729833462074170),
+               s58 = real(0.79056941504209483), s10q = real(0.79056941504209483),
+               s5q = real(0.55901699437494742), s5 = real(2.2360679774997897), s5h = real(1.1180339887498949),
+               s70q = real(2.0916500663351889), s35e = real(0.73950997288745200),
+               s35h = real(2.9580398915498080);
+    const real xx = x * x, yy = y * y, zz = z * z, p2 = xx + yy;
+    if constexpr (lm == 0) { Y = x; gx = 1; gy = 0; gz = 0; }
+    else if constexpr (lm == 1) { Y = y; gx = 0; gy = 1; gz = 0; }
+    else if constexpr (lm == 2) { Y = z; gx = 0; gy = 0; gz = 1; }
+    else if constexpr (lm == 3) { Y = s3 * x * y; gx = s3 * y; gy = s3 * x; gz = 0; }
+    else if constexpr (lm == 4) { Y = s3 * y * z; gx = 0; gy = s3 * z; gz = s3 * y; }
+    else if constexpr (lm == 5) { Y = real(0.5) * (real(2) * zz - p2); gx = -x; gy = -y; gz = real(2) * z; }
+    else if constexpr (lm == 6) { Y = s3 * x * z; gx = s3 * z; gy = 0; gz = s3 * x; }
+    else if constexpr (lm == 7) { Y = real(0.5) * s3 * (xx - yy); gx = s3 * x; gy = -s3 * y; gz = 0; }
+    else if constexpr (lm == 8) {
+        Y = z * (zz - real(1.5) * p2);
+        gx = real(-3) * x * z; gy = real(-3) * y * z; gz = real(3) * zz - real(1.5) * p2;
+    } else if constexpr (lm == 9) {
+        Y = s38 * x * (real(4) * zz - p2);
+        gx = s38 * (real(4) * zz - real(3) * xx - yy); gy = s38 * real(-2) * x * y; gz = s38 * real(8) * x * z;
+    } else if constexpr (lm == 10) {
+        Y = s38 * y * (real(4) * zz - p2);
+        gx = s38 * real(-2) * x * y; gy = s38 * (real(4) * zz - xx - real(3) * yy); gz = s38 * real(8) * y * z;
+    } else if constexpr (lm == 11) {
+        Y = s15h * z * (xx - yy); gx = s15 * x * z; gy = -s15 * y * z; gz = s15h * (xx - yy);
+    } else if constexpr (lm == 12) {
+        Y = s15 * x * y * z; gx = s15 * y * z; gy = s15 * x * z; gz = s15 * x * y;
+    } else if constexpr (lm == 13) {
+        Y = s58 * x * (xx - real(3) * yy); gx = s58 * real(3) * (xx - yy); gy = s58 * real(-6) * x * y; gz = 0;
+    } else if constexpr (lm == 14) {
+        Y = s58 * y * (real(3) * xx - yy); gx = s58 * real(6) * x * y; gy = s58 * real(3) * (xx - yy); gz = 0;
+    } else if constexpr (lm == 15) {
+        Y = zz * zz - real(3) * zz * p2 + real(0.375) * p2 * p2;
+        gx = x * (real(-6) * zz + real(1.5) * p2); gy = y * (real(-6) * zz + real(1.5) * p2);
+        gz = z * (real(4) * zz - real(6) * p2);
+    } else if constexpr (lm == 16) {
+        Y = s10q * x * z * (real(4) * zz - real(3) * p2);
+        gx = s10q * z * (real(4) * zz - real(9) * xx - real(3) * yy); gy = s10q * real(-6) * x * y * z;
+        gz = s10q * x * (real(12) * zz - real(3) * p2);
+    } else if constexpr (lm == 17) {
+        Y = s10q * y * z * (real(4) * zz - real(3) * p2);
+        gx = s10q * real(-6) * x * y * z; gy = s10q * z * (real(4) * zz - real(3) * xx - real(9) * yy);
+        gz = s10q * y * (real(12) * zz - real(3) * p2);
+    } else if constexpr (lm == 18) {
+        Y = s5q * (xx - yy) * (real(6) * zz - p2);
+        gx = s5 * x * (real(3) * zz - xx); gy = -s5 * y * (real(3) * zz - yy); gz = real(3) * s5 * z * (xx - yy);
+    } else if constexpr (lm == 19) {
+        Y = s5h * x * y * (real(6) * zz - p2);
+        gx = s5h * y * (real(6) * zz - real(3) * xx - yy); gy = s5h * x * (real(6) * zz - xx - real(3) * yy);
+        gz = real(6) * s5 * x * y * z;
+    } else if constexpr (lm == 20) {
+        Y = s70q * x * z * (xx - real(3) * yy);
+        gx = s70q * real(3) * z * (xx - yy); gy = s70q * real(-6) * x * y * z; gz = s70q * x * (xx - real(3) * yy);
+    } else if constexpr (lm == 21) {
+        Y = s70q * y * z * (real(3) * xx - yy);
+        gx = s70q * real(6) * x * y * z; gy = s70q * real(3) * z * (xx - yy); gz = s70q * y * (real(3) * xx - yy);
+    } else if constexpr (lm == 22) {
+        Y = s35e * (xx * xx - real(6) * xx * yy + yy * yy);
+        gx = s35e * (real(4) * xx * x - real(12) * x * yy); gy = s35e * (real(4) * yy * y - real(12) * xx * y); gz = 0;
+    } else {
+        Y = s35h * x * y * (xx - yy);
+        gx = s35h * (real(3) * xx * y - yy * y); gy = s35h * (xx * x - real(3) * x * yy); gz = 0;
+    }
+}
+
+// the same with lm known only at run time (wave-uniform switch)
+template <typename real>
+__device__ inline void harmonic_dyn(int lm, real x, real y, real z, real &Y, real &gx, real &gy, real &gz) {
+    switch (lm) {
+#define NEP_HCASE(k) \
+    case k: harmonic_one<k>(x, y, z, Y, gx, gy, gz); break;
+        NEP_HCASE(0) NEP_HCASE(1) NEP_HCASE(2) NEP_HCASE(3) NEP_HCASE(4) NEP_HCASE(5) NEP_HCASE(6) NEP_HCASE(7)
+        NEP_HCASE(8) NEP_HCASE(9) NEP_HCASE(10) NEP_HCASE(11) NEP_HCASE(12) NEP_HCASE(13) NEP_HCASE(14)
+        NEP_HCASE(15) NEP_HCASE(16) NEP_HCASE(17) NEP_HCASE(18) NEP_HCASE(19) NEP_HCASE(20) NEP_HCASE(21)
+        NEP_HCASE(22)
+        default: harmonic_one<23>(x, y, z, Y, gx, gy, gz); break;
+#undef NEP_HCASE
+    }
+}
+
+// compile-time loop helper
+template <int N, typename F>
+__device__ inline void static_for(F &&f) {
+    if constexpr (N > 0) {
+        static_for<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
+}
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the two 32x32->64
 // multiplications and the Weyl key schedule.

@@ -165,7 +165,7 @@ struct Replica {
 static size_t bytes_per_atom(sl_precision prec) {
     const size_t rs = prec == SL_FP64 ? 8 : 4;
     size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
-    b += rs * (2 * DP + 1 + NA * NAB + 12 + 6 * MAXR + 6 * MAXA);
+    b += rs * (2 * DP + 1 + NA * NAB + 6 + 6 * MAXR + 4 * MAXA);
     b += (rs * (MAXFE * 9 + 8) + 4 * (MAXFE + 3)) / 2 + 64;
     return b;
 }
@@ -313,9 +313,8 @@ struct Engine {
         w.Ei = take(c);
         w.AB = take(c * NA * NAB);
         w.pbR = take((size_t)MAXR * c * 6);
-        w.pbA = take((size_t)MAXA * c * 6);
+        w.pbA = take((size_t)MAXA * c * 4);
         w.ownR = take(c * 6);
-        w.ownA = take(c * 6);
         w.craw = take((size_t)MAXFE * cf * 3);
         w.cpl = take((size_t)MAXFE * cf * 6);
         w.selfc = take(cf * 8);
@@ -326,8 +325,8 @@ struct Engine {
 
     static size_t work_count(size_t c, size_t cf) {
         auto r = [](size_t n) { return (n + 63) & ~(size_t)63; };
-        return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r((size_t)MAXR * c * 6) + r((size_t)MAXA * c * 6) +
-               2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
+        return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r((size_t)MAXR * c * 6) + r((size_t)MAXA * c * 4) +
+               r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
     }
 
     int reserve(size_t n, size_t nfe, size_t ncell, size_t nrep, size_t nchunk) {

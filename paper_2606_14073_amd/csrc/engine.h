@@ -39,8 +39,9 @@ struct ModelDev {
 template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
-    real *pbR, *pbA;            // pair records [MAXR|MAXA][N][6]: dE_i/dd_ij, dE_i/ds_j
-    real *ownR, *ownA;          // [N][6]: sum_j dE_i/dd_ij, dE_i/ds_i
+    real *pbR;                  // radial pair records [MAXR][N][6]: dE_i/dd_ij, dE_i/ds_j
+    real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij
+    real *ownR;                 // [N][6]: radial-set sum_j dE_i/dd_ij, dE_i/ds_i
     real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij (atom order)
     real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat (colour-list order)
     real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i (colour-list order)

@@ -222,63 +222,115 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
 }
 
 // -------------------------------------------------------------------------
-// forward: angular set (eight lanes per atom, lane n < 7 owns function n)
+// angular-set kernels: 32 atoms x 8 lanes per workgroup
 // -------------------------------------------------------------------------
+
+// coefficient tables c^A and c^sa of the workgroup's centre species for both
+// neighbour species, staged in LDS: [neighbour species][A | sa][n][k]
+template <typename real>
+__device__ inline void stage_ang_coeffs(const ModelDev<real> &M, int tc, real *sc) {
+    for (int x = threadIdx.x; x < 2 * 2 * NA * NB; x += blockDim.x) {
+        const int part = x / (2 * NA * NB), rem = x - part * 2 * NA * NB;
+        const int tab = rem / (NA * NB), nk = rem - tab * NA * NB;
+        sc[x] = (tab ? M.cSA : M.cA)[(tc + part) * NA * NB + nk];
+    }
+}
+
+template <typename real>
+__device__ inline real dotc(const real *c, const real f[NB]) {
+    real s = 0;
+#pragma unroll
+    for (int k = 0; k < NB; k++) s += c[k] * f[k];
+    return s;
+}
+
+// forward: lanes first stage eight neighbours of their atom (geometry, radial
+// functions g^A_n and (s_i.s_j) g^sa_n for all n, the 24 harmonics) in LDS,
+// then lane n accumulates A_nlm and B_nlm over the staged neighbours.
+constexpr int ANG_TW = 2 * NA + NLM;     // staged values per neighbour
+constexpr int ANG_TS = 8 * ANG_TW + 1;   // per-atom stride (shifts LDS banks)
 
 template <typename real>
 __global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, Work<real> W, const d4 *spin,
                                                       int nbFe) {
-    const int lane = threadIdx.x & 7;
+    __shared__ real tile[32 * ANG_TS];
+    __shared__ real sc[2 * 2 * NA * NB];
+    __shared__ int smax;
+    const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
-    const int i = atom_of_block(S, 32, nbFe, threadIdx.x >> 3, fe);
-    if (i < 0) return;
+    const int i = atom_of_block(S, 32, nbFe, slot, fe);
+    stage_ang_coeffs(M, fe ? 0 : 2, sc);
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    int cnt = 0, nfe = 0;
+    d4 pi = {0, 0, 0, 0};
+    real si[3] = {0, 0, 0};
+    const RepDev *R = nullptr;
+    if (i >= 0) {
+        cnt = S.cntA[i];
+        nfe = S.cntFeA[i];
+        pi = S.pos[i];
+        load_spin(spin, i, si);
+        R = &S.rep[S.rid[i]];
+        if (lane == 0) atomicMax(&smax, cnt);
+    }
+    __syncthreads();
+    const int rounds = (smax + 7) >> 3;
     const int n = lane < NA ? lane : NA - 1;
-    const RepDev &R = S.rep[S.rid[i]];
-    const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
-    const int cnt = S.cntA[i], nfe = S.cntFeA[i];
     const size_t ld = S.N;
-    real si[3];
-    load_spin(spin, i, si);
     real A[NLM], B[NLM];
 #pragma unroll
     for (int m = 0; m < NLM; m++) A[m] = B[m] = 0;
-    const int tc = fe ? 0 : 2;
-    for (int part = 0; part < 2; part++) {
-        const int tau = tc + part;
-        real cA[NB], cS[NB];
-#pragma unroll
-        for (int k = 0; k < NB; k++) {
-            cA[k] = M.cA[(tau * NA + n) * NB + k];
-            cS[k] = M.cSA[(tau * NA + n) * NB + k];
-        }
-        const bool spins = fe && part == 0;
-        const int b = part ? nfe : 0, e = part ? cnt : nfe;
-        for (int s = b; s < e; s++) {
+    real *my = tile + slot * ANG_TS;
+    for (int rd = 0; rd < rounds; rd++) {
+        const int s = rd * 8 + lane;
+        real *e = my + lane * ANG_TW;
+        if (s < cnt) {
             const int j = S.nbrA[s * ld + i];
             real d[3];
-            const real r2 = geom(S, R, pi, j, d);
-            if (r2 >= rc2) continue;
-            const real r = dsqrt(r2), ir = real(1) / r;
-            real f[NB];
-            radial_basis(r, rc, f);
-            const real gA = dotk(cA, f);
-            real gS = 0;
-            if (spins) {
-                real sj[3];
-                load_spin(spin, j, sj);
-                gS = dotk(cS, f) * (si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2]);
-            }
-            real Y[NLM];
-            harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+            const real r2 = geom(S, *R, pi, j, d);
+            if (r2 < rc2) {
+                const real r = dsqrt(r2), ir = real(1) / r;
+                real f[NB];
+                radial_basis(r, rc, f);
+                const int part = s < nfe ? 0 : 1;
+                real sig = 0;
+                if (fe && part == 0) {
+                    real sj[3];
+                    load_spin(spin, j, sj);
+                    sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+                }
+                const real *cA = sc + part * 2 * NA * NB, *cS = cA + NA * NB;
 #pragma unroll
-            for (int m = 0; m < NLM; m++) {
-                A[m] += gA * Y[m];
-                B[m] += gS * Y[m];
+                for (int nn = 0; nn < NA; nn++) {
+                    e[nn] = dotc(cA + nn * NB, f);
+                    e[NA + nn] = sig * dotc(cS + nn * NB, f);
+                }
+                real Y[NLM];
+                harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+#pragma unroll
+                for (int m = 0; m < NLM; m++) e[2 * NA + m] = Y[m];
+            } else {
+#pragma unroll
+                for (int k = 0; k < ANG_TW; k++) e[k] = 0;
             }
         }
+        __syncthreads();
+        const int qn = min(8, cnt - rd * 8);
+        for (int q = 0; q < qn; q++) {
+            const real *e2 = my + q * ANG_TW;
+            const real ga = e2[n], gs = e2[NA + n];
+#pragma unroll
+            for (int m = 0; m < NLM; m++) {
+                const real y = e2[2 * NA + m];
+                A[m] += ga * y;
+                B[m] += gs * y;
+            }
+        }
+        __syncthreads();
     }
-    if (lane >= NA) return;
+    if (i < 0 || lane >= NA) return;
     real qa[4] = {0, 0, 0, 0}, qs[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < NLM; m++) {
@@ -593,112 +645,111 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
 }
 
 // -------------------------------------------------------------------------
-// backward: angular set (eight lanes per atom)
+// backward: angular set
 //   q^A_nl = sum_m A_nlm^2, q^sa_nl = sum_m A_nlm B_nlm with
 //   A_nlm = sum_j g^A_n Y_lm(rhat_ij), B_nlm = sum_j g^sa_n (s_i.s_j) Y_lm(rhat_ij)
-//   dE/dd_ij = sum_lm [QA_lm d(g^A Y)/dd + (s_i.s_j) QS_lm d(g^sa Y)/dd],
-//   QA = 2 Fp^A A + Fp^sa B, QS = Fp^sa A;  dE_i/ds_j = (sum_lm QS Y) g^sa s_i
+//   dE_i/dd_ij = sum_lm [QA_lm d(g^A Y)/dd + (s_i.s_j) QS_lm d(g^sa Y)/dd]
+//   with QA_nlm = 2 Fp^A_nl A_nlm + Fp^sa_nl B_nlm, QS_nlm = Fp^sa_nl A_nlm;
+//   h_ij = sum_lm Y_lm sum_n QS_nlm g^sa_n, so that dE_i/ds_j = h_ij s_i and
+//   the pair adds h_ij s_j to dE_i/ds_i.
+// The eight lanes of an atom take its neighbours round robin, each pair in
+// full; the atom's 336 QA/QS values sit in LDS. A pair record holds
+// (dE_i/dd_ij, h_ij); the gather forms every sum in slot order.
 // -------------------------------------------------------------------------
+
+constexpr int QSTRIDE = 2 * NA * NLM + 1;
 
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_angular(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
-    const int lane = threadIdx.x & 7;
+    __shared__ real sQ[32 * QSTRIDE];
+    __shared__ real sc[2 * 2 * NA * NB];
+    const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
-    const int i = atom_of_block(S, 32, nbFe, threadIdx.x >> 3, fe);
+    const int i = atom_of_block(S, 32, nbFe, slot, fe);
+    stage_ang_coeffs(M, fe ? 0 : 2, sc);
+    real *Q = sQ + slot * QSTRIDE;   // QA[n][m] then QS[n][m]
+    if (i >= 0) {
+        const real *Fp = W.Fp + (size_t)i * DP;
+        for (int x = lane; x < NA * NLM; x += 8) {
+            const int n = x / NLM, m = x - n * NLM, l = l_of_lm(m) - 1;
+            const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+            const real fa = Fp[D_A + 4 * n + l], fs = Fp[D_SA + 4 * n + l];
+            Q[x] = real(2) * fa * ab[m] + fs * ab[NLM + m];
+            Q[NA * NLM + x] = fs * ab[m];
+        }
+    }
+    __syncthreads();
     if (i < 0) return;
-    const bool live = lane < NA;
-    const int n = live ? lane : NA - 1;
     const RepDev &R = S.rep[S.rid[i]];
     const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
     const int cnt = S.cntA[i], nfe = S.cntFeA[i];
     const size_t ld = S.N;
-    const real *Fp = W.Fp + (size_t)i * DP;
     real si[3];
     load_spin(S.spin, i, si);
-    real QA[NLM], QS[NLM];
-    {
-        const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
-        real fa[4], fs[4];
-#pragma unroll
-        for (int l = 0; l < 4; l++) {
-            fa[l] = live ? Fp[D_A + 4 * n + l] : real(0);
-            fs[l] = live ? Fp[D_SA + 4 * n + l] : real(0);
+    for (int s = lane; s < cnt; s += 8) {
+        const int j = S.nbrA[s * ld + i];
+        real d[3];
+        const real r2 = geom(S, R, pi, j, d);
+        real *rec = W.pbA + ((size_t)s * ld + i) * 4;
+        if (r2 >= rc2) {
+            rec[0] = rec[1] = rec[2] = rec[3] = 0;
+            continue;
         }
-#pragma unroll
-        for (int m = 0; m < NLM; m++) {
-            const int l = l_of_lm(m) - 1;
-            const real a = ab[m], b = ab[NLM + m];
-            QA[m] = real(2) * fa[l] * a + fs[l] * b;
-            QS[m] = fs[l] * a;
-        }
-    }
-    const real zero3[3] = {0, 0, 0};
-    real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
-    const int tc = fe ? 0 : 2;
-    for (int part = 0; part < 2; part++) {
-        const int tau = tc + part;
-        real cA[NB], cS[NB];
-#pragma unroll
-        for (int k = 0; k < NB; k++) {
-            cA[k] = M.cA[(tau * NA + n) * NB + k];
-            cS[k] = M.cSA[(tau * NA + n) * NB + k];
-        }
+        const real r = dsqrt(r2), ir = real(1) / r;
+        const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+        real f[NB], df[NB];
+        radial_basis_d(r, rc, f, df);
+        const int part = s < nfe ? 0 : 1;
         const bool spins = fe && part == 0;
-        const int b = part ? nfe : 0, e = part ? cnt : nfe;
-        for (int s = b; s < e; s++) {
-            const int j = S.nbrA[s * ld + i];
-            real d[3];
-            const real r2 = geom(S, R, pi, j, d);
-            if (r2 >= rc2) {
-                if (lane == 0) put_pair(W.pbA, s * ld + i, zero3, zero3);
-                continue;
-            }
-            const real r = dsqrt(r2), ir = real(1) / r;
-            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-            real f[NB], df[NB];
-            radial_basis_d(r, rc, f, df);
-            const real gA = dotk(cA, f), dgA = dotk(cA, df);
-            real sj[3] = {0, 0, 0}, sig = 0, gS = 0, dgS = 0;
-            if (spins) {
-                load_spin(S.spin, j, sj);
-                sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
-                gS = dotk(cS, f);
-                dgS = dotk(cS, df);
-            }
-            real Y[NLM], G[NLM][3];
-            harmonics(rh[0], rh[1], rh[2], Y);
-            harmonics_grad(rh[0], rh[1], rh[2], G);
-            real sv = 0, sl = 0, w = 0, su[3] = {0, 0, 0};
-            const real sgS = sig * gS, sdgS = sig * dgS;
-#pragma unroll
-            for (int m = 0; m < NLM; m++) {
-                const real u = QA[m] * gA + QS[m] * sgS;
-                const real v = QA[m] * dgA + QS[m] * sdgS;
-                sv += v * Y[m];
-                sl += real(l_of_lm(m)) * u * Y[m];
-                w += QS[m] * Y[m];
-                su[0] += u * G[m][0];
-                su[1] += u * G[m][1];
-                su[2] += u * G[m][2];
-            }
-            real g3[3];
-#pragma unroll
-            for (int x = 0; x < 3; x++) g3[x] = xor_sum8(sv * rh[x] + (su[x] - sl * rh[x]) * ir);
-            const real hs = xor_sum8(w * gS);
-            F[0] += g3[0];
-            F[1] += g3[1];
-            F[2] += g3[2];
-            h[0] += hs * sj[0];
-            h[1] += hs * sj[1];
-            h[2] += hs * sj[2];
-            if (lane == 0) {
-                const real hq[3] = {hs * si[0], hs * si[1], hs * si[2]};
-                put_pair(W.pbA, s * ld + i, g3, hq);
-            }
+        real sig = 0;
+        if (spins) {
+            real sj[3];
+            load_spin(S.spin, j, sj);
+            sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
         }
+        const real *cA = sc + part * 2 * NA * NB, *cS = cA + NA * NB;
+        real gA[NA], dgA[NA], gS[NA], dgS[NA];
+#pragma unroll
+        for (int n = 0; n < NA; n++) {
+            gA[n] = dotc(cA + n * NB, f);
+            dgA[n] = dotc(cA + n * NB, df);
+            gS[n] = spins ? dotc(cS + n * NB, f) : real(0);
+            dgS[n] = spins ? dotc(cS + n * NB, df) : real(0);
+        }
+        real sv = 0, sl = 0, hs = 0, su0 = 0, su1 = 0, su2 = 0;
+#pragma unroll 1
+        for (int m = 0; m < NLM; m++) {
+            real Y, gx, gy, gz;
+            harmonic_dyn(m, rh[0], rh[1], rh[2], Y, gx, gy, gz);
+            real qa_g = 0, qa_dg = 0, qs_g = 0, qs_dg = 0;
+#pragma unroll
+            for (int n = 0; n < NA; n++) {
+                const real qa = Q[n * NLM + m];
+                qa_g += qa * gA[n];
+                qa_dg += qa * dgA[n];
+            }
+            if (spins) {
+#pragma unroll
+                for (int n = 0; n < NA; n++) {
+                    const real qs = Q[NA * NLM + n * NLM + m];
+                    qs_g += qs * gS[n];
+                    qs_dg += qs * dgS[n];
+                }
+            }
+            const real U = qa_g + sig * qs_g, V = qa_dg + sig * qs_dg;
+            sv += V * Y;
+            sl += real(l_of_lm(m)) * U * Y;
+            hs += qs_g * Y;
+            su0 += U * gx;
+            su1 += U * gy;
+            su2 += U * gz;
+        }
+        rec[0] = sv * rh[0] + (su0 - sl * rh[0]) * ir;
+        rec[1] = sv * rh[1] + (su1 - sl * rh[1]) * ir;
+        rec[2] = sv * rh[2] + (su2 - sl * rh[2]) * ir;
+        rec[3] = hs;
     }
-    if (lane == 0) put_pair(W.ownA, (size_t)i, F, h);
 }
 
 // -------------------------------------------------------------------------
@@ -710,15 +761,16 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.N) return;
     const size_t ld = S.N;
+    const bool fe = k < S.N_fe;
     real F[3], h[3];
     {
-        const real *a = W.ownR + (size_t)k * 6, *b = W.ownA + (size_t)k * 6;
-        F[0] = a[0] + b[0];
-        F[1] = a[1] + b[1];
-        F[2] = a[2] + b[2];
-        h[0] = a[3] + b[3];
-        h[1] = a[4] + b[4];
-        h[2] = a[5] + b[5];
+        const real *a = W.ownR + (size_t)k * 6;
+        F[0] = a[0];
+        F[1] = a[1];
+        F[2] = a[2];
+        h[0] = a[3];
+        h[1] = a[4];
+        h[2] = a[5];
     }
     const int nr = S.cntR[k], na = S.cntA[k];
     for (int s = 0; s < nr; s++) {
@@ -735,18 +787,24 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     for (int s = 0; s < na; s++) {
         const int j = S.nbrA[s * ld + k];
         const int t = S.revA[s * ld + k];
-        const real *p = W.pbA + ((size_t)t * ld + j) * 6;
-        F[0] -= p[0];
-        F[1] -= p[1];
-        F[2] -= p[2];
-        h[0] += p[3];
-        h[1] += p[4];
-        h[2] += p[5];
+        const real *o = W.pbA + ((size_t)s * ld + k) * 4;
+        const real *p = W.pbA + ((size_t)t * ld + j) * 4;
+        F[0] += o[0] - p[0];
+        F[1] += o[1] - p[1];
+        F[2] += o[2] - p[2];
+        if (fe && j < S.N_fe) {
+            real sj[3];
+            load_spin(S.spin, j, sj);
+            const real w = o[3] + p[3];
+            h[0] += w * sj[0];
+            h[1] += w * sj[1];
+            h[2] += w * sj[2];
+        }
     }
     d4 f4 = {(double)F[0], (double)F[1], (double)F[2], 0.0};
     S.force[k] = f4;
     d4 h4 = {0, 0, 0, 0};
-    if (k < S.N_fe) {
+    if (fe) {
         const RepDev &R = S.rep[S.rid[k]];
         const double fr = ramp_frac(R), zs = R.mu_s * MUB;
         h4.x = -(double)h[0] + zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr);
@@ -836,30 +894,33 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
     o[7] = 0;
 }
 
-// spin-angular part of a_ij: sum_n g^sa_n(r_ij) sum_lm Fp^sa_nl A_nlm Y_lm(rhat_ij)
+// spin-angular part of a_ij: sum_n g^sa_n(r_ij) sum_lm Fp^sa_nl A_nlm Y_lm(rhat_ij);
+// lanes take the atom's spin-carrying neighbours round robin, P = Fp^sa A in LDS
+constexpr int PSTRIDE = NA * NLM + 1;
+
 template <typename real>
 __global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> M, Work<real> W) {
-    const int lane = threadIdx.x & 7;
-    const int i = blockIdx.x * 32 + (threadIdx.x >> 3);
+    __shared__ real sP[32 * PSTRIDE];
+    __shared__ real sc[NA * NB];
+    const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
+    const int i = blockIdx.x * 32 + slot;
+    for (int x = threadIdx.x; x < NA * NB; x += blockDim.x) sc[x] = M.cSA[x];   // tau = (Fe, Fe)
+    real *P = sP + slot * PSTRIDE;
+    if (i < S.N_fe) {
+        const real *Fp = W.Fp + (size_t)i * DP;
+        for (int x = lane; x < NA * NLM; x += 8) {
+            const int n = x / NLM, m = x - n * NLM;
+            P[x] = Fp[D_SA + 4 * n + l_of_lm(m) - 1] * W.AB[((size_t)i * NA + n) * NAB + m];
+        }
+    }
+    __syncthreads();
     if (i >= S.N_fe) return;
-    const bool live = lane < NA;
-    const int n = live ? lane : NA - 1;
     const RepDev &R = S.rep[S.rid[i]];
     const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
     const int nfe = S.cntFeA[i];
     const size_t ld = S.N, lf = S.N_fe;
-    const real *Fp = W.Fp + (size_t)i * DP;
-    real P[NLM];
-    {
-        const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
-#pragma unroll
-        for (int m = 0; m < NLM; m++) P[m] = live ? Fp[D_SA + 4 * n + l_of_lm(m) - 1] * ab[m] : real(0);
-    }
-    real cS[NB];
-#pragma unroll
-    for (int k = 0; k < NB; k++) cS[k] = M.cSA[(0 * NA + n) * NB + k];
-    for (int s = 0; s < nfe; s++) {
+    for (int s = lane; s < nfe; s += 8) {
         const int j = S.nbrA[s * ld + i];
         real d[3];
         const real r2 = geom(S, R, pi, j, d);
@@ -867,14 +928,22 @@ __global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> 
         const real r = dsqrt(r2), ir = real(1) / r;
         real f[NB];
         radial_basis(r, rc, f);
-        real Y[NLM];
-        harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
-        real w = 0;
+        real gS[NA];
 #pragma unroll
-        for (int m = 0; m < NLM; m++) w += P[m] * Y[m];
-        const real a = xor_sum8(w * dotk(cS, f));
+        for (int n = 0; n < NA; n++) gS[n] = dotc(sc + n * NB, f);
+        real a = 0;
+        const real x = d[0] * ir, y = d[1] * ir, z = d[2] * ir;
+#pragma unroll 1
+        for (int m = 0; m < NLM; m++) {
+            real Y, gx, gy, gz;
+            harmonic_dyn(m, x, y, z, Y, gx, gy, gz);
+            real w = 0;
+#pragma unroll
+            for (int n = 0; n < NA; n++) w += P[n * NLM + m] * gS[n];
+            a += w * Y;
+        }
         const int sr = S.a2r[s * ld + i];
-        if (lane == 0 && sr < MAXFE) W.craw[((size_t)sr * lf + i) * 3] += a;
+        if (sr < MAXFE) W.craw[((size_t)sr * lf + i) * 3] += a;
     }
 }
 
