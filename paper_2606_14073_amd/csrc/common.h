@@ -46,7 +46,7 @@ struct alignas(32) d4 {
 // Per-replica parameters, resident in device memory. Every kernel finds its
 // atom's replica through rid[] and reads box, schedule and counters here.
 struct RepDev {
-    double box[3];
+    double box[3], ibox[3];
     double dt, T0, T1, alpha, gammaL, mu_s, mid_tol, skin;
     double B0[3], B1[3];
     double cell_lo[3], cell_w[3];
@@ -69,9 +69,9 @@ __device__ inline void min_image(const RepDev &R, const d4 &pi, const d4 &pj, do
     dx = pj.x - pi.x;
     dy = pj.y - pi.y;
     dz = pj.z - pi.z;
-    if (R.pbc[0]) dx -= R.box[0] * rint(dx / R.box[0]);
-    if (R.pbc[1]) dy -= R.box[1] * rint(dy / R.box[1]);
-    if (R.pbc[2]) dz -= R.box[2] * rint(dz / R.box[2]);
+    if (R.pbc[0]) dx -= R.box[0] * rint(dx * R.ibox[0]);
+    if (R.pbc[1]) dy -= R.box[1] * rint(dy * R.ibox[1]);
+    if (R.pbc[2]) dz -= R.box[2] * rint(dz * R.ibox[2]);
 }
 
 template <typename real>
@@ -99,11 +99,80 @@ __device__ inline double dtanh<double>(double x) { return tanh(x); }
 template <>
 __device__ inline float dtanh<float>(float x) { return tanhf(x); }
 
+// Cutoff function fc(r) = (1 + cos(pi r/rc))/2 and its r-derivative. With
+// t = pi (r/rc - 1/2), |t| <= pi/2: cos(pi r/rc) = -sin t and
+// sin(pi r/rc) = cos t. In FP64 sin t and cos t come from their Taylor series
+// (coefficients +-1/n!, truncation below 2e-18 on |t| <= pi/2); FP32 uses
+// the device sinf/cosf.
+__device__ inline void sin_cos_halfpi(double t, double &sn, double &cs) {
+    const double t2 = t * t;
+    // p = -(1 - t^2/3! + t^4/5! - ... + t^20/21!), so sin t = -t p
+    double p = -1.0 / 51090942171709440000.0;           // 21!
+    p = p * t2 + 1.0 / 121645100408832000.0;            // 19!
+    p = p * t2 - 1.0 / 355687428096000.0;               // 17!
+    p = p * t2 + 1.0 / 1307674368000.0;                 // 15!
+    p = p * t2 - 1.0 / 6227020800.0;                    // 13!
+    p = p * t2 + 1.0 / 39916800.0;                      // 11!
+    p = p * t2 - 1.0 / 362880.0;                        // 9!
+    p = p * t2 + 1.0 / 5040.0;                          // 7!
+    p = p * t2 - 1.0 / 120.0;                           // 5!
+    p = p * t2 + 1.0 / 6.0;                             // 3!
+    p = p * t2 - 1.0;
+    sn = -t * p;
+    // q = 1/2! - t^2/4! + ... + t^20/22!, so cos t = 1 - t^2 q
+    double q = 1.0 / 1124000727777607680000.0;          // 1/22!
+    q = q * t2 - 1.0 / 2432902008176640000.0;           // -1/20!
+    q = q * t2 + 1.0 / 6402373705728000.0;              // 1/18!
+    q = q * t2 - 1.0 / 20922789888000.0;                // -1/16!
+    q = q * t2 + 1.0 / 87178291200.0;                   // 1/14!
+    q = q * t2 - 1.0 / 479001600.0;                     // -1/12!
+    q = q * t2 + 1.0 / 3628800.0;                       // 1/10!
+    q = q * t2 - 1.0 / 40320.0;                         // -1/8!
+    q = q * t2 + 1.0 / 720.0;                           // 1/6!
+    q = q * t2 - 1.0 / 24.0;                            // -1/4!
+    q = q * t2 + 0.5;                                   // 1/2!
+    cs = 1.0 - t2 * q;
+}
+
+template <typename real>
+__device__ inline void cutoff_fc(real r, real rc, real &fc, real &dfc);
+template <>
+__device__ inline void cutoff_fc<double>(double r, double rc, double &fc, double &dfc) {
+    double sn, cs;
+    sin_cos_halfpi(PI * (r / rc - 0.5), sn, cs);
+    fc = 0.5 * (1.0 - sn);
+    dfc = -0.5 * PI / rc * cs;
+}
+template <>
+__device__ inline void cutoff_fc<float>(float r, float rc, float &fc, float &dfc) {
+    const float a = (float)PI / rc;
+    fc = 0.5f * (1.0f + cosf(a * r));
+    dfc = -0.5f * a * sinf(a * r);
+}
+
+// r and 1/r from r^2: hardware reciprocal square root refined by Newton steps
+template <typename real>
+__device__ inline void r_and_inv(real r2, real &r, real &ir);
+template <>
+__device__ inline void r_and_inv<double>(double r2, double &r, double &ir) {
+    double y = __builtin_amdgcn_rsq(r2);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    y = y * (1.5 - 0.5 * r2 * y * y);
+    ir = y;
+    r = r2 * y;
+}
+template <>
+__device__ inline void r_and_inv<float>(float r2, float &r, float &ir) {
+    ir = rsqrtf(r2);
+    r = r2 * ir;
+}
+
 // Chebyshev radial basis at r < rc: f_k = (T_k(x)+1)/2 * fc(r), x = 2(r/rc-1)^2-1,
 // with T_k by the running recurrence T_{k+1} = 2x T_k - T_{k-1}.
 template <typename real>
 __device__ inline void radial_basis(real r, real rc, real f[NB]) {
-    const real fc = real(0.5) * (real(1) + dcos<real>(real(PI) * r / rc));
+    real fc, dfc;
+    cutoff_fc(r, rc, fc, dfc);
     const real u = r / rc - real(1);
     const real x = real(2) * u * u - real(1);
     real t0 = real(1), t1 = x;
@@ -122,10 +191,8 @@ __device__ inline void radial_basis(real r, real rc, real f[NB]) {
 // basis and its r-derivative; dT_{k+1} = 2 T_k + 2x dT_k - dT_{k-1}
 template <typename real>
 __device__ inline void radial_basis_d(real r, real rc, real f[NB], real df[NB]) {
-    const real a = real(PI) / rc;
-    const real cs = dcos<real>(a * r), sn = dsin<real>(a * r);
-    const real fc = real(0.5) * (real(1) + cs);
-    const real dfc = real(-0.5) * a * sn;
+    real fc, dfc;
+    cutoff_fc(r, rc, fc, dfc);
     const real u = r / rc - real(1);
     const real x = real(2) * u * u - real(1);
     const real dx = real(4) * u / rc;

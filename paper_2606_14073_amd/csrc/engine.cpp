@@ -872,6 +872,7 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
     std::memset(&d, 0, sizeof(d));
     for (int a = 0; a < 3; a++) {
         d.box[a] = sys->box[a];
+        d.ibox[a] = sys->box[a] > 0 ? 1.0 / sys->box[a] : 0.0;
         d.pbc[a] = sys->pbc[a] ? 1 : 0;
         d.B0[a] = d.B1[a] = sys->B[a];
     }

@@ -113,7 +113,8 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
             real d[3];
             const real r2 = geom(S, R, pi, j, d);
             if (r2 >= rc2) continue;
-            const real r = dsqrt(r2), ir = real(1) / r;
+            real r, ir;
+            r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
             real f[NB];
             radial_basis(r, rc, f);
@@ -161,7 +162,8 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
             real d[3];
             const real r2 = geom(S, R, pi, j, d);
             if (r2 >= rc2) continue;
-            const real r = dsqrt(r2), ir = real(1) / r;
+            real r, ir;
+            r_and_inv(r2, r, ir);
             real f[NB];
             radial_basis(r, rc, f);
             const real a = (si[0] * d[0] + si[1] * d[1] + si[2] * d[2]) * ir;
@@ -195,8 +197,9 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) continue;
-                real f[NB];
-                radial_basis(dsqrt(r2), rc, f);
+                real f[NB], r, ir;
+                r_and_inv(r2, r, ir);
+                radial_basis(r, rc, f);
 #pragma unroll
                 for (int k = 0; k < NB; k++) FR[k] += f[k];
             }
@@ -222,19 +225,16 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
 }
 
 // -------------------------------------------------------------------------
-// angular-set kernels: 32 atoms x 8 lanes per workgroup
+// angular-set kernels: one wavefront = 8 atoms x 8 lanes
+// Every neighbour loop runs in two phases, spin-carrying neighbours first
+// (they lead each list) and then the others, so within a phase the pair type
+// tau and thus every coefficient address is uniform across the wavefront and
+// the coefficients are scalar operands.
 // -------------------------------------------------------------------------
 
-// coefficient tables c^A and c^sa of the workgroup's centre species for both
-// neighbour species, staged in LDS: [neighbour species][A | sa][n][k]
-template <typename real>
-__device__ inline void stage_ang_coeffs(const ModelDev<real> &M, int tc, real *sc) {
-    for (int x = threadIdx.x; x < 2 * 2 * NA * NB; x += blockDim.x) {
-        const int part = x / (2 * NA * NB), rem = x - part * 2 * NA * NB;
-        const int tab = rem / (NA * NB), nk = rem - tab * NA * NB;
-        sc[x] = (tab ? M.cSA : M.cA)[(tc + part) * NA * NB + nk];
-    }
-}
+constexpr int ANG_ATOMS = 8;             // atoms per workgroup
+constexpr int ANG_TW = 2 * NA + NLM;     // staged values per neighbour
+constexpr int ANG_TS = 8 * ANG_TW + 1;   // per-atom stride (shifts LDS banks)
 
 template <typename real>
 __device__ inline real dotc(const real *c, const real f[NB]) {
@@ -244,23 +244,18 @@ __device__ inline real dotc(const real *c, const real f[NB]) {
     return s;
 }
 
-// forward: lanes first stage eight neighbours of their atom (geometry, radial
+// forward: per round, lanes stage eight neighbours of their atom (radial
 // functions g^A_n and (s_i.s_j) g^sa_n for all n, the 24 harmonics) in LDS,
-// then lane n accumulates A_nlm and B_nlm over the staged neighbours.
-constexpr int ANG_TW = 2 * NA + NLM;     // staged values per neighbour
-constexpr int ANG_TS = 8 * ANG_TW + 1;   // per-atom stride (shifts LDS banks)
-
+// then lane n accumulates A_nlm and B_nlm over the staged neighbours
 template <typename real>
-__global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, Work<real> W, const d4 *spin,
-                                                      int nbFe) {
-    __shared__ real tile[32 * ANG_TS];
-    __shared__ real sc[2 * 2 * NA * NB];
-    __shared__ int smax;
+__global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restrict__ C, Work<real> W,
+                                                     const d4 *spin, int nbFe) {
+    __shared__ real tile[ANG_ATOMS * ANG_TS];
+    __shared__ int smax[2];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
-    const int i = atom_of_block(S, 32, nbFe, slot, fe);
-    stage_ang_coeffs(M, fe ? 0 : 2, sc);
-    if (threadIdx.x == 0) smax = 0;
+    const int i = atom_of_block(S, ANG_ATOMS, nbFe, slot, fe);
+    if (threadIdx.x == 0) smax[0] = smax[1] = 0;
     __syncthreads();
     int cnt = 0, nfe = 0;
     d4 pi = {0, 0, 0, 0};
@@ -272,10 +267,12 @@ __global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, W
         pi = S.pos[i];
         load_spin(spin, i, si);
         R = &S.rep[S.rid[i]];
-        if (lane == 0) atomicMax(&smax, cnt);
+        if (lane == 0) {
+            atomicMax(&smax[0], nfe);
+            atomicMax(&smax[1], cnt - nfe);
+        }
     }
     __syncthreads();
-    const int rounds = (smax + 7) >> 3;
     const int n = lane < NA ? lane : NA - 1;
     const real rc = (real)RC_A, rc2 = rc * rc;
     const size_t ld = S.N;
@@ -283,52 +280,58 @@ __global__ void __launch_bounds__(256) k_desc_angular(Sys S, ModelDev<real> M, W
 #pragma unroll
     for (int m = 0; m < NLM; m++) A[m] = B[m] = 0;
     real *my = tile + slot * ANG_TS;
-    for (int rd = 0; rd < rounds; rd++) {
-        const int s = rd * 8 + lane;
-        real *e = my + lane * ANG_TW;
-        if (s < cnt) {
-            const int j = S.nbrA[s * ld + i];
-            real d[3];
-            const real r2 = geom(S, *R, pi, j, d);
-            if (r2 < rc2) {
-                const real r = dsqrt(r2), ir = real(1) / r;
-                real f[NB];
-                radial_basis(r, rc, f);
-                const int part = s < nfe ? 0 : 1;
-                real sig = 0;
-                if (fe && part == 0) {
-                    real sj[3];
-                    load_spin(spin, j, sj);
-                    sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+    for (int part = 0; part < 2; part++) {
+        const int tau = (fe ? 0 : 2) + part;
+        const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
+        const bool spins = fe && part == 0;
+        const int b = part ? nfe : 0, e = part ? cnt : nfe;
+        const int rounds = (smax[part] + 7) >> 3;
+        for (int rd = 0; rd < rounds; rd++) {
+            const int s = b + rd * 8 + lane;
+            real *en = my + lane * ANG_TW;
+            if (s < e) {
+                const int j = S.nbrA[s * ld + i];
+                real d[3];
+                const real r2 = geom(S, *R, pi, j, d);
+                if (r2 < rc2) {
+                    real r, ir;
+                    r_and_inv(r2, r, ir);
+                    real f[NB];
+                    radial_basis(r, rc, f);
+                    real sig = 0;
+                    if (spins) {
+                        real sj[3];
+                        load_spin(spin, j, sj);
+                        sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+                    }
+#pragma unroll
+                    for (int nn = 0; nn < NA; nn++) {
+                        en[nn] = dotc(cA + nn * NB, f);
+                        en[NA + nn] = spins ? sig * dotc(cS + nn * NB, f) : real(0);
+                    }
+                    real Y[NLM];
+                    harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+#pragma unroll
+                    for (int m = 0; m < NLM; m++) en[2 * NA + m] = Y[m];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < ANG_TW; k++) en[k] = 0;
                 }
-                const real *cA = sc + part * 2 * NA * NB, *cS = cA + NA * NB;
+            }
+            __syncthreads();
+            const int qn = min(8, e - (b + rd * 8));
+            for (int q = 0; q < qn; q++) {
+                const real *e2 = my + q * ANG_TW;
+                const real ga = e2[n], gs = e2[NA + n];
 #pragma unroll
-                for (int nn = 0; nn < NA; nn++) {
-                    e[nn] = dotc(cA + nn * NB, f);
-                    e[NA + nn] = sig * dotc(cS + nn * NB, f);
+                for (int m = 0; m < NLM; m++) {
+                    const real y = e2[2 * NA + m];
+                    A[m] += ga * y;
+                    B[m] += gs * y;
                 }
-                real Y[NLM];
-                harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
-#pragma unroll
-                for (int m = 0; m < NLM; m++) e[2 * NA + m] = Y[m];
-            } else {
-#pragma unroll
-                for (int k = 0; k < ANG_TW; k++) e[k] = 0;
             }
+            __syncthreads();
         }
-        __syncthreads();
-        const int qn = min(8, cnt - rd * 8);
-        for (int q = 0; q < qn; q++) {
-            const real *e2 = my + q * ANG_TW;
-            const real ga = e2[n], gs = e2[NA + n];
-#pragma unroll
-            for (int m = 0; m < NLM; m++) {
-                const real y = e2[2 * NA + m];
-                A[m] += ga * y;
-                B[m] += gs * y;
-            }
-        }
-        __syncthreads();
     }
     if (i < 0 || lane >= NA) return;
     real qa[4] = {0, 0, 0, 0}, qs[4] = {0, 0, 0, 0};
@@ -548,7 +551,8 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                     put_pair(W.pbR, s * ld + i, zero3, zero3);
                     continue;
                 }
-                const real r = dsqrt(r2), ir = real(1) / r;
+                real r, ir;
+            r_and_inv(r2, r, ir);
                 const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
@@ -597,7 +601,8 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                     put_pair(W.pbR, s * ld + i, zero3, zero3);
                     continue;
                 }
-                const real r = dsqrt(r2), ir = real(1) / r;
+                real r, ir;
+            r_and_inv(r2, r, ir);
                 const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
@@ -629,7 +634,8 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                     put_pair(W.pbR, s * ld + i, zero3, zero3);
                     continue;
                 }
-                const real r = dsqrt(r2), ir = real(1) / r;
+                real r, ir;
+            r_and_inv(r2, r, ir);
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
                 const real g = dotk(CR, df) * ir;
@@ -660,13 +666,11 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
 constexpr int QSTRIDE = 2 * NA * NLM + 1;
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_bwd_angular(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
-    __shared__ real sQ[32 * QSTRIDE];
-    __shared__ real sc[2 * 2 * NA * NB];
+__global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
+    __shared__ real sQ[ANG_ATOMS * QSTRIDE];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
-    const int i = atom_of_block(S, 32, nbFe, slot, fe);
-    stage_ang_coeffs(M, fe ? 0 : 2, sc);
+    const int i = atom_of_block(S, ANG_ATOMS, nbFe, slot, fe);
     real *Q = sQ + slot * QSTRIDE;   // QA[n][m] then QS[n][m]
     if (i >= 0) {
         const real *Fp = W.Fp + (size_t)i * DP;
@@ -687,68 +691,77 @@ __global__ void __launch_bounds__(256) k_bwd_angular(Sys S, ModelDev<real> M, Wo
     const size_t ld = S.N;
     real si[3];
     load_spin(S.spin, i, si);
-    for (int s = lane; s < cnt; s += 8) {
-        const int j = S.nbrA[s * ld + i];
-        real d[3];
-        const real r2 = geom(S, R, pi, j, d);
-        real *rec = W.pbA + ((size_t)s * ld + i) * 4;
-        if (r2 >= rc2) {
-            rec[0] = rec[1] = rec[2] = rec[3] = 0;
-            continue;
-        }
-        const real r = dsqrt(r2), ir = real(1) / r;
-        const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-        real f[NB], df[NB];
-        radial_basis_d(r, rc, f, df);
-        const int part = s < nfe ? 0 : 1;
-        const bool spins = fe && part == 0;
-        real sig = 0;
-        if (spins) {
-            real sj[3];
-            load_spin(S.spin, j, sj);
-            sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
-        }
-        const real *cA = sc + part * 2 * NA * NB, *cS = cA + NA * NB;
-        real gA[NA], dgA[NA], gS[NA], dgS[NA];
-#pragma unroll
-        for (int n = 0; n < NA; n++) {
-            gA[n] = dotc(cA + n * NB, f);
-            dgA[n] = dotc(cA + n * NB, df);
-            gS[n] = spins ? dotc(cS + n * NB, f) : real(0);
-            dgS[n] = spins ? dotc(cS + n * NB, df) : real(0);
-        }
-        real sv = 0, sl = 0, hs = 0, su0 = 0, su1 = 0, su2 = 0;
 #pragma unroll 1
-        for (int m = 0; m < NLM; m++) {
-            real Y, gx, gy, gz;
-            harmonic_dyn(m, rh[0], rh[1], rh[2], Y, gx, gy, gz);
-            real qa_g = 0, qa_dg = 0, qs_g = 0, qs_dg = 0;
+    for (int part = 0; part < 2; part++) {
+        const int tau = (fe ? 0 : 2) + part;
+        const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
+        const bool spins = fe && part == 0;
+        const int b = part ? nfe : 0, e = part ? cnt : nfe;
+#pragma unroll 1
+        for (int s = b + lane; s < e; s += 8) {
+            const int j = S.nbrA[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            real *rec = W.pbA + ((size_t)s * ld + i) * 4;
+            if (r2 >= rc2) {
+                rec[0] = rec[1] = rec[2] = rec[3] = 0;
+                continue;
+            }
+            real r, ir;
+            r_and_inv(r2, r, ir);
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB], df[NB];
+            radial_basis_d(r, rc, f, df);
+            real sig = 0;
+            if (spins) {
+                real sj[3];
+                load_spin(S.spin, j, sj);
+                sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+            }
+            real gA[NA], dgA[NA], gS[NA], dgS[NA];
 #pragma unroll
             for (int n = 0; n < NA; n++) {
-                const real qa = Q[n * NLM + m];
-                qa_g += qa * gA[n];
-                qa_dg += qa * dgA[n];
+                gA[n] = dotc(cA + n * NB, f);
+                dgA[n] = dotc(cA + n * NB, df);
+                gS[n] = spins ? dotc(cS + n * NB, f) : real(0);
+                dgS[n] = spins ? dotc(cS + n * NB, df) : real(0);
             }
-            if (spins) {
+            real sv = 0, sl = 0, hs = 0, su0 = 0, su1 = 0, su2 = 0;
+#pragma unroll 1
+            for (int m = 0; m < NLM; m++) {
+                real Y, gx, gy, gz;
+                // keep the harmonic inside the loop (no hoisting of all 24 cases)
+                real hx = rh[0], hy = rh[1], hz = rh[2];
+                asm volatile("" : "+v"(hx), "+v"(hy), "+v"(hz));
+                harmonic_dyn(m, hx, hy, hz, Y, gx, gy, gz);
+                real qa_g = 0, qa_dg = 0, qs_g = 0, qs_dg = 0;
 #pragma unroll
                 for (int n = 0; n < NA; n++) {
-                    const real qs = Q[NA * NLM + n * NLM + m];
-                    qs_g += qs * gS[n];
-                    qs_dg += qs * dgS[n];
+                    const real qa = Q[n * NLM + m];
+                    qa_g += qa * gA[n];
+                    qa_dg += qa * dgA[n];
                 }
+                if (spins) {
+#pragma unroll
+                    for (int n = 0; n < NA; n++) {
+                        const real qs = Q[NA * NLM + n * NLM + m];
+                        qs_g += qs * gS[n];
+                        qs_dg += qs * dgS[n];
+                    }
+                }
+                const real U = qa_g + sig * qs_g, V = qa_dg + sig * qs_dg;
+                sv += V * Y;
+                sl += real(l_of_lm(m)) * U * Y;
+                hs += qs_g * Y;
+                su0 += U * gx;
+                su1 += U * gy;
+                su2 += U * gz;
             }
-            const real U = qa_g + sig * qs_g, V = qa_dg + sig * qs_dg;
-            sv += V * Y;
-            sl += real(l_of_lm(m)) * U * Y;
-            hs += qs_g * Y;
-            su0 += U * gx;
-            su1 += U * gy;
-            su2 += U * gz;
+            rec[0] = sv * rh[0] + (su0 - sl * rh[0]) * ir;
+            rec[1] = sv * rh[1] + (su1 - sl * rh[1]) * ir;
+            rec[2] = sv * rh[2] + (su2 - sl * rh[2]) * ir;
+            rec[3] = hs;
         }
-        rec[0] = sv * rh[0] + (su0 - sl * rh[0]) * ir;
-        rec[1] = sv * rh[1] + (su1 - sl * rh[1]) * ir;
-        rec[2] = sv * rh[2] + (su2 - sl * rh[2]) * ir;
-        rec[3] = hs;
     }
 }
 
@@ -773,6 +786,7 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[2] = a[5];
     }
     const int nr = S.cntR[k], na = S.cntA[k];
+#pragma unroll 4
     for (int s = 0; s < nr; s++) {
         const int j = S.nbrR[s * ld + k];
         const int t = S.revR[s * ld + k];
@@ -784,6 +798,7 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[1] += p[4];
         h[2] += p[5];
     }
+#pragma unroll 4
     for (int s = 0; s < na; s++) {
         const int j = S.nbrA[s * ld + k];
         const int t = S.revA[s * ld + k];
@@ -846,7 +861,8 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
                 c[0] = c[1] = c[2] = 0;
                 continue;
             }
-            const real r = dsqrt(r2), ir = real(1) / r;
+            real r, ir;
+            r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
             real f[NB];
             radial_basis(r, rc, f);
@@ -870,7 +886,8 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
             real d[3];
             const real r2 = geom(S, R, pi, j, d);
             if (r2 >= rc2) continue;
-            const real r = dsqrt(r2), ir = real(1) / r;
+            real r, ir;
+            r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
             real f[NB];
             radial_basis(r, rc, f);
@@ -899,12 +916,11 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
 constexpr int PSTRIDE = NA * NLM + 1;
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> M, Work<real> W) {
-    __shared__ real sP[32 * PSTRIDE];
-    __shared__ real sc[NA * NB];
+__global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__restrict__ C, Work<real> W) {
+    __shared__ real sP[ANG_ATOMS * PSTRIDE];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
-    const int i = blockIdx.x * 32 + slot;
-    for (int x = threadIdx.x; x < NA * NB; x += blockDim.x) sc[x] = M.cSA[x];   // tau = (Fe, Fe)
+    const int i = blockIdx.x * ANG_ATOMS + slot;
+    const real *cS = C + P_CSA;   // tau = (Fe, Fe)
     real *P = sP + slot * PSTRIDE;
     if (i < S.N_fe) {
         const real *Fp = W.Fp + (size_t)i * DP;
@@ -925,12 +941,13 @@ __global__ void __launch_bounds__(256) k_assemble_angular(Sys S, ModelDev<real> 
         real d[3];
         const real r2 = geom(S, R, pi, j, d);
         if (r2 >= rc2) continue;
-        const real r = dsqrt(r2), ir = real(1) / r;
+        real r, ir;
+        r_and_inv(r2, r, ir);
         real f[NB];
         radial_basis(r, rc, f);
         real gS[NA];
 #pragma unroll
-        for (int n = 0; n < NA; n++) gS[n] = dotc(sc + n * NB, f);
+        for (int n = 0; n < NA; n++) gS[n] = dotc(cS + n * NB, f);
         real a = 0;
         const real x = d[0] * ir, y = d[1] * ir, z = d[2] * ir;
 #pragma unroll 1
@@ -970,7 +987,8 @@ __global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
         const int t = min(S.revR[s * ld + i], MAXFE - 1);
         const real *a = W.craw + ((size_t)s * lf + i) * 3;
         const real *b = W.craw + ((size_t)t * lf + j) * 3;
-        const real ir = real(1) / dsqrt(r2);
+        real r, ir;
+        r_and_inv(r2, r, ir);
         real *c = W.cpl + ((size_t)cs * lf + p) * 6;
         c[0] = a[0] + b[0];
         c[1] = a[1] + b[1];
@@ -1002,8 +1020,8 @@ void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> 
 template <typename real>
 void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st) {
     if (S.N == 0) return;
-    NEP_SPLIT(32)
-    hipLaunchKernelGGL(k_desc_angular<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, spin, nb_fe);
+    NEP_SPLIT(ANG_ATOMS)
+    hipLaunchKernelGGL(k_desc_angular<real>, dim3(nb_fe + nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, spin, nb_fe);
 }
 
 template <typename real>
@@ -1023,8 +1041,8 @@ void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &
 template <typename real>
 void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N == 0) return;
-    NEP_SPLIT(32)
-    hipLaunchKernelGGL(k_bwd_angular<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, nb_fe);
+    NEP_SPLIT(ANG_ATOMS)
+    hipLaunchKernelGGL(k_bwd_angular<real>, dim3(nb_fe + nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, nb_fe);
 }
 
 template <typename real>
@@ -1037,7 +1055,7 @@ template <typename real>
 void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N_fe == 0) return;
     hipLaunchKernelGGL(k_assemble_radial<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M, W);
-    hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, 32)), dim3(256), 0, st, S, M, W);
+    hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, ANG_ATOMS)), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_assemble_sym<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, W);
 }
 
