@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the spin-lattice NEP step on one MI355X.
 
-Workload: B20 FeGe-like crystal, 32x32x32 cells = 262,144 atoms (131,072
-spins), periodic, seeded random model, 300 K Langevin lattice bath and
-stochastic-LLG spin bath (damping 0.1), dt = 1 fs, FP64 end to end. One
-step = the whole B A O S A B step (3 descriptor passes, read-out, spin
-couplings, 4 colour sweeps, one backward pass, neighbour-list upkeep and the
-lattice half-steps) for every atom. Inputs are resident on the device before
-the timed region.
+Headline workload: B20 FeGe-like crystal, 32x32x32 cells = 262,144 atoms
+(131,072 spins), periodic, seeded random model, 300 K Langevin lattice bath
+and stochastic-LLG spin bath (damping 0.1), dt = 1 fs, FP64 end to end. One
+step = the whole B A O S A B step (three descriptor passes and read-outs,
+two spin-coupling assemblies, four colour sweeps, one backward pass,
+neighbour-list upkeep, half-steps and baths) for every atom. Inputs are
+resident on the device before the timed region; the clock brackets
+sl_integrate_steps, which returns after the device has finished.
 
-Prints one JSON line (see the keys below). --gpus N > 1 is refused: this
-build runs on one GPU.
+Also reported: the FP32-mixed variant of the same workload, a bounded sample
+of the replica-serving workload (p50/p99 step latency), the roofline of the
+dominant kernel (HIP-event time over the timed region against an algorithmic
+FLOP count) and the CPU oracle on the host cores.
+
+Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -18,6 +23,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,54 +36,143 @@ import numpy as np  # noqa: E402
 from paper_2606_14073_amd import workload as W  # noqa: E402
 
 # MI355X published peaks
-PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
-PEAK_HBM_GBS = 8000.0
+PEAK = {"fp64": 78.6, "fp32": 157.3, "hbm_gbs": 8000.0}
+KERNEL_NAME = {"desc_radial": "k_desc_radial", "desc_angular": "k_desc_angular", "readout": "k_mlp",
+               "bwd_radial": "k_bwd_radial", "bwd_angular": "k_bwd_angular", "gather": "k_gather",
+               "couplings": "k_assemble_*", "sweep": "k_sweep", "nlist": "k_build/k_rev", "integrate": "k_kick/..."}
 
 
 def pair_counts(s):
-    """Neighbour statistics of the workload (for the algorithmic work model)."""
+    """Ordered neighbour pairs of the workload inside each cutoff."""
     from scipy.spatial import cKDTree
     p = np.mod(s.pos, s.box)
     tree = cKDTree(p, boxsize=s.box)
     fe = s.types == 0
     out = {}
     for rc, key in ((6.0, "R"), (4.5, "A")):
-        pairs = tree.query_pairs(rc, output_type="ndarray")
-        a, b = pairs[:, 0], pairs[:, 1]
-        out[key] = 2 * len(pairs)                                   # ordered pairs
+        pr = tree.query_pairs(rc, output_type="ndarray")
+        a, b = pr[:, 0], pr[:, 1]
+        out[key] = 2 * len(pr)
         out[key + "_fefe"] = 2 * int(np.sum(fe[a] & fe[b]))
-        out[key + "_fe_centre"] = int(np.sum(fe[a])) + int(np.sum(fe[b]))   # pairs with an Fe centre
+        out[key + "_fege"] = 2 * int(np.sum(fe[a] ^ fe[b]))     # ordered pairs with one Fe, one Ge
+    out["N"] = s.n
+    out["N_fe"] = int(fe.sum())
     return out
 
 
-def work_model(pc, n, n_fe):
-    """Algorithmic FLOPs of one launch of the angular-set backward kernel
-    (FMA = 2 FLOP), counted once per (centre, neighbour) pair inside 4.5 A:
-      per pair: radial basis with derivative (cos+sin, Chebyshev, 9 f and 9 df) 60;
-      harmonics and their gradients 24 + 72 -> 150;
-      per radial function n (7): g^A, dg^A (36), and for spin pairs g^sa, dg^sa (36);
-      per (n, lm) contraction: u, v (4 FMA), sums sv, sl, w, su (6 FMA) = 20 FLOP;
-      per pair gradient assembly 20."""
-    per_pair = 60 + 150 + 7 * 36 + 7 * 24 * 20 + 20
-    spin_pairs = pc["A_fefe"]
-    return pc["A"] * per_pair + spin_pairs * 7 * 36
+def flops_per_launch(group, pc):
+    """Algorithmic FLOPs of one launch (FMA = 2), counted once per (centre,
+    neighbour) pair inside the channel's cutoff and once per atom; the
+    figures per pair are listed in the design doc."""
+    N, Nfe = pc["N"], pc["N_fe"]
+    fe_centre_fe = pc["R_fefe"]             # spin pairs, radial set
+    fe_centre_ge = pc["R_fege"] // 2        # Fe centre, Ge neighbour
+    if group == "desc_angular":
+        # per pair: geometry/basis 75, g^A 126, harmonics 50, A accumulation 336;
+        # spin pairs: g^sa 133, B accumulation 336; per atom q^A, q^sa 672
+        return pc["A"] * 587 + pc["A_fefe"] * 469 + N * 672
+    if group == "bwd_angular":
+        # per pair: geometry/basis+derivative 110, g^A and dg^A 252, harmonics and
+        # gradients 150, per lm contraction 44 x 24; spin pairs: g^sa, dg^sa 252 and
+        # 28 x 24; per atom QA, QS 1008
+        return pc["A"] * 1568 + pc["A_fefe"] * 924 + N * 1008
+    if group == "desc_radial":
+        # per pair: geometry/basis 80 + radial accumulation 18; Fe-Fe: spin scalars 25 +
+        # four magnetic channels 72; Fe-Ge: single-ion 20; per atom contractions
+        return pc["R"] * 98 + fe_centre_fe * 97 + fe_centre_ge * 20 + Nfe * 2 * 5 * 162 + (N - Nfe) * 2 * 162
+    if group == "bwd_radial":
+        # per pair: geometry/basis+derivative 115, radial dg 18, record 20; Fe-Fe: 8 more
+        # channel values 144 + force/field terms 90; Fe-Ge: 36 + 30; per atom contractions
+        return pc["R"] * 153 + fe_centre_fe * 234 + fe_centre_ge * 66 + Nfe * 5 * 162 + N * 2 * 162
+    if group == "readout":
+        # 2 x (104 x 64) FMA per atom + tanh, energy and gradient
+        return N * (2 * 2 * 104 * 64 + 64 * 30)
+    return None
+
+
+def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
+    """Poisson arrivals of the serving request mix (cubic FeGe cells, N
+    log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed."""
+    reqs = W.serving_requests(n_req, rate=rate, seed=seed, n_steps=n_steps)
+    built = []
+    for r in reqs:
+        s = W.fege_lattice(r.cells, r.cells, r.cells, seed=r.seed, greedy=False)
+        v = W.maxwell_boltzmann(s.types, r.T, seed=r.seed + 1)
+        ip = nepspin.integrator_params(dt=1.0, T0=r.T, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, r.Bz),
+                                       seed=r.seed)
+        built.append((r, s, v, ip))
+    sv = nepspin.Server(model, precision="fp32", steps_per_batch=10, max_slots=256)
+    t0 = time.perf_counter()
+    ids = []
+    for r, s, v, ip in built:
+        dt = r.t_arrival - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(sv.submit(s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                             n_steps=r.n_steps))
+    sv.drain()
+    t1 = time.perf_counter()
+    st = [sv.poll(k) for k in ids]
+    stats = sv.stats()
+    sv.close()
+    lat50 = [x["step_latency_p50"] for x in st]
+    lat99 = [x["step_latency_p99"] for x in st]
+    wait = [x["t_admit"] - x["t_submit"] for x in st]
+    atoms = sum(s.n for _, s, _, _ in built)
+    return {"requests": n_req, "steps_each": n_steps, "arrival_rate_per_s": rate,
+            "atoms_total": atoms, "wall_s": round(t1 - t0, 3),
+            "atom_steps_per_s": stats["atom_steps"] / (t1 - t0),
+            "p50_step_latency_ms": 1e3 * float(np.median(lat50)),
+            "p99_step_latency_ms": 1e3 * float(np.percentile(lat99, 99)),
+            "mean_queue_wait_s": float(np.mean(wait)),
+            "failed": int(sum(x["state"] != nepspin.SL_DONE for x in st))}
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated), if one exists."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        return d.get(kernel, {}).get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the traffic counters."""
+    import torch
+    n = 1 << 27     # 128 Mi doubles = 1 GiB
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=24)
+    ap.add_argument("--serving-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=1)
-    ap.add_argument("--breakdown", action="store_true", help="print the kernel-group breakdown to stderr")
+    ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} requested, but this build runs on one GPU only; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib:
+        copy_calibration()
+        return
 
     from paper_2606_14073_amd import nepspin
 
@@ -100,38 +195,54 @@ def main():
         t1 = time.perf_counter()
         prof = sim.profile_read()
         sim.profile(())
-        return sim, t1 - t0, prof
+        sim.close()
+        return t1 - t0, prof
 
-    # FP64 (the headline workload); the dominant kernel is timed with HIP events
-    dom = "bwd_angular"
-    sim64, dt64, prof64 = run("fp64", (dom,))
+    # FP64 headline; every kernel group timed with HIP events on the library's stream
+    dt64, prof = run("fp64", tuple(nepspin.PROFILE_GROUPS))
     rate64 = s.n * K / dt64
     print(f"fp64: {K} steps in {dt64:.3f} s -> {rate64:.4e} atom-steps/s", file=sys.stderr, flush=True)
+    tot = sum(v[0] for v in prof.values())
+    for g, (m_, n_) in prof.items():
+        print(f"  {g:13s} {m_ / K:8.3f} ms/step  {100 * m_ / tot:5.1f}%  launches/step {n_ / K:.1f}",
+              file=sys.stderr)
 
     pc = pair_counts(s)
-    flops_launch = work_model(pc, s.n, int((s.types == 0).sum()))
-    ms, nl = prof64[dom]
-    avg_ms = ms / max(nl, 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_bwd_angular<double>", "bound": "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(avg_ms, 4), "launches": nl,
-                "flop_per_launch": flops_launch}
+    dom = max(prof, key=lambda g: prof[g][0])
+    groups = {}
+    for g, (ms, nl) in prof.items():
+        fl = flops_per_launch(g, pc)
+        if fl is None or nl == 0:
+            continue
+        avg = ms / nl
+        ach = fl / (avg * 1e-3) / 1e12
+        groups[g] = {"avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_launch": int(fl),
+                     "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4)}
+    d = groups.get(dom)
+    kname = f"{KERNEL_NAME.get(dom, dom)}<double>"
+    if d is not None:
+        roofline = {"kernel": kname, "bound": "mfma" if dom == "readout" else "alu",
+                    "achieved": d["achieved_tflops"], "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                    "frac": d["frac_fp64_peak"], "traffic": traffic_from_profile(kname),
+                    "avg_launch_ms": d["avg_launch_ms"], "launches": d["launches"],
+                    "flop_per_launch": d["flop_per_launch"]}
+    else:
+        roofline = {"kernel": kname, "bound": None, "achieved": None, "peak": None, "unit": None,
+                    "frac": None, "traffic": None, "note": "dominant group has no work model"}
 
-    extra = {}
-    if args.breakdown:
-        _, _, prof = run("fp64", tuple(nepspin.PROFILE_GROUPS))
-        tot = sum(v[0] for v in prof.values())
-        for g, (m_, n_) in prof.items():
-            print(f"  {g:13s} {m_ / K:8.3f} ms/step  {100 * m_ / tot:5.1f}%  launches/step {n_ / K:.1f}",
-                  file=sys.stderr)
-        extra["breakdown_ms_per_step"] = {g: round(m_ / K, 4) for g, (m_, n_) in prof.items()}
+    extra = {"breakdown_ms_per_step": {g: round(m_ / K, 4) for g, (m_, n_) in prof.items()},
+             "kernel_rooflines": groups}
 
     if not args.no_fp32:
-        _, dt32, _ = run("fp32")
-        extra["fp32_mixed"] = {"value": s.n * K / dt32, "ms_per_step": 1e3 * dt32 / K}
+        dt32, _ = run("fp32")
+        extra["fp32_mixed"] = {"value": s.n * K / dt32, "ms_per_step": 1e3 * dt32 / K,
+                               "speedup_vs_fp64": dt64 / dt32}
         print(f"fp32-mixed: {K} steps in {dt32:.3f} s -> {s.n * K / dt32:.4e} atom-steps/s",
               file=sys.stderr, flush=True)
+
+    if not args.no_serving:
+        extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)
+        print(f"serving: {extra['serving']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
@@ -144,8 +255,9 @@ def main():
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cpu = {"value": s.n * args.cpu_steps / (t1 - t0), "unit": "atom-steps/s", "cores": cores,
                "kind": "oracle",
-               "sample": f"{args.cpu_steps} step(s) of the same 262,144-atom workload from its initial state "
-                         f"({t1 - t0:.1f} s, OpenMP over atoms)"}
+               "sample": f"{args.cpu_steps} full step(s) of the same 262,144-atom workload from its initial state, "
+                         f"{t1 - t0:.1f} s with OpenMP over atoms"}
+        print(f"cpu oracle: {cpu}", file=sys.stderr, flush=True)
 
     line = {
         "metric": "atom-steps/s per MI355X (FP64 spin-lattice NEP step)",

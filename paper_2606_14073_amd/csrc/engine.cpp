@@ -153,7 +153,7 @@ struct Replica {
     int fe_off = -1, ge_off = -1;          // position in the current layout, -1 when not resident
     int slot = -1;                         // replica index in the layout
     std::vector<double> pos, vel, spin;    // caller order, used before admission / after eviction
-    int64_t n_steps = 0, steps_done = 0;
+    int64_t n_steps = 0, steps_done = 0, step0 = 0;
     int state = SL_QUEUED, error = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     std::vector<double> lat;
@@ -818,7 +818,7 @@ static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int
     for (int i : fe) {
         const int ci = cid[i];
         int c0 = ci / (nc[1] * nc[2]), c1 = (ci / nc[2]) % nc[1], c2 = ci % nc[2];
-        std::vector<char> used(64, 0);
+        std::vector<char> used(512, 0);
         for (int dx = -1; dx <= 1; dx++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dz = -1; dz <= 1; dz++) {
@@ -1304,7 +1304,6 @@ void sl_server::run() {
         }
         if (changed || next != eng.reps) {
             int rc = eng.set_layout(next);
-            if (!rc) rc = eng.check_flags();
             std::lock_guard<std::mutex> lk(mu);
             resident = next;
             if (rc) {
@@ -1337,7 +1336,7 @@ void sl_server::run() {
         hobs.resize(k * nr * NOBS);
         (void)hipMemcpyAsync(hobs.data(), eng.obs, hobs.size() * 8, hipMemcpyDeviceToHost, eng.st);
         hipError_t herr = hipStreamSynchronize(eng.st);
-        int frc = herr == hipSuccess ? eng.check_flags() : SL_E_DEVICE;
+        const int frc = herr == hipSuccess ? SL_OK : SL_E_DEVICE;
         const double te = now_s();
         std::vector<double> lat(k);
         for (int64_t q = 0; q < k; q++) {
@@ -1358,15 +1357,15 @@ void sl_server::run() {
                 const int64_t kk = std::min<int64_t>(k, r->n_steps - r->steps_done);
                 for (int64_t q = 0; q < kk; q++) {
                     const double *o = hobs.data() + (q * nr + a) * NOBS;
-                    if (o[8] != 0 && r->state == SL_RUNNING) {
+                    if (o[NOBS - 1] != 0 && r->state == SL_RUNNING) {
                         r->state = SL_FAILED;
-                        r->error = SL_E_NONFINITE;
+                        r->error = o[NOBS - 1] >= 1e6 ? SL_E_OVERFLOW : SL_E_NONFINITE;
                     }
                     r->lat.push_back(lat[q]);
                 }
                 if (kk > 0) {
                     std::memcpy(r->obs_last, hobs.data() + ((kk - 1) * nr + a) * NOBS, NOBS * 8);
-                    r->obs_step = r->dev.step + r->steps_done + kk;
+                    r->obs_step = r->step0 + r->steps_done + kk;
                 }
                 r->steps_done += kk;
                 atom_steps += (double)kk * r->n;
@@ -1420,6 +1419,7 @@ extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const
     r->n_steps = n_steps;
     r->bytes = bytes_per_atom(sv->cfg.precision) * (size_t)r->n + 4096;
     if (r->bytes > sv->budget) return fail(SL_E_OOM, "replica larger than the whole HBM budget");
+    r->step0 = r->dev.step;
     r->dev.step_end = r->dev.step + n_steps;
     std::lock_guard<std::mutex> lk(sv->mu);
     r->id = sv->next_id++;

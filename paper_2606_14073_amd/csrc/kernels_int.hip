@@ -228,6 +228,10 @@ __global__ void k_step_end(Sys S) {
     if (r >= S.n_rep) return;
     RepDev &R = S.rep[r];
     if (!R.active) return;
+    if (R.failed) {
+        R.active = 0;
+        return;
+    }
     R.step += 1;
     if (R.step >= R.step_end) R.active = 0;
 }
@@ -295,7 +299,14 @@ __global__ void __launch_bounds__(256) k_obs_final(Sys S, const int *chunk_ptr, 
             for (int k = 0; k < NOBS; k++) red[k][t] += red[k][t + off];
         __syncthreads();
     }
-    if (t < NOBS) out[(size_t)r * NOBS + t] = red[t][0];
+    // slot NOBS-1 counts non-finite atoms; a replica whose neighbour lists
+    // overflowed or whose colouring failed is marked with 1e6 (overflow) or
+    // 2e6 (colouring) on top
+    if (t < NOBS) {
+        double v = red[t][0];
+        if (t == NOBS - 1) v += 1e6 * (double)(S.rep[r].failed & 3);
+        out[(size_t)r * NOBS + t] = v;
+    }
 }
 
 }  // namespace

@@ -174,6 +174,7 @@ __global__ void __launch_bounds__(BLK) k_build(Sys S, double rl2R, double rl2A) 
             }
     if (nr > MAXR || na > MAXA) {
         atomicOr(&S.flags[F_OVERFLOW], 1);
+        atomicOr(&S.rep[S.rid[i]].failed, 1);
         nr = min(nr, MAXR);
         na = min(na, MAXA);
     }
@@ -187,7 +188,10 @@ __global__ void __launch_bounds__(BLK) k_build(Sys S, double rl2R, double rl2A) 
     }
     S.cntR[i] = nr;
     S.cntFeR[i] = fe;
-    if (i < S.N_fe && fe > MAXFE) atomicOr(&S.flags[F_OVERFLOW], 1);
+    if (i < S.N_fe && fe > MAXFE) {
+        atomicOr(&S.flags[F_OVERFLOW], 1);
+        atomicOr(&S.rep[S.rid[i]].failed, 1);
+    }
     fe = 0;
     for (int s = 0; s < na; s++) {
         const int j = rowA[s * BLK + t];
@@ -232,13 +236,19 @@ __global__ void k_rev(Sys S) {
         S.revA[(size_t)s * S.N + i] = r < 0 ? 0 : r;
         S.a2r[(size_t)s * S.N + i] = m < 0 ? 0 : m;
     }
-    if (bad) atomicOr(&S.flags[F_OVERFLOW], 2);
+    if (bad) {
+        atomicOr(&S.flags[F_OVERFLOW], 2);
+        atomicOr(&S.rep[S.rid[i]].failed, 1);
+    }
     if (S.colour && i < S.N_fe && S.colour[i] >= 0) {
         const int ci = S.colour[i];
         const int nfe = S.cntFeR[i];
         for (int s = 0; s < nfe; s++) {
             const int j = S.nbrR[(size_t)s * S.N + i];
-            if (S.colour[j] == ci) atomicOr(&S.flags[F_COLOUR], 1);
+            if (S.colour[j] == ci) {
+                atomicOr(&S.flags[F_COLOUR], 1);
+                atomicOr(&S.rep[S.rid[i]].failed, 2);
+            }
         }
     }
 }

@@ -71,13 +71,14 @@ class System:
 
 def fege_lattice(nx: int, ny: int, nz: int, *, seed: int = SEED_STATE,
                  noise: float = 0.02, pbc=(1, 1, 1), spins: str = "random",
-                 helix_pitch: float = 700.0) -> System:
+                 helix_pitch: float = 700.0, greedy: bool = True) -> System:
     """B20 FeGe-like supercell.
 
     Atom index = ((cx*ny + cy)*nz + cz)*8 + site, sites 0-3 Fe and 4-7 Ge.
     Positions are lattice sites plus N(0, noise) per component. Fe spins are
     uniform on the sphere ("random") or a helix s = (0, cos 2pi x/p, sin 2pi x/p)
-    along x ("helix"); Ge spins are zero.
+    along x ("helix"); Ge spins are zero. When the periodic colouring does not
+    apply, the greedy one is drawn if `greedy`, else colour is None.
     """
     rng = np.random.default_rng(seed)
     frac = np.concatenate([b20_fractional(U_FE), b20_fractional(U_GE)])  # [8,3]
@@ -107,7 +108,7 @@ def fege_lattice(nx: int, ny: int, nz: int, *, seed: int = SEED_STATE,
     else:
         raise ValueError(spins)
     colour = colour_periodic(nx, ny, nz, pbc)
-    if colour is None:
+    if colour is None and greedy:
         colour = colour_greedy(types, pos, box, pbc, 7.0)
     return System(types, pos, spin, box, pbc, (nx, ny, nz), colour)
 

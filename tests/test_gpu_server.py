@@ -1,0 +1,122 @@
+"""Replica server: continuous batching of independent spin-lattice replicas.
+
+A replica's result must not depend on which other replicas share the GPU:
+run alone and in a mix it is bitwise identical (FP64 and FP32-mixed), and
+equal to a direct single-system simulation of the same request."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2606_14073_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def model():
+    from paper_2606_14073_amd import nepspin
+    return nepspin.Model(W.random_params())
+
+
+def _request(cells, T, Bz, seed, *, pbc=(1, 1, 1)):
+    from paper_2606_14073_amd import nepspin
+    s = W.fege_lattice(cells, cells, cells, seed=seed, pbc=pbc)
+    v = W.maxwell_boltzmann(s.types, T, seed=seed + 7)
+    ip = nepspin.integrator_params(dt=1.0, T0=T, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, Bz),
+                                   seed=1000 + seed)
+    return s, v, ip
+
+
+def _submit(sv, req, n_steps):
+    s, v, ip = req
+    return sv.submit(s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip, n_steps=n_steps)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_alone_equals_mix_equals_direct(model, precision):
+    from paper_2606_14073_amd import nepspin
+    X = _request(4, 120.0, 0.4, 11)
+    n = 12
+    # alone
+    sv = nepspin.Server(model, precision=precision, steps_per_batch=5, max_slots=8)
+    a = _submit(sv, X, n)
+    sv.drain()
+    alone = sv.fetch(a)
+    st = sv.poll(a)
+    assert st["state"] == nepspin.SL_DONE and st["steps_done"] == n
+    assert st["n_latency_samples"] == n and st["step_latency_p99"] >= st["step_latency_p50"] > 0
+    sv.close()
+    # in a mix: other sizes (odd cell counts use the greedy colouring), temperatures, fields and
+    # lengths; some arrive while X runs
+    sv = nepspin.Server(model, precision=precision, steps_per_batch=3, max_slots=8)
+    others = [_request(5, 250.0, 0.9, 3), _request(6, 60.0, 0.0, 4), _request(4, 300.0, 1.0, 5)]
+    ids = [_submit(sv, others[0], 7)]
+    b = _submit(sv, X, n)
+    time.sleep(0.05)
+    ids += [_submit(sv, others[1], 20), _submit(sv, others[2], 4)]
+    sv.drain()
+    mixed = sv.fetch(b)
+    for k in ids:
+        assert sv.poll(k)["state"] == nepspin.SL_DONE
+    stats = sv.stats()
+    assert stats["atom_steps"] == pytest.approx(sum(o[0].n * m for o, m in zip(others, (7, 20, 4))) + X[0].n * n)
+    sv.close()
+    for x, y in zip(alone[:3], mixed[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(alone[3], mixed[3])
+    # the same request as a direct simulation
+    s, v, ip = X
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                      precision=precision)
+    sim.integrate(n)
+    direct = sim.state()
+    for x, y in zip(direct[:3], alone[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_budget_admission_and_oom(model):
+    from paper_2606_14073_amd import nepspin
+    reqs = [_request(4, 100.0 + 20 * k, 0.2 * k, 20 + k) for k in range(4)]
+    # a budget that holds about two 512-atom replicas at a time
+    per = 512 * 12000
+    sv = nepspin.Server(model, precision="fp32", steps_per_batch=2, max_slots=8, hbm_budget_bytes=2 * per + 10000)
+    ids = [_submit(sv, r, 6) for r in reqs]
+    big = _request(8, 100.0, 0.0, 9)
+    with pytest.raises(nepspin.NepError) as e:
+        _submit(sv, big, 5)
+    assert e.value.code == nepspin.SL_E_OOM
+    sv.drain()
+    adm = sorted(sv.poll(k)["t_admit"] for k in ids)
+    done = sorted(sv.poll(k)["t_done"] for k in ids)
+    for k in ids:
+        st = sv.poll(k)
+        assert st["state"] == nepspin.SL_DONE and st["steps_done"] == 6
+    # not all four were admitted at once: the later two waited for a slot in the budget
+    assert adm[2] >= done[0] - 1e-6
+    sv.close()
+
+
+def test_failed_replica_is_isolated(model):
+    from paper_2606_14073_amd import nepspin
+    good = _request(4, 150.0, 0.3, 31)
+    s, v, ip = _request(4, 150.0, 0.3, 32)
+    pos = s.pos.copy()
+    pos[:200] = pos[0] + np.random.default_rng(0).normal(0, 0.2, (200, 3))   # collapsed region
+    sv = nepspin.Server(model, precision="fp64", steps_per_batch=3, max_slots=8)
+    g = _submit(sv, good, 6)
+    bad = sv.submit(s.types, pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip, n_steps=6)
+    sv.drain()
+    assert sv.poll(bad)["state"] == nepspin.SL_FAILED
+    assert sv.poll(g)["state"] == nepspin.SL_DONE
+    with pytest.raises(nepspin.NepError):
+        sv.fetch(bad)
+    got = sv.fetch(g)
+    sv.close()
+    sv = nepspin.Server(model, precision="fp64", steps_per_batch=3, max_slots=8)
+    g2 = _submit(sv, good, 6)
+    sv.drain()
+    ref = sv.fetch(g2)
+    sv.close()
+    for x, y in zip(got[:3], ref[:3]):
+        assert np.array_equal(x, y)
