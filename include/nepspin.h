@@ -56,8 +56,7 @@ typedef enum {
     SL_E_NONFINITE = -5,  /* NaN/Inf in the state of a replica              */
     SL_E_NOTFOUND = -6,   /* unknown replica id                             */
     SL_E_BUSY = -7,       /* replica not finished yet                       */
-    SL_E_OVERFLOW = -8,   /* neighbour list capacity exceeded, or two spins
-                             of one colour within coupling range            */
+    SL_E_OVERFLOW = -8,   /* neighbour list capacity exceeded               */
     SL_E_NOLIB = -9       /* no usable GPU / device code                    */
 } sl_status;
 
@@ -204,8 +203,14 @@ typedef struct {
 
 /* Create a simulation of one system: copies the state to the device and
  * evaluates F^0. vel[n][3] may be NULL (zero). colour[n]: colour class
- * (0..C-1) of each species-0 atom and -1 elsewhere, no two same-colour spins
- * within r_c^R + skin; NULL lets the library colour greedily.
+ * (0..C-1) of each species-0 atom and -1 elsewhere; NULL lets the library
+ * colour greedily (graph r < r_c^R + skin + 0.5 A, atoms in caller order).
+ * Two spins of one colour within r_c^R of each other would be updated at once
+ * although coupled: SL_E_INVALID. The colouring is kept like a neighbour list:
+ * whenever a list rebuild finds two same-colour spins within r_c^R + skin
+ * (not yet coupled, and unable to come within r_c^R before the next rebuild),
+ * the system stops after that step, is recoloured greedily from its current
+ * positions, and goes on; the steps stay exact, only the sweep order changes.
  * Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM, SL_E_OVERFLOW, SL_E_DEVICE. */
 int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel,
               const int32_t *colour, const sl_integrator_params *ip, sl_precision prec,
@@ -213,8 +218,12 @@ int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel,
 
 /* Advance n_steps steps. per_step_out[n_steps] receives the observables of
  * every step, or NULL. Errors: SL_E_NONFINITE (state not finite),
- * SL_E_OVERFLOW, SL_E_DEVICE. */
+ * SL_E_OVERFLOW, SL_E_INVALID (colouring), SL_E_DEVICE. */
 int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *per_step_out);
+
+/* Current colouring in caller order (colour[n], -1 on species 1; may be NULL)
+ * and the number of recolourings since creation (may be NULL). */
+int sl_get_colour(const sl_sim *s, int32_t *colour, int64_t *n_recolour);
 
 /* State in caller order: pos, vel, spin [n][3] (any may be NULL), step. */
 int sl_get_state(const sl_sim *s, double *pos, double *vel, double *spin, int64_t *step);

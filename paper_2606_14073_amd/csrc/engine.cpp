@@ -160,6 +160,8 @@ struct Replica {
     double obs_last[NOBS] = {0};
     int64_t obs_step = 0;
     size_t bytes = 0;
+    int64_t n_recolour = 0;                // colourings replaced since creation
+    bool need_recolour = false;            // paused on a colour conflict in the list shell
 };
 
 static size_t bytes_per_atom(sl_precision prec) {
@@ -686,7 +688,20 @@ struct Engine {
         if (rc) return rc;
         if (h[F_OVERFLOW] & 1) return fail(SL_E_OVERFLOW, "neighbour list capacity exceeded (more than 128 atoms within rc_R+skin, 64 within rc_A+skin or 64 spin neighbours)");
         if (h[F_OVERFLOW] & 2) return fail(SL_E_OVERFLOW, "asymmetric neighbour lists");
-        if (h[F_COLOUR]) return fail(SL_E_OVERFLOW, "two spins of the same colour are within coupling range");
+        return SL_OK;
+    }
+
+    // device records of the resident replicas (step counters, failure bits)
+    int read_reps(std::vector<RepDev> &out) {
+        out.resize(reps.size());
+        if (!reps.empty())
+            HIPCHK(hipMemcpyAsync(out.data(), rep, reps.size() * sizeof(RepDev), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return SL_OK;
+    }
+    int write_rep(const Replica *r, const RepDev &d) {
+        HIPCHK(hipMemcpyAsync(rep + r->slot, &d, sizeof(RepDev), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
         return SL_OK;
     }
 
@@ -848,6 +863,66 @@ static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int
     }
     return SL_OK;
 }
+
+// New greedy colouring of a resident replica from its current positions; the
+// pause bit is cleared and the replica re-activated. The caller re-lays out.
+static int recolour_replica(Engine &e, Replica *r) {
+    std::vector<double> p(3 * r->n);
+    int rc = e.download(r, p.data(), nullptr, nullptr);
+    if (rc) return rc;
+    std::vector<int32_t> types(r->n, 1);
+    for (int q : r->fe_idx) types[q] = 0;
+    sl_system_view v{};
+    v.n_atoms = r->n;
+    v.types = types.data();
+    v.pos = p.data();
+    for (int a = 0; a < 3; a++) {
+        v.box[a] = r->dev.box[a];
+        v.pbc[a] = r->dev.pbc[a];
+    }
+    std::vector<int> col;
+    if ((rc = greedy_colour(&v, r->dev.skin, col))) return rc;
+    r->ncol = 0;
+    for (int64_t q = 0; q < r->n_fe; q++) {
+        r->colour_fe[q] = col[r->fe_idx[q]];
+        r->ncol = std::max(r->ncol, r->colour_fe[q] + 1);
+    }
+    std::vector<RepDev> d;
+    if ((rc = e.read_reps(d))) return rc;
+    RepDev x = d[r->slot];
+    x.failed &= ~4;
+    x.active = x.step < x.step_end;
+    r->n_recolour++;
+    return e.write_rep(r, x);
+}
+
+// After a (re)layout: turn the replicas' failure bits into errors, recolour
+// those whose colouring conflicts inside the list shell, and lay out again.
+// bad[k] receives the status of replica k (SL_OK if it may run).
+static int settle_layout(Engine &e, std::vector<int> &bad, bool global_flags = true) {
+    for (int it = 0; it < 4; it++) {
+        int rc = global_flags ? e.check_flags() : SL_OK;
+        if (rc) return rc;
+        std::vector<RepDev> d;
+        if ((rc = e.read_reps(d))) return rc;
+        bad.assign(d.size(), SL_OK);
+        bool again = false;
+        for (size_t k = 0; k < d.size(); k++) {
+            if (d[k].failed & 1) bad[k] = SL_E_OVERFLOW;
+            else if (d[k].failed & 2) bad[k] = SL_E_INVALID;
+            else if (d[k].failed & 4) {
+                if ((rc = recolour_replica(e, e.reps[k]))) return rc;
+                again = true;
+            }
+        }
+        if (!again) return SL_OK;
+        std::vector<Replica *> same = e.reps;
+        if ((rc = e.set_layout(same))) return rc;
+    }
+    return fail(SL_E_INVALID, "recolouring did not settle");
+}
+
+static const char *colour_msg = "two spins of the same colour lie within rc_R of each other (invalid colouring)";
 
 static int make_replica(const sl_system_view *sys, const double *vel, const int32_t *colour,
                         const sl_integrator_params *ip, bool need_colour, Replica &r) {
@@ -1092,14 +1167,13 @@ struct sl_sim {
     Replica r;
 };
 
-static void fill_obs(const double *o, int64_t step, int64_t n_atoms, sl_observables *out) {
+static void fill_obs(const double *o, double nfe, int64_t step, int64_t n_atoms, sl_observables *out) {
     out->step = step;
     out->E_pot = o[0];
     out->E_kin = o[1];
     out->E_zeeman = o[2];
     out->T_lattice = n_atoms ? 2.0 * o[1] / (3.0 * n_atoms * KB) : 0.0;
     out->T_spin = o[4] != 0 ? o[3] / (2.0 * KB * o[4]) : 0.0;
-    const double nfe = o[9];
     for (int a = 0; a < 3; a++) out->M[a] = nfe > 0 ? o[5 + a] / nfe : 0.0;
 }
 
@@ -1116,7 +1190,10 @@ extern "C" int sl_create(const nep_model *m, const sl_system_view *sys, const do
     s->eng.prec = prec;
     s->eng.K_corr = ip->K_corr;
     if ((rc = s->eng.set_layout({&s->r}))) return rc;
-    if ((rc = s->eng.check_flags())) return rc;
+    std::vector<int> bad;
+    if ((rc = settle_layout(s->eng, bad))) return rc;
+    if (bad[0] == SL_E_INVALID) return fail(SL_E_INVALID, colour_msg);
+    if (bad[0]) return fail(bad[0], "neighbour list capacity exceeded");
     *out = s.release();
     return SL_OK;
 }
@@ -1127,15 +1204,13 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
     Engine &e = s->eng;
     const int64_t chunk = 256;
     std::vector<double> h(chunk * NOBS);
+    std::vector<RepDev> d;
     int rc;
     if ((rc = e.ensure_obs(chunk))) return rc;
-    int64_t step0 = 0;
-    {
-        RepDev d;
-        HIPCHK(hipMemcpy(&d, e.rep, sizeof(RepDev), hipMemcpyDeviceToHost));
-        step0 = d.step;
-    }
-    for (int64_t done = 0; done < n_steps; done += chunk) {
+    if ((rc = e.read_reps(d))) return rc;
+    int64_t step = d[0].step;
+    int64_t done = 0;
+    while (done < n_steps) {
         const int64_t k = std::min(chunk, n_steps - done);
         for (int64_t q = 0; q < k; q++) e.step(e.obs + q * NOBS);
         HIPCHK(hipGetLastError());
@@ -1143,14 +1218,39 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
         HIPCHK(hipStreamSynchronize(e.st));
         e.prof_collect();
         if ((rc = e.check_flags())) return rc;
-        for (int64_t q = 0; q < k; q++) {
-            double o[NOBS + 1];
-            std::memcpy(o, h.data() + q * NOBS, NOBS * 8);
-            o[9] = (double)s->r.n_fe;
-            if (per_step_out) fill_obs(o, step0 + done + q + 1, s->r.n, per_step_out + done + q);
-            if (o[8] != 0) return fail(SL_E_NONFINITE, "state became non-finite at step " + std::to_string(step0 + done + q + 1));
+        if ((rc = e.read_reps(d))) return rc;
+        const int64_t ran = d[0].step - step;       // steps completed in this chunk
+        for (int64_t q = 0; q < ran; q++) {
+            const double *o = h.data() + q * NOBS;
+            if (per_step_out) fill_obs(o, (double)s->r.n_fe, step + q + 1, s->r.n, per_step_out + done + q);
+            if (o[NOBS - 1] != 0) return fail(SL_E_NONFINITE, "state became non-finite at step " + std::to_string(step + q + 1));
+        }
+        done += ran;
+        step += ran;
+        if (d[0].failed & 1) return fail(SL_E_OVERFLOW, "neighbour list capacity exceeded");
+        if (d[0].failed & 2) return fail(SL_E_INVALID, colour_msg);
+        if (d[0].failed & 4) {
+            // a same-colour pair entered the list shell: new colouring, then go on
+            if ((rc = recolour_replica(e, &s->r))) return rc;
+            if ((rc = e.set_layout({&s->r}))) return rc;
+            std::vector<int> bad;
+            if ((rc = settle_layout(e, bad))) return rc;
+            if (bad[0]) return fail(bad[0], bad[0] == SL_E_INVALID ? colour_msg : "neighbour list capacity exceeded");
+        } else if (ran < k) {
+            return fail(SL_E_DEVICE, "replica stopped before its steps were done");
         }
     }
+    return SL_OK;
+}
+
+extern "C" int sl_get_colour(const sl_sim *s, int32_t *colour, int64_t *n_recolour) {
+    if (!s) return fail(SL_E_INVALID, "sim is NULL");
+    const Replica &r = s->r;
+    if (colour) {
+        for (int64_t q = 0; q < r.n; q++) colour[q] = -1;
+        for (int64_t q = 0; q < r.n_fe; q++) colour[r.fe_idx[q]] = r.colour_fe[q];
+    }
+    if (n_recolour) *n_recolour = r.n_recolour;
     return SL_OK;
 }
 
@@ -1187,7 +1287,10 @@ extern "C" int sl_set_state(sl_sim *s, const double *pos, const double *vel, con
     s->eng.reps.clear();
     int rc = s->eng.set_layout({&r});
     if (rc) return rc;
-    return s->eng.check_flags();
+    std::vector<int> bad;
+    if ((rc = settle_layout(s->eng, bad))) return rc;
+    if (bad[0]) return fail(bad[0], bad[0] == SL_E_INVALID ? colour_msg : "neighbour list capacity exceeded");
+    return SL_OK;
 }
 
 extern "C" int sl_profile_enable(sl_sim *s, unsigned mask) {
@@ -1302,19 +1405,36 @@ void sl_server::run() {
             }
             next = keep;
         }
-        if (changed || next != eng.reps) {
-            int rc = eng.set_layout(next);
+        // replicas paused on a colour conflict get a new colouring first
+        int rc = SL_OK;
+        for (Replica *r : next)
+            if (r->need_recolour && r->slot >= 0 && !rc) {
+                rc = recolour_replica(eng, r);
+                r->need_recolour = false;
+                changed = true;
+            }
+        if (!rc && (changed || next != eng.reps)) {
+            rc = eng.set_layout(next);
+            std::vector<int> bad;
+            if (!rc) rc = settle_layout(eng, bad, false);
             std::lock_guard<std::mutex> lk(mu);
             resident = next;
-            if (rc) {
-                for (Replica *r : next) {
-                    r->state = SL_FAILED;
-                    r->error = rc;
+            for (size_t a = 0; a < bad.size() && !rc; a++)
+                if (bad[a] && next[a]->state == SL_RUNNING) {
+                    next[a]->state = SL_FAILED;
+                    next[a]->error = bad[a];
                 }
-                worker_error = rc;
-                worker_msg = g_err;
-                continue;
+        }
+        if (rc) {
+            std::lock_guard<std::mutex> lk(mu);
+            resident = next;
+            for (Replica *r : next) {
+                r->state = SL_FAILED;
+                r->error = rc;
             }
+            worker_error = rc;
+            worker_msg = g_err;
+            continue;
         }
         // batched steps of every resident replica
         int64_t k = spb;
@@ -1336,7 +1456,9 @@ void sl_server::run() {
         hobs.resize(k * nr * NOBS);
         (void)hipMemcpyAsync(hobs.data(), eng.obs, hobs.size() * 8, hipMemcpyDeviceToHost, eng.st);
         hipError_t herr = hipStreamSynchronize(eng.st);
-        const int frc = herr == hipSuccess ? SL_OK : SL_E_DEVICE;
+        std::vector<RepDev> dv;
+        int frc = herr == hipSuccess ? SL_OK : SL_E_DEVICE;
+        if (!frc) frc = eng.read_reps(dv);
         const double te = now_s();
         std::vector<double> lat(k);
         for (int64_t q = 0; q < k; q++) {
@@ -1354,25 +1476,34 @@ void sl_server::run() {
             for (size_t a = 0; a < nr; a++) {
                 Replica *r = next[a];
                 if (r->state != SL_RUNNING) continue;
-                const int64_t kk = std::min<int64_t>(k, r->n_steps - r->steps_done);
+                if (frc) {
+                    r->state = SL_FAILED;
+                    r->error = frc;
+                    continue;
+                }
+                // steps this replica completed in the batch (it stops early on a
+                // failure or a colour conflict)
+                const int64_t kk = std::max<int64_t>(
+                    0, std::min<int64_t>(dv[a].step - (r->step0 + r->steps_done), r->n_steps - r->steps_done));
                 for (int64_t q = 0; q < kk; q++) {
                     const double *o = hobs.data() + (q * nr + a) * NOBS;
                     if (o[NOBS - 1] != 0 && r->state == SL_RUNNING) {
                         r->state = SL_FAILED;
-                        r->error = o[NOBS - 1] >= 1e6 ? SL_E_OVERFLOW : SL_E_NONFINITE;
+                        r->error = SL_E_NONFINITE;
                     }
                     r->lat.push_back(lat[q]);
                 }
+                if (r->state == SL_RUNNING && (dv[a].failed & 3)) {
+                    r->state = SL_FAILED;
+                    r->error = (dv[a].failed & 1) ? SL_E_OVERFLOW : SL_E_INVALID;
+                }
+                if (r->state == SL_RUNNING && (dv[a].failed & 4)) r->need_recolour = true;
                 if (kk > 0) {
                     std::memcpy(r->obs_last, hobs.data() + ((kk - 1) * nr + a) * NOBS, NOBS * 8);
                     r->obs_step = r->step0 + r->steps_done + kk;
                 }
                 r->steps_done += kk;
                 atom_steps += (double)kk * r->n;
-                if (frc) {
-                    r->state = SL_FAILED;
-                    r->error = frc;
-                }
             }
         }
     }
@@ -1465,10 +1596,7 @@ extern "C" int sl_replica_fetch(sl_server *sv, uint64_t id, double *pos, double 
     if (vel) std::memcpy(vel, r->vel.data(), 24 * r->n);
     if (spin) std::memcpy(spin, r->spin.data(), 24 * r->n);
     if (obs) {
-        double o[NOBS + 1];
-        std::memcpy(o, r->obs_last, NOBS * 8);
-        o[9] = (double)r->n_fe;
-        fill_obs(o, r->obs_step, r->n, obs);
+        fill_obs(r->obs_last, (double)r->n_fe, r->obs_step, r->n, obs);
     }
     return SL_OK;
 }

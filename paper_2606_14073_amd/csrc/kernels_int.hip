@@ -228,12 +228,13 @@ __global__ void k_step_end(Sys S) {
     if (r >= S.n_rep) return;
     RepDev &R = S.rep[r];
     if (!R.active) return;
-    if (R.failed) {
+    if (R.failed & 3) {      // list overflow or coupled same-colour spins: the step is void
         R.active = 0;
         return;
     }
     R.step += 1;
-    if (R.step >= R.step_end) R.active = 0;
+    // a replica waiting for a new colouring stops after this (exact) step
+    if (R.step >= R.step_end || (R.failed & 4)) R.active = 0;
 }
 
 // per-chunk partial sums of the observables (fixed tree), then per replica
@@ -299,14 +300,8 @@ __global__ void __launch_bounds__(256) k_obs_final(Sys S, const int *chunk_ptr, 
             for (int k = 0; k < NOBS; k++) red[k][t] += red[k][t + off];
         __syncthreads();
     }
-    // slot NOBS-1 counts non-finite atoms; a replica whose neighbour lists
-    // overflowed or whose colouring failed is marked with 1e6 (overflow) or
-    // 2e6 (colouring) on top
-    if (t < NOBS) {
-        double v = red[t][0];
-        if (t == NOBS - 1) v += 1e6 * (double)(S.rep[r].failed & 3);
-        out[(size_t)r * NOBS + t] = v;
-    }
+    // slot NOBS-1 counts non-finite atoms
+    if (t < NOBS) out[(size_t)r * NOBS + t] = red[t][0];
 }
 
 }  // namespace

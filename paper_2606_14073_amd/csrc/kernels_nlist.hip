@@ -215,7 +215,11 @@ __device__ inline int find_sorted(const int *nbr, int N, int row, int n, int key
 }
 
 // reverse slots (where i sits in j's list), angular->radial slot map, and the
-// colouring check: no two same-colour spins inside r_list
+// colouring check. A same-colour spin pair inside rc_R would be updated
+// concurrently by the sweep although coupled: the replica fails (bit 2). A
+// same-colour pair in the list shell (rc_R, rc_R + skin] is not coupled yet
+// and cannot come inside rc_R before the next rebuild, so the step stays
+// exact; the replica is paused at the end of the step for recolouring (bit 4).
 __global__ void k_rev(Sys S) {
     if (S.flags[F_REBUILD] == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,12 +247,20 @@ __global__ void k_rev(Sys S) {
     if (S.colour && i < S.N_fe && S.colour[i] >= 0) {
         const int ci = S.colour[i];
         const int nfe = S.cntFeR[i];
+        const RepDev &R = S.rep[S.rid[i]];
+        const d4 pi = S.pos[i];
+        int conflict = 0;
         for (int s = 0; s < nfe; s++) {
             const int j = S.nbrR[(size_t)s * S.N + i];
             if (S.colour[j] == ci) {
-                atomicOr(&S.flags[F_COLOUR], 1);
-                atomicOr(&S.rep[S.rid[i]].failed, 2);
+                double dx, dy, dz;
+                min_image(R, pi, S.pos[j], dx, dy, dz);
+                conflict |= dx * dx + dy * dy + dz * dz < RC_R * RC_R ? 2 : 4;
             }
+        }
+        if (conflict) {
+            atomicOr(&S.flags[F_COLOUR], 1);
+            atomicOr(&S.rep[S.rid[i]].failed, conflict);
         }
     }
 }

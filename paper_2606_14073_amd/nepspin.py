@@ -24,7 +24,7 @@ PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED, "bf16h": SL_FP32_BF16H}
 EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
            "sl_replica_submit", "sl_replica_poll", "sl_replica_fetch", "sl_server_drain", "sl_server_stats",
-           "sl_server_destroy", "sl_profile_enable", "sl_profile_read"]
+           "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour"]
 
 PROFILE_GROUPS = ["desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "gather", "couplings",
                   "sweep", "nlist", "integrate"]
@@ -114,6 +114,7 @@ def load():
         L.sl_server_destroy.argtypes = [P]
         L.sl_profile_enable.argtypes = [P, ct.c_uint]
         L.sl_profile_read.argtypes = [P, P, P]
+        L.sl_get_colour.argtypes = [P, P, ct.POINTER(I64)]
         _lib = L
     return _lib
 
@@ -249,6 +250,14 @@ class Sim:
         st = ct.c_int64()
         _check(load().sl_get_state(self.h, _p(pos), _p(vel), _p(spin), ct.byref(st)))
         return pos, vel, spin, st.value
+
+    def colour(self):
+        """Current colouring (caller order, -1 on species 1) and the number of
+        recolourings since creation."""
+        col = np.zeros(self.n, dtype=np.int32)
+        k = ct.c_int64()
+        _check(load().sl_get_colour(self.h, col.ctypes.data_as(ct.c_void_p), ct.byref(k)))
+        return col, k.value
 
     def profile(self, groups):
         """time the named kernel groups (PROFILE_GROUPS) with HIP events"""

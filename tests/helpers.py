@@ -54,3 +54,26 @@ def gpu_available():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def approaching_pair(s, d_lo=6.62, d_hi=6.9, speed=0.015):
+    """A colouring of system s (greedy at 6.6 A, so valid for lists up to
+    rc_R + skin = 6.5 A) and velocities that drive one same-colour spin pair,
+    first found at a distance in (d_lo, d_hi), head-on towards each other at
+    `speed` A/fs each; every other atom starts at rest. Returns (colour, vel,
+    (i, j))."""
+    from paper_2606_14073_amd import workload as W
+    col = W.colour_greedy(s.types, s.pos, s.box, s.pbc, 6.6)
+    fe = np.nonzero(s.types == 0)[0]
+    for i in fe:
+        d = min_image_delta(s.pos[fe], s.pos[i], s.box, s.pbc)
+        r = np.sqrt((d * d).sum(axis=1))
+        cand = np.nonzero((col[fe] == col[i]) & (r > d_lo) & (r < d_hi))[0]
+        if cand.size:
+            j = fe[cand[0]]
+            u = d[cand[0]] / r[cand[0]]
+            vel = np.zeros((s.n, 3))
+            vel[i] = speed * u
+            vel[j] = -speed * u
+            return col, vel, (int(i), int(j))
+    raise AssertionError("no same-colour pair in range")

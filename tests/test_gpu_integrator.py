@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2606_14073_amd import workload as W
-from tests.helpers import min_image_delta, rel_inf
+from tests.helpers import approaching_pair, min_image_delta, rel_inf
 
 pytestmark = pytest.mark.gpu
 
@@ -185,7 +185,40 @@ def test_bad_colouring_is_rejected(model):
     col[s.types == 0] = 0
     with pytest.raises(nepspin.NepError) as e:
         nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, colour=col, params=nepspin.integrator_params())
-    assert e.value.code == nepspin.SL_E_OVERFLOW
+    assert e.value.code == nepspin.SL_E_INVALID
+
+
+def test_recolouring_mid_run_matches_oracle(model, oracle):
+    """A same-colour spin pair driven into the list shell: the run stops after
+    that step, takes the greedy colouring of its current positions and goes on.
+    Every step matches the oracle run with the colouring the library used for
+    it, and the new colouring is the greedy one (radius rc_R + skin + 0.5)."""
+    from paper_2606_14073_amd import nepspin
+    kw = SCHEDULES["nve"]
+    s = W.config_small()
+    p = W.random_params()
+    col0, v, (i, j) = approaching_pair(s)
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=col0, params=_params(nepspin, **kw))
+    col, nrc = sim.colour()
+    assert nrc == 0 and np.array_equal(col, col0)
+    prev = sim.state()
+    worst = [0, 0, 0]
+    at = []
+    for k in range(30):
+        col_used, _ = sim.colour()
+        sim.integrate(1)
+        cur = sim.state()
+        e = _compare_step(oracle, s, p, col_used, prev, cur, kw)
+        worst = [max(a, b) for a, b in zip(worst, e)]
+        col_new, nrc_new = sim.colour()
+        if nrc_new != len(at):
+            at.append(k)
+            assert np.array_equal(col_new, W.colour_greedy(s.types, cur[0], s.box, s.pbc, 7.0))
+        prev = cur
+    print(f"recoloured after steps {at}; pair {i},{j}; worst per-step rel err pos {worst[0]:.2e} vel {worst[1]:.2e} "
+          f"spin {worst[2]:.2e}", flush=True)
+    assert len(at) >= 1
+    assert max(worst) <= TOL64
 
 
 def test_fp32_mixed_step_error(model, oracle):

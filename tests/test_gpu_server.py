@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2606_14073_amd import workload as W
+from tests.helpers import approaching_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -119,4 +120,30 @@ def test_failed_replica_is_isolated(model):
     ref = sv.fetch(g2)
     sv.close()
     for x, y in zip(got[:3], ref[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_recoloured_replica_equals_direct(model):
+    """A replica that must be recoloured mid-run (same-colour pair driven into
+    the list shell) finishes all its steps in the server, next to another
+    replica, and ends bitwise equal to the direct simulation."""
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    col, v, _ = approaching_pair(s)
+    ip = nepspin.integrator_params(dt=1.0, B0=(0, 0, 1.0))
+    n = 30
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=col, params=ip)
+    sim.integrate(n)
+    direct = sim.state()
+    assert sim.colour()[1] >= 1
+    sv = nepspin.Server(model, precision="fp64", steps_per_batch=4, max_slots=8)
+    other = _submit(sv, _request(4, 200.0, 0.5, 41), 25)
+    a = sv.submit(s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=col, params=ip, n_steps=n)
+    sv.drain()
+    st = sv.poll(a)
+    assert st["state"] == nepspin.SL_DONE and st["steps_done"] == n
+    assert sv.poll(other)["state"] == nepspin.SL_DONE
+    got = sv.fetch(a)
+    sv.close()
+    for x, y in zip(direct[:3], got[:3]):
         assert np.array_equal(x, y)
