@@ -610,11 +610,11 @@ struct Engine {
 
     // forward + backward at the current positions and the given spins
     template <typename real>
-    void forward(const ModelDev<real> &m, const Work<real> &w, const d4 *spins) {
+    void forward(const ModelDev<real> &m, const Work<real> &w, const d4 *spins, int mode = PASS_FULL) {
         const Sys S = sys();
-        { ProfScope p(this, 0); launch_desc_radial(S, m, w, spins, st); }
-        { ProfScope p(this, 1); launch_desc_angular(S, m, w, spins, st); }
-        { ProfScope p(this, 2); launch_mlp(S, m, w, st); }
+        { ProfScope p(this, 0); launch_desc_radial(S, m, w, spins, mode, st); }
+        { ProfScope p(this, 1); launch_desc_angular(S, m, w, spins, mode, st); }
+        { ProfScope p(this, 2); launch_mlp(S, m, w, mode, st); }
     }
 
     template <typename real>
@@ -647,7 +647,8 @@ struct Engine {
         const Sys S = sys();
         { ProfScope q(this, 9); launch_spin_prep(S, st); }
         for (int p = 0; p <= K_corr; p++) {
-            forward(m, w, spin_hat);
+            // every pass sits at the same mid positions: the structural terms of the first are reused
+            forward(m, w, spin_hat, p == 0 ? PASS_SPIN : PASS_SPIN_REUSE);
             { ProfScope q(this, 6); launch_assemble(S, m, w, st); }
             {
                 ProfScope q(this, 7);

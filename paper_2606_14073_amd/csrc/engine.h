@@ -54,12 +54,18 @@ struct Work {
 void launch_skin_check(const Sys &S, hipStream_t st);
 void launch_rebuild(const Sys &S, double r_listR, double r_listA, hipStream_t st);
 
+// forward-pass modes: the full evaluation, the spin step's first pass at the
+// mid positions, and its later passes at the same positions
+enum { PASS_FULL = 0, PASS_SPIN = 1, PASS_SPIN_REUSE = 2 };
+
 template <typename real>
-void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st);
+void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, int mode,
+                        hipStream_t st);
 template <typename real>
-void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st);
+void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, int mode,
+                         hipStream_t st);
 template <typename real>
-void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int mode, hipStream_t st);
 template <typename real>
 void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
 template <typename real>

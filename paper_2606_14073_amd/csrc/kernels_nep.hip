@@ -246,15 +246,21 @@ __device__ inline real dotc(const real *c, const real f[NB]) {
 
 // forward: per round, lanes stage eight neighbours of their atom (radial
 // functions g^A_n and (s_i.s_j) g^sa_n for all n, the 24 harmonics) in LDS,
-// then lane n accumulates A_nlm and B_nlm over the staged neighbours
+// then lane n accumulates A_nlm and B_nlm over the staged neighbours. B only
+// has spin-carrying pairs (spin-carrying centre, first phase).
+// Pass modes: PASS_FULL stores A (all atoms) and B (spin carriers) for the
+// backward pass; PASS_SPIN (spin carriers only) stores A for the coupling
+// assembly; PASS_SPIN_REUSE (same positions as the preceding PASS_SPIN)
+// takes A from it and only recomputes B and q^sa.
 template <typename real>
 __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restrict__ C, Work<real> W,
-                                                     const d4 *spin, int nbFe) {
+                                                     const d4 *spin, int nbFe, int mode) {
     __shared__ real tile[ANG_ATOMS * ANG_TS];
     __shared__ int smax[2];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
     const int i = atom_of_block(S, ANG_ATOMS, nbFe, slot, fe);
+    const bool reuse = mode == PASS_SPIN_REUSE;
     if (threadIdx.x == 0) smax[0] = smax[1] = 0;
     __syncthreads();
     int cnt = 0, nfe = 0;
@@ -280,7 +286,8 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
 #pragma unroll
     for (int m = 0; m < NLM; m++) A[m] = B[m] = 0;
     real *my = tile + slot * ANG_TS;
-    for (int part = 0; part < 2; part++) {
+    const int nparts = reuse ? 1 : 2;
+    for (int part = 0; part < nparts; part++) {
         const int tau = (fe ? 0 : 2) + part;
         const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
         const bool spins = fe && part == 0;
@@ -298,16 +305,16 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
                     r_and_inv(r2, r, ir);
                     real f[NB];
                     radial_basis(r, rc, f);
-                    real sig = 0;
                     if (spins) {
                         real sj[3];
                         load_spin(spin, j, sj);
-                        sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
-                    }
+                        const real sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
 #pragma unroll
-                    for (int nn = 0; nn < NA; nn++) {
-                        en[nn] = dotc(cA + nn * NB, f);
-                        en[NA + nn] = spins ? sig * dotc(cS + nn * NB, f) : real(0);
+                        for (int nn = 0; nn < NA; nn++) en[NA + nn] = sig * dotc(cS + nn * NB, f);
+                    }
+                    if (!reuse) {
+#pragma unroll
+                        for (int nn = 0; nn < NA; nn++) en[nn] = dotc(cA + nn * NB, f);
                     }
                     real Y[NLM];
                     harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
@@ -320,37 +327,60 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
             }
             __syncthreads();
             const int qn = min(8, e - (b + rd * 8));
-            for (int q = 0; q < qn; q++) {
-                const real *e2 = my + q * ANG_TW;
-                const real ga = e2[n], gs = e2[NA + n];
+            if (spins && !reuse) {
+                for (int q = 0; q < qn; q++) {
+                    const real *e2 = my + q * ANG_TW;
+                    const real ga = e2[n], gs = e2[NA + n];
 #pragma unroll
-                for (int m = 0; m < NLM; m++) {
-                    const real y = e2[2 * NA + m];
-                    A[m] += ga * y;
-                    B[m] += gs * y;
+                    for (int m = 0; m < NLM; m++) {
+                        const real y = e2[2 * NA + m];
+                        A[m] += ga * y;
+                        B[m] += gs * y;
+                    }
+                }
+            } else if (spins) {
+                for (int q = 0; q < qn; q++) {
+                    const real *e2 = my + q * ANG_TW;
+                    const real gs = e2[NA + n];
+#pragma unroll
+                    for (int m = 0; m < NLM; m++) B[m] += gs * e2[2 * NA + m];
+                }
+            } else {
+                for (int q = 0; q < qn; q++) {
+                    const real *e2 = my + q * ANG_TW;
+                    const real ga = e2[n];
+#pragma unroll
+                    for (int m = 0; m < NLM; m++) A[m] += ga * e2[2 * NA + m];
                 }
             }
             __syncthreads();
         }
     }
     if (i < 0 || lane >= NA) return;
+    real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+    real *q = W.q + (size_t)i * DP;
+    if (reuse) {
+#pragma unroll
+        for (int m = 0; m < NLM; m++) A[m] = ab[m];
+    }
     real qa[4] = {0, 0, 0, 0}, qs[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < NLM; m++) {
         qa[l_of_lm(m) - 1] += A[m] * A[m];
         qs[l_of_lm(m) - 1] += A[m] * B[m];
     }
-    real *q = W.q + (size_t)i * DP;
 #pragma unroll
     for (int l = 0; l < 4; l++) {
-        q[D_A + 4 * n + l] = qa[l];
+        if (!reuse) q[D_A + 4 * n + l] = qa[l];
         q[D_SA + 4 * n + l] = qs[l];
     }
-    real *ab = W.AB + ((size_t)i * NA + n) * NAB;
+    if (!reuse) {
 #pragma unroll
-    for (int m = 0; m < NLM; m++) {
-        ab[m] = A[m];
-        ab[NLM + m] = B[m];
+        for (int m = 0; m < NLM; m++) ab[m] = A[m];
+    }
+    if (fe && mode == PASS_FULL) {
+#pragma unroll
+        for (int m = 0; m < NLM; m++) ab[NLM + m] = B[m];
     }
 }
 
@@ -678,7 +708,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
             const int n = x / NLM, m = x - n * NLM, l = l_of_lm(m) - 1;
             const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
             const real fa = Fp[D_A + 4 * n + l], fs = Fp[D_SA + 4 * n + l];
-            Q[x] = real(2) * fa * ab[m] + fs * ab[NLM + m];
+            Q[x] = real(2) * fa * ab[m] + (fe ? fs * ab[NLM + m] : real(0));
             Q[NA * NLM + x] = fs * ab[m];
         }
     }
@@ -1010,25 +1040,33 @@ inline int nblk(int n, int b) { return (n + b - 1) / b; }
     const int ge = S.N - S.N_fe;                        \
     const int nb_fe = nblk(S.N_fe, per), nb_ge = nblk(ge, per);
 
+// spin-step passes (PASS_SPIN, PASS_SPIN_REUSE) cover the spin carriers only:
+// the frozen-Fp magnetic energy has no term on atoms without a spin
 template <typename real>
-void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st) {
+void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, int mode,
+                        hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(256)
-    hipLaunchKernelGGL(k_desc_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, spin, nb_fe);
+    const int nb = mode == PASS_FULL ? nb_fe + nb_ge : nb_fe;
+    if (nb) hipLaunchKernelGGL(k_desc_radial<real>, dim3(nb), dim3(256), 0, st, S, M, W, spin, nb_fe);
 }
 
 template <typename real>
-void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, hipStream_t st) {
+void launch_desc_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, const d4 *spin, int mode,
+                         hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(ANG_ATOMS)
-    hipLaunchKernelGGL(k_desc_angular<real>, dim3(nb_fe + nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, spin, nb_fe);
+    const int nb = mode == PASS_FULL ? nb_fe + nb_ge : nb_fe;
+    if (nb)
+        hipLaunchKernelGGL(k_desc_angular<real>, dim3(nb), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, spin, nb_fe, mode);
 }
 
 template <typename real>
-void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int mode, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(MLP_ATOMS)
-    hipLaunchKernelGGL(k_mlp<real>, dim3(nb_fe + nb_ge), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
+    const int nb = mode == PASS_FULL ? nb_fe + nb_ge : nb_fe;
+    if (nb) hipLaunchKernelGGL(k_mlp<real>, dim3(nb), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
 }
 
 template <typename real>
@@ -1061,10 +1099,10 @@ void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W,
 
 #define NEP_INST(real)                                                                                           \
     template void launch_desc_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, const d4 *, \
-                                           hipStream_t);                                                         \
+                                           int, hipStream_t);                                                    \
     template void launch_desc_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, const d4 *,\
-                                            hipStream_t);                                                        \
-    template void launch_mlp<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);        \
+                                            int, hipStream_t);                                                   \
+    template void launch_mlp<real>(const Sys &, const ModelDev<real> &, const Work<real> &, int, hipStream_t);   \
     template void launch_bwd_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t); \
     template void launch_bwd_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
     template void launch_gather<real>(const Sys &, const Work<real> &, hipStream_t);                             \
