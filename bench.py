@@ -90,6 +90,17 @@ def flops_per_launch(group, pc):
     return None
 
 
+def sweep_bytes_per_launch(pc, n_colours, real_bytes=8):
+    """Algorithmic HBM bytes of one colour-class launch of the spin sweep: per
+    spin its couplings inside rc_R (J, D, K, rhat and the neighbour index) and
+    the neighbours' spins, its self terms, own spin, noise, list entries, and
+    the spin it writes back."""
+    nfe = pc["N_fe"]
+    nc = pc["R_fefe"] / nfe                      # couplings per spin
+    per_spin = nc * (6 * real_bytes + 4 + 24) + 7 * real_bytes + 24 + 24 + 12 + 24
+    return per_spin * nfe / n_colours
+
+
 def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
     """Poisson arrivals of the serving request mix (cubic FeGe cells, N
     log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed."""
@@ -131,13 +142,17 @@ def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
                          for k, x in enumerate(st) if x["state"] != nepspin.SL_DONE]}
 
 
-def kernel_source_hash():
-    """Hash of the potential kernels' sources (their translation unit and the
-    headers it includes), to tell whether stored counters are stale."""
+KERNEL_SOURCE = {"k_sweep": "kernels_int.hip"}     # every other measured kernel is in kernels_nep.hip
+
+
+def kernel_source_hash(kernel="k_desc_angular<double>"):
+    """Hash of the translation unit that holds `kernel` and the headers it
+    includes, to tell whether stored counters are stale."""
     import hashlib
+    base = kernel.split("<")[0]
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_14073_amd", "csrc")
-    for f in ("kernels_nep.hip", "common.h", "engine.h"):
+    for f in (KERNEL_SOURCE.get(base, "kernels_nep.hip"), "common.h", "engine.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -145,7 +160,7 @@ def kernel_source_hash():
 def traffic_from_profile(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    if there is none or the kernel sources changed since it was taken."""
+    if there is none or the kernel's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -153,9 +168,10 @@ def traffic_from_profile(kernel):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    k = d.get("kernels", {}).get(kernel)
+    if not k or k.get("source_hash") != kernel_source_hash(kernel):
         return None
-    return d.get("kernels", {}).get(kernel, {}).get("bytes_per_launch")
+    return k.get("bytes_per_launch")
 
 
 def copy_calibration():
@@ -168,7 +184,7 @@ def copy_calibration():
     for _ in range(3):
         torch.neg(x, out=y)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "source_hash": kernel_source_hash()}))
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
 
 
 def main():
@@ -246,7 +262,17 @@ def main():
     kname = f"{KERNEL_NAME.get(dom, dom)}<double>"
     fl = flops_per_launch(dom, pc)
     ms_dom, nl_dom = prof.get(dom, (0.0, 0))
-    if fl is not None and nl_dom:
+    if dom == "sweep" and nl_dom:
+        # one profiled sweep = 2 x n_colours launches of k_sweep (ascending, descending)
+        ncol = int(s.colour.max()) + 1
+        nk = nl_dom * 2 * ncol
+        avg = ms_dom / nk
+        by = sweep_bytes_per_launch(pc, ncol)
+        ach = by / (avg * 1e-3) / 1e9
+        roofline = {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
+                    "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": traffic_from_profile(kname),
+                    "avg_launch_ms": round(avg, 5), "launches": nk, "bytes_per_launch": int(by)}
+    elif fl is not None and nl_dom:
         avg = ms_dom / nl_dom
         ach = fl / (avg * 1e-3) / 1e12
         roofline = {"kernel": kname, "bound": "mfma" if dom == "readout" else "alu",

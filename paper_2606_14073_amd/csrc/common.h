@@ -74,6 +74,31 @@ __device__ inline void min_image(const RepDev &R, const d4 &pi, const d4 &pj, do
     if (R.pbc[2]) dz -= R.box[2] * rint(dz * R.ibox[2]);
 }
 
+// The box of one replica in registers for neighbour loops: free axes carry a
+// zero edge and inverse edge, so the correction box * rint(d * ibox) is an
+// exact zero there and the loop needs neither branches nor reloads of the
+// replica record.
+struct Img {
+    double b[3], ib[3];
+};
+__device__ inline Img img_of(const RepDev &R) {
+    Img g;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        g.b[a] = R.pbc[a] ? R.box[a] : 0.0;
+        g.ib[a] = R.pbc[a] ? R.ibox[a] : 0.0;
+    }
+    return g;
+}
+__device__ inline void min_image(const Img &g, const d4 &pi, const d4 &pj, double &dx, double &dy, double &dz) {
+    dx = pj.x - pi.x;
+    dy = pj.y - pi.y;
+    dz = pj.z - pi.z;
+    dx -= g.b[0] * rint(dx * g.ib[0]);
+    dy -= g.b[1] * rint(dy * g.ib[1]);
+    dz -= g.b[2] * rint(dz * g.ib[2]);
+}
+
 template <typename real>
 __device__ inline real dcos(real x);
 template <>
@@ -138,10 +163,11 @@ template <typename real>
 __device__ inline void cutoff_fc(real r, real rc, real &fc, real &dfc);
 template <>
 __device__ inline void cutoff_fc<double>(double r, double rc, double &fc, double &dfc) {
+    const double irc = 1.0 / rc;    // rc is a constant at every call site: folded
     double sn, cs;
-    sin_cos_halfpi(PI * (r / rc - 0.5), sn, cs);
+    sin_cos_halfpi(PI * (r * irc - 0.5), sn, cs);
     fc = 0.5 * (1.0 - sn);
-    dfc = -0.5 * PI / rc * cs;
+    dfc = (-0.5 * PI * irc) * cs;
 }
 template <>
 __device__ inline void cutoff_fc<float>(float r, float rc, float &fc, float &dfc) {
@@ -173,7 +199,7 @@ template <typename real>
 __device__ inline void radial_basis(real r, real rc, real f[NB]) {
     real fc, dfc;
     cutoff_fc(r, rc, fc, dfc);
-    const real u = r / rc - real(1);
+    const real u = r * (real(1) / rc) - real(1);
     const real x = real(2) * u * u - real(1);
     real t0 = real(1), t1 = x;
     const real hf = real(0.5) * fc;
@@ -193,9 +219,9 @@ template <typename real>
 __device__ inline void radial_basis_d(real r, real rc, real f[NB], real df[NB]) {
     real fc, dfc;
     cutoff_fc(r, rc, fc, dfc);
-    const real u = r / rc - real(1);
+    const real u = r * (real(1) / rc) - real(1);
     const real x = real(2) * u * u - real(1);
-    const real dx = real(4) * u / rc;
+    const real dx = real(4) * u * (real(1) / rc);
     real t0 = real(1), t1 = x, d0 = real(0), d1 = real(1);
     f[0] = fc;
     df[0] = dfc;

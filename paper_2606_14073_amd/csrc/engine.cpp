@@ -167,7 +167,7 @@ struct Replica {
 static size_t bytes_per_atom(sl_precision prec) {
     const size_t rs = prec == SL_FP64 ? 8 : 4;
     size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
-    b += rs * (2 * DP + 1 + NA * NAB + 6 + 6 * MAXR + 4 * MAXA);
+    b += rs * (2 * DP + 1 + NA * NAB + 12 + 6 * MAXR + 4 * MAXA);
     b += (rs * (MAXFE * 9 + 8) + 4 * (MAXFE + 3)) / 2 + 64;
     return b;
 }
@@ -197,7 +197,8 @@ struct Engine {
     Work<double> w64{};
     Work<float> w32{};
     Chunk *chunks = nullptr;
-    int *chunk_ptr = nullptr, *col_idx = nullptr, *colpos = nullptr, *cpl_j = nullptr, *cpl_n = nullptr;
+    int *chunk_ptr = nullptr, *col_idx = nullptr, *colpos = nullptr, *col_rid = nullptr, *cpl_j = nullptr,
+        *cpl_n = nullptr;
     double *partial = nullptr, *obs = nullptr;
     size_t cap_obs = 0, cap_col = 0;
     int n_chunks = 0;
@@ -259,7 +260,7 @@ struct Engine {
         dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
         dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
         dfree(cell_of); dfree(cell_cnt); dfree(cell_start); dfree(cell_fill); dfree(cell_atoms);
-        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(colpos); dfree(cpl_j); dfree(cpl_n);
+        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(colpos); dfree(col_rid); dfree(cpl_j); dfree(cpl_n);
         dfree(partial); dfree(obs);
         if (work) (void)hipFree(work);
         work = nullptr;
@@ -285,6 +286,7 @@ struct Engine {
         S.colour = colour;
         S.col_idx = col_idx;
         S.colpos = colpos;
+        S.col_rid = col_rid;
         S.nbrR = nbrR; S.cntR = cntR; S.cntFeR = cntFeR; S.revR = revR;
         S.nbrA = nbrA; S.cntA = cntA; S.cntFeA = cntFeA; S.revA = revA; S.a2r = a2r;
         S.cell_of = cell_of; S.cell_cnt = cell_cnt; S.cell_start = cell_start; S.cell_fill = cell_fill;
@@ -317,6 +319,7 @@ struct Engine {
         w.pbR = take((size_t)MAXR * c * 6);
         w.pbA = take((size_t)MAXA * c * 4);
         w.ownR = take(c * 6);
+        w.ownA = take(c * 6);
         w.craw = take((size_t)MAXFE * cf * 3);
         w.cpl = take((size_t)MAXFE * cf * 6);
         w.selfc = take(cf * 8);
@@ -328,7 +331,7 @@ struct Engine {
     static size_t work_count(size_t c, size_t cf) {
         auto r = [](size_t n) { return (n + 63) & ~(size_t)63; };
         return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r((size_t)MAXR * c * 6) + r((size_t)MAXA * c * 4) +
-               r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
+               2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
     }
 
     int reserve(size_t n, size_t nfe, size_t ncell, size_t nrep, size_t nchunk) {
@@ -397,7 +400,9 @@ struct Engine {
         if (!col_idx || cap_col < cap_fe) {
             dfree(col_idx);
             dfree(colpos);
-            if ((rc = dalloc(&col_idx, cap_fe)) || (rc = dalloc(&colpos, cap_fe))) return rc;
+            dfree(col_rid);
+            if ((rc = dalloc(&col_idx, cap_fe)) || (rc = dalloc(&colpos, cap_fe)) || (rc = dalloc(&col_rid, cap_fe)))
+                return rc;
             cap_col = cap_fe;
         }
         return SL_OK;
@@ -548,7 +553,12 @@ struct Engine {
         if (!h_rep.empty()) HIPCHK(hipMemcpyAsync(rep, h_rep.data(), h_rep.size() * sizeof(RepDev), hipMemcpyHostToDevice, st));
         if (!h_chunks.empty()) HIPCHK(hipMemcpyAsync(chunks, h_chunks.data(), h_chunks.size() * sizeof(Chunk), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(chunk_ptr, h_cptr.data(), h_cptr.size() * 4, hipMemcpyHostToDevice, st));
-        if (!h_colidx.empty()) HIPCHK(hipMemcpyAsync(col_idx, h_colidx.data(), h_colidx.size() * 4, hipMemcpyHostToDevice, st));
+        std::vector<int> h_colrid(h_colidx.size());
+        for (size_t q = 0; q < h_colidx.size(); q++) h_colrid[q] = h_rid[h_colidx[q]];
+        if (!h_colidx.empty()) {
+            HIPCHK(hipMemcpyAsync(col_idx, h_colidx.data(), h_colidx.size() * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(col_rid, h_colrid.data(), h_colrid.size() * 4, hipMemcpyHostToDevice, st));
+        }
         // state
         std::vector<d4> buf;
         for (size_t k = 0; k < reps.size(); k++) {
@@ -650,11 +660,17 @@ struct Engine {
             // every pass sits at the same mid positions: the structural terms of the first are reused
             forward(m, w, spin_hat, p == 0 ? PASS_SPIN : PASS_SPIN_REUSE);
             { ProfScope q(this, 6); launch_assemble(S, m, w, st); }
+            if (p > 0) {
+                ProfScope q(this, 9);
+                launch_spin_restore(S, st);
+            }
             {
                 ProfScope q(this, 7);
-                if (p > 0) launch_spin_restore(S, st);
                 launch_sweep(S, w, col_ptr.data(), (int)col_ptr.size() - 1, st);
-                if (p < K_corr) launch_spin_mid(S, st);
+            }
+            if (p < K_corr) {
+                ProfScope q(this, 9);
+                launch_spin_mid(S, st);
             }
         }
     }

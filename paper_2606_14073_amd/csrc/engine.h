@@ -22,6 +22,7 @@ struct Sys {
     const int *colour;     // [N] colour on spin carriers, -1 elsewhere
     const int *col_idx;    // [N_fe] spin carriers grouped by colour
     const int *colpos;     // [N_fe] position of each spin carrier in col_idx
+    const int *col_rid;    // [N_fe] replica of each entry of col_idx
     int *nbrR, *cntR, *cntFeR, *revR;
     int *nbrA, *cntA, *cntFeA, *revA, *a2r;
     int *cell_of, *cell_cnt, *cell_start, *cell_fill, *cell_atoms;
@@ -39,9 +40,10 @@ struct ModelDev {
 template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
-    real *pbR;                  // radial pair records [MAXR][N][6]: dE_i/dd_ij, dE_i/ds_j
-    real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij
+    real *pbR;                  // radial pair records [MAXR][N][6]: dE_i/dd_ij, dE_i/ds_j at [slot of i in j's row][j]
+    real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise
     real *ownR;                 // [N][6]: radial-set sum_j dE_i/dd_ij, dE_i/ds_i
+    real *ownA;                 // [N][6]: angular-set sum_j dE_i/dd_ij, sum_j h_ij s_j
     real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij (atom order)
     real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat (colour-list order)
     real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i (colour-list order)

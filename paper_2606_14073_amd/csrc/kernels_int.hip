@@ -127,33 +127,77 @@ __device__ inline void sin_omc_taylor(double t, double &sn, double &omc) {
     omc = t2 * pc;
 }
 
+// 1/sqrt(x) for x > 0 in FP64: hardware estimate refined by two Newton steps
+__device__ inline double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
 // Eight lanes share a spin: they split the neighbour gather (couplings stored
 // in colour-list order, so a wavefront reads contiguous records), reduce, and
 // then run the midpoint iteration in lockstep; lane 0 stores the result.
+// Latency is what bounds a colour class, so the loads are issued in two
+// waves: everything indexed by the colour-list position (atom, replica,
+// coupling count, self terms, the first four coupling slots of each lane,
+// read whether or not they are in use and masked afterwards), then the
+// neighbours' spins, the spin itself, its noise and the replica record.
+constexpr int SWEEP_R0 = 4;    // coupling slots per lane loaded up front (32 per spin)
+
 template <typename real>
 __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count) {
     const int lane = threadIdx.x & 7;
     const int t = blockIdx.x * 32 + (threadIdx.x >> 3);
     if (t >= count) return;
     const int p = base + t;
-    const int i = S.col_idx[p];
-    const RepDev &R = S.rep[S.rid[i]];
-    if (!R.active) return;
     const size_t lf = S.N_fe;
+    // first wave of loads
+    const int i = S.col_idx[p];
+    const int r = S.col_rid[p];
     const int nc = W.cpl_n[p];
+    const real *o = W.selfc + (size_t)p * 8;
+    const double Axx = o[0], Ayy = o[1], Azz = o[2], Axy = o[3], Axz = o[4], Ayz = o[5], os = o[6];
+    int cj[SWEEP_R0];
+    double cv[SWEEP_R0][6];
+#pragma unroll
+    for (int k = 0; k < SWEEP_R0; k++) {
+        const size_t q = (size_t)(lane + 8 * k) * lf + p;
+        cj[k] = W.cpl_j[q];
+        const real *c = W.cpl + q * 6;
+#pragma unroll
+        for (int x = 0; x < 6; x++) cv[k][x] = c[x];
+    }
+    // second wave
+    const RepDev &R = S.rep[r];
+    const d4 e = S.eta[i];
+    const d4 s4 = S.spin[i];
     double hx = 0, hy = 0, hz = 0;
-    for (int s = lane; s < nc; s += 8) {
+    d4 sj[SWEEP_R0];
+#pragma unroll
+    for (int k = 0; k < SWEEP_R0; k++) sj[k] = S.spin[lane + 8 * k < nc ? cj[k] : i];
+#pragma unroll
+    for (int k = 0; k < SWEEP_R0; k++) {
+        if (lane + 8 * k >= nc) continue;
+        const double J = cv[k][0], D = cv[k][1], K = cv[k][2], rx = cv[k][3], ry = cv[k][4], rz = cv[k][5];
+        const double sr = sj[k].x * rx + sj[k].y * ry + sj[k].z * rz;
+        hx -= J * sj[k].x + D * (sj[k].y * rz - sj[k].z * ry) + K * sr * rx;
+        hy -= J * sj[k].y + D * (sj[k].z * rx - sj[k].x * rz) + K * sr * ry;
+        hz -= J * sj[k].z + D * (sj[k].x * ry - sj[k].y * rx) + K * sr * rz;
+    }
+    // spins with more than 8 * SWEEP_R0 couplings
+    for (int s = lane + 8 * SWEEP_R0; s < nc; s += 8) {
         const int j = W.cpl_j[(size_t)s * lf + p];
         const real *c = W.cpl + ((size_t)s * lf + p) * 6;
         const double J = c[0], D = c[1], K = c[2], rx = c[3], ry = c[4], rz = c[5];
-        const d4 sj = S.spin[j];
-        const double sr = sj.x * rx + sj.y * ry + sj.z * rz;
-        hx -= J * sj.x + D * (sj.y * rz - sj.z * ry) + K * sr * rx;
-        hy -= J * sj.y + D * (sj.z * rx - sj.x * rz) + K * sr * ry;
-        hz -= J * sj.z + D * (sj.x * ry - sj.y * rx) + K * sr * rz;
+        const d4 v = S.spin[j];
+        const double sr = v.x * rx + v.y * ry + v.z * rz;
+        hx -= J * v.x + D * (v.y * rz - v.z * ry) + K * sr * rx;
+        hy -= J * v.y + D * (v.z * rx - v.x * rz) + K * sr * ry;
+        hz -= J * v.z + D * (v.x * ry - v.y * rx) + K * sr * rz;
     }
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) {
@@ -161,20 +205,19 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         hy += __shfl_xor(hy, m);
         hz += __shfl_xor(hz, m);
     }
-    const real *o = W.selfc + (size_t)p * 8;
-    const double Axx = o[0], Ayy = o[1], Azz = o[2], Axy = o[3], Axz = o[4], Ayz = o[5], os = o[6];
+    if (!R.active) return;
     const double fr = ramp_frac(R), zs = R.mu_s * MUB;
-    const d4 e = S.eta[i];
     hx += zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr) + e.x;
     hy += zs * (R.B0[1] + (R.B1[1] - R.B0[1]) * fr) + e.y;
     hz += zs * (R.B0[2] + (R.B1[2] - R.B0[2]) * fr) + e.z;
     const double al = R.alpha, inv = 1.0 / (1.0 + al * al), tau = 0.5 * R.dt / HBAR;
-    const d4 s4 = S.spin[i];
+    const double tol = R.mid_tol;
+    const int cap = R.mid_cap;
     const double sx = s4.x, sy = s4.y, sz = s4.z;
     double yx = sx, yy = sy, yz = sz;
-    for (int it = 0; it < R.mid_cap; it++) {
+    for (int it = 0; it < cap; it++) {
         double mx = sx + yx, my = sy + yy, mz = sz + yz;
-        const double mn = 1.0 / sqrt(mx * mx + my * my + mz * mz);
+        const double mn = rsqrt_nr(mx * mx + my * my + mz * mz);
         mx *= mn;
         my *= mn;
         mz *= mn;
@@ -184,27 +227,27 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         const double wx = (h0 + al * (my * h2 - mz * h1)) * inv;
         const double wy = (h1 + al * (mz * h0 - mx * h2)) * inv;
         const double wz = (h2 + al * (mx * h1 - my * h0)) * inv;
-        const double wn = sqrt(wx * wx + wy * wy + wz * wz);
+        const double w2 = wx * wx + wy * wy + wz * wz;
         double nx, ny, nz;
-        if (wn == 0.0) {
+        if (w2 == 0.0) {
             nx = sx;
             ny = sy;
             nz = sz;
         } else {
-            const double th = wn * tau;
+            const double iw = rsqrt_nr(w2);
+            const double th = w2 * iw * tau;
             double sn, cs, omc;
-            if (fabs(th) < 1e-8) {
+            if (th < 1e-8) {
                 sn = th - th * th * th / 6.0;
                 omc = th * th / 2.0;
                 cs = 1.0 - omc;
-            } else if (fabs(th) <= 1.0) {
+            } else if (th <= 1.0) {
                 sin_omc_taylor(th, sn, omc);
                 cs = 1.0 - omc;
             } else {
                 sincos(th, &sn, &cs);
                 omc = 1.0 - cs;
             }
-            const double iw = 1.0 / wn;
             const double ux = wx * iw, uy = wy * iw, uz = wz * iw;
             const double us = ux * sx + uy * sy + uz * sz;
             nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
@@ -215,7 +258,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         yx = nx;
         yy = ny;
         yz = nz;
-        if (diff <= R.mid_tol) break;
+        if (diff <= tol) break;
     }
     if (lane == 0) {
         d4 out = {yx, yy, yz, 0.0};

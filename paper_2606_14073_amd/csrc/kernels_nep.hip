@@ -46,7 +46,7 @@ __device__ inline void load_spin(const d4 *sp, int j, real s[3]) {
 
 // displacement in FP64, then cast
 template <typename real>
-__device__ inline real geom(const Sys &S, const RepDev &R, const d4 &pi, int j, real d[3]) {
+__device__ inline real geom(const Sys &S, const Img &R, const d4 &pi, int j, real d[3]) {
     double dx, dy, dz;
     min_image(R, pi, S.pos[j], dx, dy, dz);
     d[0] = (real)dx;
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
     bool fe;
     const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
     if (i < 0) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc;
     const int cnt = S.cntR[i], nfe = S.cntFeR[i];
@@ -266,13 +266,13 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
     int cnt = 0, nfe = 0;
     d4 pi = {0, 0, 0, 0};
     real si[3] = {0, 0, 0};
-    const RepDev *R = nullptr;
+    Img R = {};
     if (i >= 0) {
         cnt = S.cntA[i];
         nfe = S.cntFeA[i];
         pi = S.pos[i];
         load_spin(spin, i, si);
-        R = &S.rep[S.rid[i]];
+        R = img_of(S.rep[S.rid[i]]);
         if (lane == 0) {
             atomicMax(&smax[0], nfe);
             atomicMax(&smax[1], cnt - nfe);
@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
             if (s < e) {
                 const int j = S.nbrA[s * ld + i];
                 real d[3];
-                const real r2 = geom(S, *R, pi, j, d);
+                const real r2 = geom(S, R, pi, j, d);
                 if (r2 < rc2) {
                     real r, ir;
                     r_and_inv(r2, r, ir);
@@ -420,12 +420,25 @@ typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 constexpr int MLP_WAVES = 8;           // 8 wavefronts x 16 atoms per workgroup
 constexpr int MLP_ATOMS = 16 * MLP_WAVES;
 constexpr int DPT = 112;               // descriptor rows padded to 7 tiles of 16
-constexpr int WLD = NH + 2;            // LDS row of W0^T
-constexpr int GLD = NH + 1;            // LDS row of the per-wave hidden tile
+// LDS row strides of W0^T and of the per-wave hidden tile. The MFMA operand
+// reads walk 16 rows (lanes i16) and 4 columns (lanes kq); a stride of 2
+// dwords mod 64 for 8-byte and 4 dwords mod 64 for 4-byte elements puts those
+// 64 reads on distinct banks.
+template <typename real>
+struct MlpLds;
+template <>
+struct MlpLds<double> {
+    static constexpr int LD = NH + 1;
+};
+template <>
+struct MlpLds<float> {
+    static constexpr int LD = NH + 4;
+};
 
 template <typename real>
 __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
     typedef typename MF<real>::acc_t acc_t;
+    constexpr int WLD = MlpLds<real>::LD, GLD = MlpLds<real>::LD;
     __shared__ real sW[DPT * WLD];
     __shared__ real sG[MLP_WAVES * 16 * GLD];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -479,10 +492,15 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
         }
     }
     if (!done) {
-        for (int ks = 0; ks < DP / 4; ks++) {
-            const real a = rv ? qrow[ks * 4 + kq] : real(0);
+        // this lane's 26 descriptor values, all loads in flight at once
+        real qa[DP / 4];
 #pragma unroll
-            for (int jt = 0; jt < 4; jt++) acc[jt] = MF<real>::mma(a, sW[(ks * 4 + kq) * WLD + jt * 16 + i16], acc[jt]);
+        for (int ks = 0; ks < DP / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
+#pragma unroll
+        for (int ks = 0; ks < DP / 4; ks++) {
+#pragma unroll
+            for (int jt = 0; jt < 4; jt++)
+                acc[jt] = MF<real>::mma(qa[ks], sW[(ks * 4 + kq) * WLD + jt * 16 + i16], acc[jt]);
         }
     }
     // activation, energy and the hidden-layer gradient
@@ -551,7 +569,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
     bool fe;
     const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
     if (i < 0) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc;
     const int cnt = S.cntR[i], nfe = S.cntFeR[i];
@@ -578,7 +596,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) {
-                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
                     continue;
                 }
                 real r, ir;
@@ -616,7 +634,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 hq[0] += gD * (rh[1] * si[2] - rh[2] * si[1]);
                 hq[1] += gD * (rh[2] * si[0] - rh[0] * si[2]);
                 hq[2] += gD * (rh[0] * si[1] - rh[1] * si[0]);
-                put_pair(W.pbR, s * ld + i, G, hq);
+                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, hq);
             }
         }
         {
@@ -628,7 +646,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) {
-                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
                     continue;
                 }
                 real r, ir;
@@ -648,7 +666,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                     h[x] += real(2) * gS * a * rh[x];
                     F[x] += G[x];
                 }
-                put_pair(W.pbR, s * ld + i, G, zero3);
+                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, zero3);
             }
         }
     } else {
@@ -661,7 +679,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) {
-                    put_pair(W.pbR, s * ld + i, zero3, zero3);
+                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
                     continue;
                 }
                 real r, ir;
@@ -673,7 +691,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 F[0] += G[0];
                 F[1] += G[1];
                 F[2] += G[2];
-                put_pair(W.pbR, s * ld + i, G, zero3);
+                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, zero3);
             }
         }
     }
@@ -714,13 +732,19 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
     }
     __syncthreads();
     if (i < 0) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
     const int cnt = S.cntA[i], nfe = S.cntFeA[i];
     const size_t ld = S.N;
     real si[3];
     load_spin(S.spin, i, si);
+    real Fo[3] = {0, 0, 0}, ho[3] = {0, 0, 0};     // own-side sums of this lane's pairs
+    // In-cutoff pairs go to the atom's lanes by their rank among in-cutoff
+    // pairs, so that the lane partial sums (and their rounding) depend on the
+    // positions only and not on which farther atoms the list happens to hold.
+    const int gbase = threadIdx.x & ~7;
+    int rank = 0;
 #pragma unroll 1
     for (int part = 0; part < 2; part++) {
         const int tau = (fe ? 0 : 2) + part;
@@ -728,23 +752,48 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
         const bool spins = fe && part == 0;
         const int b = part ? nfe : 0, e = part ? cnt : nfe;
 #pragma unroll 1
-        for (int s = b + lane; s < e; s += 8) {
-            const int j = S.nbrA[s * ld + i];
-            real d[3];
-            const real r2 = geom(S, R, pi, j, d);
-            real *rec = W.pbA + ((size_t)s * ld + i) * 4;
-            if (r2 >= rc2) {
-                rec[0] = rec[1] = rec[2] = rec[3] = 0;
-                continue;
+        for (int base = b; base < e; base += 8) {
+            const int s0 = base + lane;
+            int j0 = 0;
+            real d0[3] = {0, 0, 0}, r20 = rc2;
+            if (s0 < e) {
+                j0 = S.nbrA[s0 * ld + i];
+                r20 = geom(S, R, pi, j0, d0);
             }
+            const bool in = s0 < e && r20 < rc2;
+            // records of listed pairs beyond the cutoff are zero; each record
+            // goes where the partner's gather reads it
+            if (s0 < e && !in) {
+                real *z = W.pbA + ((size_t)S.revA[s0 * ld + i] * ld + j0) * 4;
+                z[0] = z[1] = z[2] = z[3] = 0;
+            }
+            const unsigned gm = (unsigned)(__ballot(in) >> gbase) & 0xffu;
+            const int c = __popc(gm);
+            const int q = (lane - rank) & 7;
+            int src = 0;
+            {
+                unsigned m = gm;
+                for (int x = 0; x < q && m; x++) m &= m - 1;
+                src = m ? __ffs(m) - 1 : 0;
+            }
+            const bool mine = q < c;
+            rank += c;
+            const int j = __shfl(j0, gbase + src);
+            const int s = __shfl(s0, gbase + src);
+            real d[3];
+            d[0] = __shfl(d0[0], gbase + src);
+            d[1] = __shfl(d0[1], gbase + src);
+            d[2] = __shfl(d0[2], gbase + src);
+            const real r2 = __shfl(r20, gbase + src);
+            if (!mine) continue;
+            real *rec = W.pbA + ((size_t)S.revA[s * ld + i] * ld + j) * 4;
             real r, ir;
             r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
             real f[NB], df[NB];
             radial_basis_d(r, rc, f, df);
-            real sig = 0;
+            real sig = 0, sj[3] = {0, 0, 0};
             if (spins) {
-                real sj[3];
                 load_spin(S.spin, j, sj);
                 sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
             }
@@ -787,12 +836,28 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
                 su1 += U * gy;
                 su2 += U * gz;
             }
-            rec[0] = sv * rh[0] + (su0 - sl * rh[0]) * ir;
-            rec[1] = sv * rh[1] + (su1 - sl * rh[1]) * ir;
-            rec[2] = sv * rh[2] + (su2 - sl * rh[2]) * ir;
+            const real G0 = sv * rh[0] + (su0 - sl * rh[0]) * ir;
+            const real G1 = sv * rh[1] + (su1 - sl * rh[1]) * ir;
+            const real G2 = sv * rh[2] + (su2 - sl * rh[2]) * ir;
+            rec[0] = G0;
+            rec[1] = G1;
+            rec[2] = G2;
             rec[3] = hs;
+            Fo[0] += G0;
+            Fo[1] += G1;
+            Fo[2] += G2;
+            ho[0] += hs * sj[0];
+            ho[1] += hs * sj[1];
+            ho[2] += hs * sj[2];
         }
     }
+    // own-side sums over the atom's eight lanes (fixed xor tree)
+#pragma unroll
+    for (int x = 0; x < 3; x++) {
+        Fo[x] = xor_sum8(Fo[x]);
+        ho[x] = xor_sum8(ho[x]);
+    }
+    if (lane == 0) put_pair(W.ownA, (size_t)i, Fo, ho);
 }
 
 // -------------------------------------------------------------------------
@@ -816,11 +881,19 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[2] = a[5];
     }
     const int nr = S.cntR[k], na = S.cntA[k];
+    {
+        const real *a = W.ownA + (size_t)k * 6;
+        F[0] += a[0];
+        F[1] += a[1];
+        F[2] += a[2];
+        h[0] += a[3];
+        h[1] += a[4];
+        h[2] += a[5];
+    }
+    // partner records sit in this atom's own slots: the reads are coalesced
 #pragma unroll 4
     for (int s = 0; s < nr; s++) {
-        const int j = S.nbrR[s * ld + k];
-        const int t = S.revR[s * ld + k];
-        const real *p = W.pbR + ((size_t)t * ld + j) * 6;
+        const real *p = W.pbR + ((size_t)s * ld + k) * 6;
         F[0] -= p[0];
         F[1] -= p[1];
         F[2] -= p[2];
@@ -830,20 +903,19 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     }
 #pragma unroll 4
     for (int s = 0; s < na; s++) {
-        const int j = S.nbrA[s * ld + k];
-        const int t = S.revA[s * ld + k];
-        const real *o = W.pbA + ((size_t)s * ld + k) * 4;
-        const real *p = W.pbA + ((size_t)t * ld + j) * 4;
-        F[0] += o[0] - p[0];
-        F[1] += o[1] - p[1];
-        F[2] += o[2] - p[2];
-        if (fe && j < S.N_fe) {
-            real sj[3];
-            load_spin(S.spin, j, sj);
-            const real w = o[3] + p[3];
-            h[0] += w * sj[0];
-            h[1] += w * sj[1];
-            h[2] += w * sj[2];
+        const real *p = W.pbA + ((size_t)s * ld + k) * 4;
+        F[0] -= p[0];
+        F[1] -= p[1];
+        F[2] -= p[2];
+        if (fe) {
+            const int j = S.nbrA[s * ld + k];
+            if (j < S.N_fe) {
+                real sj[3];
+                load_spin(S.spin, j, sj);
+                h[0] += p[3] * sj[0];
+                h[1] += p[3] * sj[1];
+                h[2] += p[3] * sj[2];
+            }
         }
     }
     d4 f4 = {(double)F[0], (double)F[1], (double)F[2], 0.0};
@@ -869,7 +941,7 @@ template <typename real>
 __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc;
     const int cnt = S.cntR[i], nfe_all = S.cntFeR[i], nfe = min(nfe_all, MAXFE);
@@ -961,7 +1033,7 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
     }
     __syncthreads();
     if (i >= S.N_fe) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
     const int nfe = S.cntFeA[i];
@@ -1002,7 +1074,7 @@ template <typename real>
 __global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
-    const RepDev &R = S.rep[S.rid[i]];
+    const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const int nfe = min(S.cntFeR[i], MAXFE);
     const size_t ld = S.N, lf = S.N_fe;
