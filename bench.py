@@ -55,38 +55,49 @@ def pair_counts(s):
         out[key] = 2 * len(pr)
         out[key + "_fefe"] = 2 * int(np.sum(fe[a] & fe[b]))
         out[key + "_fege"] = 2 * int(np.sum(fe[a] ^ fe[b]))     # ordered pairs with one Fe, one Ge
+        out[key + "_fe"] = out[key + "_fefe"] + out[key + "_fege"] // 2   # ordered pairs with an Fe centre
     out["N"] = s.n
     out["N_fe"] = int(fe.sum())
     return out
 
 
-def flops_per_launch(group, pc):
-    """Algorithmic FLOPs of one launch (FMA = 2), counted once per (centre,
-    neighbour) pair inside the channel's cutoff and once per atom; the
-    figures per pair are listed in the design doc."""
+def flops_per_step(group, pc, k_corr=1):
+    """Algorithmic FLOPs of one step's launches of a kernel group (FMA = 2),
+    counted once per (centre, neighbour) pair inside the channel's cutoff and
+    once per atom; the figures per pair are listed in the design doc. The
+    descriptor and read-out groups run one full pass, one spin-step pass over
+    the spin carriers and k_corr spin-step passes that reuse the structural
+    angular terms."""
     N, Nfe = pc["N"], pc["N_fe"]
     fe_centre_fe = pc["R_fefe"]             # spin pairs, radial set
     fe_centre_ge = pc["R_fege"] // 2        # Fe centre, Ge neighbour
+    if group == "desc_radial":
+        # per pair: geometry/basis 80 + radial accumulation 18; Fe-Fe: spin scalars 25 +
+        # four magnetic channels 72; Fe-Ge: single-ion 20; per atom contractions
+        fe_part = pc["R_fe"] * 98 + fe_centre_fe * 97 + fe_centre_ge * 20 + Nfe * 2 * 5 * 162
+        full = fe_part + (pc["R"] - pc["R_fe"]) * 98 + (N - Nfe) * 2 * 162
+        return full + (1 + k_corr) * fe_part
     if group == "desc_angular":
         # per pair: geometry/basis 75, g^A 126, harmonics 50, A accumulation 336;
-        # spin pairs: g^sa 133, B accumulation 336; per atom q^A, q^sa 672
-        return pc["A"] * 587 + pc["A_fefe"] * 469 + N * 672
+        # spin pairs: g^sa 133, B accumulation 336; per atom q^A, q^sa 672.
+        # Reuse passes: spin pairs only (geometry, harmonics, g^sa, B) and q^sa
+        full = pc["A"] * 587 + pc["A_fefe"] * 469 + N * 672
+        spin = pc["A_fe"] * 587 + pc["A_fefe"] * 469 + Nfe * 672
+        reuse = pc["A_fefe"] * (75 + 50 + 133 + 336) + Nfe * 336
+        return full + spin + k_corr * reuse
     if group == "bwd_angular":
         # per pair: geometry/basis+derivative 110, g^A and dg^A 252, harmonics and
         # gradients 150, per lm contraction 44 x 24; spin pairs: g^sa, dg^sa 252 and
         # 28 x 24; per atom QA, QS 1008
         return pc["A"] * 1568 + pc["A_fefe"] * 924 + N * 1008
-    if group == "desc_radial":
-        # per pair: geometry/basis 80 + radial accumulation 18; Fe-Fe: spin scalars 25 +
-        # four magnetic channels 72; Fe-Ge: single-ion 20; per atom contractions
-        return pc["R"] * 98 + fe_centre_fe * 97 + fe_centre_ge * 20 + Nfe * 2 * 5 * 162 + (N - Nfe) * 2 * 162
     if group == "bwd_radial":
         # per pair: geometry/basis+derivative 115, radial dg 18, record 20; Fe-Fe: 8 more
         # channel values 144 + force/field terms 90; Fe-Ge: 36 + 30; per atom contractions
         return pc["R"] * 153 + fe_centre_fe * 234 + fe_centre_ge * 66 + Nfe * 5 * 162 + N * 2 * 162
     if group == "readout":
         # 2 x (104 x 64) FMA per atom + tanh, energy and gradient
-        return N * (2 * 2 * 104 * 64 + 64 * 30)
+        per = 2 * 2 * 104 * 64 + 64 * 30
+        return N * per + (1 + k_corr) * Nfe * per
     return None
 
 
@@ -252,16 +263,19 @@ def main():
     pc = pair_counts(s)
     groups = {}
     for g, (ms, nl) in prof_all.items():
-        fl = flops_per_launch(g, pc)
-        if fl is None or nl == 0:
+        fs = flops_per_step(g, pc, kw["K_corr"])
+        if fs is None or nl == 0:
             continue
+        per_step = nl / n_prof
         avg = ms / nl
-        ach = fl / (avg * 1e-3) / 1e12
-        groups[g] = {"avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_launch": int(fl),
-                     "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4)}
+        ach = fs * n_prof / (ms * 1e-3) / 1e12
+        groups[g] = {"avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_step": int(fs),
+                     "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4),
+                     "launches_per_step": per_step}
     kname = f"{KERNEL_NAME.get(dom, dom)}<double>"
-    fl = flops_per_launch(dom, pc)
+    fs_dom = flops_per_step(dom, pc, kw["K_corr"])
     ms_dom, nl_dom = prof.get(dom, (0.0, 0))
+    fl = None if fs_dom is None or not nl_dom else fs_dom * K / nl_dom     # mean FLOPs per launch
     if dom == "sweep" and nl_dom:
         # one profiled sweep = 2 x n_colours launches of k_sweep (ascending, descending)
         ncol = int(s.colour.max()) + 1

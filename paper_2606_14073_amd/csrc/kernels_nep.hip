@@ -806,24 +806,28 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
                 dgS[n] = spins ? dotc(cS + n * NB, df) : real(0);
             }
             real sv = 0, sl = 0, hs = 0, su0 = 0, su1 = 0, su2 = 0;
-#pragma unroll 1
-            for (int m = 0; m < NLM; m++) {
+            // straight-line over the 24 harmonics; the register fence before
+            // each one keeps the compiler from evaluating all of them at once
+            static_for<NLM>([&](auto M) {
+                constexpr int m = decltype(M)::value;
                 real Y, gx, gy, gz;
-                // keep the harmonic inside the loop (no hoisting of all 24 cases)
                 real hx = rh[0], hy = rh[1], hz = rh[2];
-                asm volatile("" : "+v"(hx), "+v"(hy), "+v"(hz));
-                harmonic_dyn(m, hx, hy, hz, Y, gx, gy, gz);
+                int qo = slot * QSTRIDE;
+                asm volatile("" : "+v"(hx), "+v"(hy), "+v"(hz), "+v"(qo), "+v"(sv), "+v"(sl), "+v"(hs), "+v"(su0),
+                             "+v"(su1), "+v"(su2));
+                const real *Qm = sQ + qo;
+                harmonic_one<m>(hx, hy, hz, Y, gx, gy, gz);
                 real qa_g = 0, qa_dg = 0, qs_g = 0, qs_dg = 0;
 #pragma unroll
                 for (int n = 0; n < NA; n++) {
-                    const real qa = Q[n * NLM + m];
+                    const real qa = Qm[n * NLM + m];
                     qa_g += qa * gA[n];
                     qa_dg += qa * dgA[n];
                 }
                 if (spins) {
 #pragma unroll
                     for (int n = 0; n < NA; n++) {
-                        const real qs = Q[NA * NLM + n * NLM + m];
+                        const real qs = Qm[NA * NLM + n * NLM + m];
                         qs_g += qs * gS[n];
                         qs_dg += qs * dgS[n];
                     }
@@ -835,7 +839,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
                 su0 += U * gx;
                 su1 += U * gy;
                 su2 += U * gz;
-            }
+            });
             const real G0 = sv * rh[0] + (su0 - sl * rh[0]) * ir;
             const real G1 = sv * rh[1] + (su1 - sl * rh[1]) * ir;
             const real G2 = sv * rh[2] + (su2 - sl * rh[2]) * ir;
@@ -1051,15 +1055,14 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
 #pragma unroll
         for (int n = 0; n < NA; n++) gS[n] = dotc(cS + n * NB, f);
         real a = 0;
-        const real x = d[0] * ir, y = d[1] * ir, z = d[2] * ir;
-#pragma unroll 1
+        real Y[NLM];
+        harmonics(d[0] * ir, d[1] * ir, d[2] * ir, Y);
+#pragma unroll
         for (int m = 0; m < NLM; m++) {
-            real Y, gx, gy, gz;
-            harmonic_dyn(m, x, y, z, Y, gx, gy, gz);
             real w = 0;
 #pragma unroll
             for (int n = 0; n < NA; n++) w += P[n * NLM + m] * gS[n];
-            a += w * Y;
+            a += w * Y[m];
         }
         const int sr = S.a2r[s * ld + i];
         if (sr < MAXFE) W.craw[((size_t)sr * lf + i) * 3] += a;
