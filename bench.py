@@ -112,6 +112,51 @@ def sweep_bytes_per_launch(pc, n_colours, real_bytes=8):
     return per_spin * nfe / n_colours
 
 
+def sim_rate(model, nepspin, s, v, ip, precision, n_steps, warmup=2):
+    """atom-steps/s of n_steps on a resident system (clock around the steps only)."""
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                      precision=precision)
+    if warmup:
+        sim.integrate(warmup, observables=False)
+    t0 = time.perf_counter()
+    sim.integrate(n_steps, observables=False)
+    t1 = time.perf_counter()
+    sim.close()
+    return s.n * n_steps / (t1 - t0)
+
+
+def run_precision_form(model, nepspin, n_steps):
+    """96^3 cells = 7,077,888 atoms at 300 K: FP64, FP32-mixed and the BF16
+    variant side by side, with the errors of E, F, H against FP64."""
+    s = W.config_precision()
+    v = W.maxwell_boltzmann(s.types, 300.0)
+    ip = nepspin.integrator_params(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, seed=W.SEED_PHILOX)
+    out = {"workload": "FeGe B20 96x96x96 cells, 7,077,888 atoms, periodic, 300 K, K_corr 1", "steps": n_steps}
+    for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed"), ("bf16h", "bf16_hidden")):
+        out[key] = sim_rate(model, nepspin, s, v, ip, prec, n_steps)
+    ref = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, want=("E", "F", "H"))
+    errs = {}
+    for prec, key in (("fp32", "fp32_mixed"), ("bf16h", "bf16_hidden")):
+        got = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, precision=prec, want=("E", "F", "H"))
+        errs[key] = {"dE_per_atom_eV": abs(got["E"] - ref["E"]) / s.n,
+                     "F_rel_l2": float(np.linalg.norm(got["F"] - ref["F"]) / np.linalg.norm(ref["F"])),
+                     "H_rel_l2": float(np.linalg.norm(got["H"] - ref["H"]) / np.linalg.norm(ref["H"]))}
+    out["errors_vs_fp64"] = errs
+    return out
+
+
+def run_slab(model, nepspin, n_steps):
+    """256x256x8 cells = 4,194,304 atoms, free z, 700 A helix, T 150 -> 280 K
+    and B 0 -> 1 T over 20,000 steps, FP32-mixed."""
+    s = W.config_slab()
+    v = W.maxwell_boltzmann(s.types, 150.0)
+    ip = nepspin.integrator_params(dt=1.0, T0=150.0, T1=280.0, B0=(0, 0, 0), B1=(0, 0, 1.0), n_ramp=20000,
+                                   alpha_s=0.1, gamma_L=0.01, ensemble=1, seed=W.SEED_PHILOX)
+    return {"workload": "FeGe B20 slab 256x256x8 cells, 4,194,304 atoms, periodic x,y, free z, helix 700 A, "
+                        "T 150->280 K, B 0->1 T over 20,000 steps", "steps": n_steps,
+            "fp32_mixed": sim_rate(model, nepspin, s, v, ip, "fp32", n_steps)}
+
+
 def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
     """Poisson arrivals of the serving request mix (cubic FeGe cells, N
     log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed."""
@@ -206,6 +251,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 7.1M-atom precision form and the 4.2M slab")
+    ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--serving-requests", type=int, default=24)
     ap.add_argument("--serving-steps", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=1)
@@ -310,6 +357,15 @@ def main():
     if not args.no_serving:
         extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)
         print(f"serving: {extra['serving']}", file=sys.stderr, flush=True)
+
+    if not args.no_large:
+        # a model of their own: its evaluation engine (up to 120 GB) is released afterwards
+        big = nepspin.Model(params)
+        extra["precision_form"] = run_precision_form(big, nepspin, args.large_steps)
+        print(f"precision form: {extra['precision_form']}", file=sys.stderr, flush=True)
+        extra["slab"] = run_slab(big, nepspin, args.large_steps)
+        print(f"slab: {extra['slab']}", file=sys.stderr, flush=True)
+        big.close()
 
     cpu = None
     if not args.no_cpu:

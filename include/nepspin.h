@@ -145,8 +145,12 @@ typedef struct {
  *   energy_atom[n] : E_i (NEP part), or NULL
  *   force[n][3]    : F_i = -dE/dr_i, or NULL
  *   field[n][3]    : H_i = -dE/ds_i (+ mu_s mu_B B), species-0 rows; or NULL
+ * The model keeps the device work arrays of its last evaluation (about
+ * 17.3 KB per atom in FP64, 9.8 KB in FP32) for the next call of the same
+ * precision; another precision, a system more than eight times smaller or
+ * nep_model_destroy releases them. Calls on one model are serialised.
  * Errors: SL_E_INVALID (bad sizes/types), SL_E_BOX, SL_E_OVERFLOW (more than
- * 128 neighbours inside 6.5 A or 64 inside 5 A), SL_E_DEVICE. */
+ * 128 neighbours inside 6.5 A or 64 inside 5 A), SL_E_OOM, SL_E_DEVICE. */
 int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec,
                   double *energy, double *energy_atom, double *force, double *field,
                   const sl_exec *ex);

@@ -1078,6 +1078,13 @@ static int eval_common(const nep_model *mc, const sl_system_view *sys, sl_precis
     int rc = check_prec(prec);
     if (rc) return rc;
     if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r))) return rc;
+    // one evaluation engine per model: the work arrays of another precision,
+    // or of a system more than eight times larger, are released first
+    for (int q = 0; q < 3; q++)
+        if (m->eval_eng[q] && (q != (int)prec || (size_t)r.n * 8 < m->eval_eng[q]->cap)) {
+            delete m->eval_eng[q];
+            m->eval_eng[q] = nullptr;
+        }
     Engine *&e = m->eval_eng[prec];
     if (!e) {
         e = new Engine();
