@@ -40,9 +40,11 @@ struct ModelDev {
 template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
-    real *pbR;                  // radial pair records [MAXR][N][6]: dE_i/dd_ij, dE_i/ds_j at [slot of i in j's row][j]
+    real *pbR;                  // radial pair records [MAXR][N][3]: dE_i/dd_ij (radial, single-ion) at [slot of i in j's row][j]
+    real *pbM;                  // magnetic pair records [MAXFE][N_fe][6]: dE_i/dd_ij, dE_i/ds_j (exchange, DMI, anisotropic), likewise
+    real *ownM;                 // [N_fe][6]: magnetic-pair sum_j dE_i/dd_ij, dE_i/ds_i
     real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise
-    real *ownR;                 // [N][6]: radial-set sum_j dE_i/dd_ij, dE_i/ds_i
+    real *ownR;                 // [N][6]: radial and single-ion sum_j dE_i/dd_ij, dE_i/ds_i
     real *ownA;                 // [N][6]: angular-set sum_j dE_i/dd_ij, sum_j h_ij s_j
     real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij (atom order)
     real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat (colour-list order)

@@ -60,6 +60,8 @@ template <typename real>
 __device__ inline void contract(const real *c, const real *Fp, int nn, real C[NB]) {
 #pragma unroll
     for (int k = 0; k < NB; k++) C[k] = 0;
+    // once per atom: rolled, so the coefficients are loaded nine at a time
+#pragma unroll 1
     for (int n = 0; n < nn; n++) {
         const real f = Fp[n];
 #pragma unroll
@@ -88,8 +90,8 @@ __device__ inline real xor_sum8(real v) {
 // -------------------------------------------------------------------------
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Work<real> W, const d4 *spin,
-                                                     int nbFe) {
+__global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restrict__ C, Work<real> W,
+                                                     const d4 *spin, int nbFe) {
     bool fe;
     const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
     if (i < 0) return;
@@ -142,11 +144,11 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
             real r_ = 0, e_ = 0, d_ = 0, a_ = 0, s_ = 0;
 #pragma unroll
             for (int k = 0; k < NB; k++) {
-                r_ += M.cR[o + k] * FR[k];
-                e_ += M.cEX[o + k] * FE[k];
-                d_ += M.cDM[o + k] * FD[k];
-                a_ += M.cAN[o + k] * FA[k];
-                s_ += M.cSI[o + k] * FS[k];
+                r_ += (C + P_CR)[o + k] * FR[k];
+                e_ += (C + P_CEX)[o + k] * FE[k];
+                d_ += (C + P_CDM)[o + k] * FD[k];
+                a_ += (C + P_CAN)[o + k] * FA[k];
+                s_ += (C + P_CSI)[o + k] * FS[k];
             }
             qR[n] = r_;
             qE[n] = e_;
@@ -179,8 +181,8 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
             real r_ = 0, s_ = 0;
 #pragma unroll
             for (int k = 0; k < NB; k++) {
-                r_ += M.cR[o + k] * FR[k];
-                s_ += M.cSI[o + k] * FS[k];
+                r_ += (C + P_CR)[o + k] * FR[k];
+                s_ += (C + P_CSI)[o + k] * FS[k];
             }
             qR[n] += r_;
             qS[n] += s_;
@@ -208,7 +210,7 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, ModelDev<real> M, Wo
                 const int o = (tau * NR + n) * NB;
                 real r_ = 0;
 #pragma unroll
-                for (int k = 0; k < NB; k++) r_ += M.cR[o + k] * FR[k];
+                for (int k = 0; k < NB; k++) r_ += (C + P_CR)[o + k] * FR[k];
                 qR[n] += r_;
             }
         }
@@ -565,7 +567,19 @@ __device__ inline void put_pair(real *pb, size_t idx, const real G[3], const rea
 }
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
+__device__ inline void put3(real *pb, size_t idx, const real G[3]) {
+    real *p = pb + idx * 3;
+    p[0] = G[0];
+    p[1] = G[1];
+    p[2] = G[2];
+}
+
+// Structural part of the radial-set backward pass: the radial channel of
+// every pair and the single-ion term of spin-carrying centres, lane per atom.
+// Record of pair (i,j): dE_i/dd_ij (these channels), stored where j's gather
+// reads it. Own sums: sum_j dE_i/dd_ij and dE_i/ds_i (single-ion and onsite).
+template <typename real>
+__global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
     bool fe;
     const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
     if (i < 0) return;
@@ -584,73 +598,22 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
         h[0] = os2 * si[0];
         h[1] = os2 * si[1];
         h[2] = os2 * si[2];
-        {
-            real CR[NB], CE[NB], CD[NB], CA[NB], CS[NB];
-            contract(M.cR, Fp + D_R, NR, CR);
-            contract(M.cEX, Fp + D_EX, NR, CE);
-            contract(M.cDM, Fp + D_DM, NR, CD);
-            contract(M.cAN, Fp + D_AN, NR, CA);
-            contract(M.cSI, Fp + D_SI, NR, CS);
-            for (int s = 0; s < nfe; s++) {
-                const int j = S.nbrR[s * ld + i];
-                real d[3];
-                const real r2 = geom(S, R, pi, j, d);
-                if (r2 >= rc2) {
-                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
-                    continue;
-                }
-                real r, ir;
-            r_and_inv(r2, r, ir);
-                const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-                real f[NB], df[NB];
-                radial_basis_d(r, rc, f, df);
-                real sj[3];
-                load_spin(S.spin, j, sj);
-                const real dgR = dotk(CR, df);
-                const real gE = dotk(CE, f), dgE = dotk(CE, df);
-                const real gD = dotk(CD, f), dgD = dotk(CD, df);
-                const real gA = dotk(CA, f), dgA = dotk(CA, df);
-                const real gS = dotk(CS, f), dgS = dotk(CS, df);
-                const real ss = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
-                const real c[3] = {si[1] * sj[2] - si[2] * sj[1], si[2] * sj[0] - si[0] * sj[2],
-                                   si[0] * sj[1] - si[1] * sj[0]};
-                const real w = rh[0] * c[0] + rh[1] * c[1] + rh[2] * c[2];
-                const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
-                const real b = sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2];
-                const real radial = dgR + dgE * ss + dgD * w + dgA * a * b + dgS * a * a;
-                const real sjxr[3] = {sj[1] * rh[2] - sj[2] * rh[1], sj[2] * rh[0] - sj[0] * rh[2],
-                                      sj[0] * rh[1] - sj[1] * rh[0]};
-                real G[3], hq[3];
-                const real kd = gD * ir, ka = gA * ir, ks = real(2) * gS * a * ir;
-#pragma unroll
-                for (int x = 0; x < 3; x++) {
-                    const real pa = si[x] - a * rh[x], pb = sj[x] - b * rh[x];
-                    G[x] = radial * rh[x] + kd * (c[x] - w * rh[x]) + ka * (b * pa + a * pb) + ks * pa;
-                    h[x] += gE * sj[x] + gD * sjxr[x] + (gA * b + real(2) * gS * a) * rh[x];
-                    hq[x] = gE * si[x] + gA * a * rh[x];
-                    F[x] += G[x];
-                }
-                // dE_i/ds_j of the DMI term: g (rhat x s_i)
-                hq[0] += gD * (rh[1] * si[2] - rh[2] * si[1]);
-                hq[1] += gD * (rh[2] * si[0] - rh[0] * si[2]);
-                hq[2] += gD * (rh[0] * si[1] - rh[1] * si[0]);
-                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, hq);
-            }
-        }
-        {
+        for (int part = 0; part < 2; part++) {
             real CR[NB], CS[NB];
-            contract(M.cR + 1 * NR * NB, Fp + D_R, NR, CR);
-            contract(M.cSI + 1 * NR * NB, Fp + D_SI, NR, CS);
-            for (int s = nfe; s < cnt; s++) {
+            contract((C + P_CR) + part * NR * NB, Fp + D_R, NR, CR);
+            contract((C + P_CSI) + part * NR * NB, Fp + D_SI, NR, CS);
+            const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            for (int s = b; s < e; s++) {
                 const int j = S.nbrR[s * ld + i];
+                const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) {
-                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
+                    put3(W.pbR, dst, zero3);
                     continue;
                 }
                 real r, ir;
-            r_and_inv(r2, r, ir);
+                r_and_inv(r2, r, ir);
                 const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
@@ -666,24 +629,25 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                     h[x] += real(2) * gS * a * rh[x];
                     F[x] += G[x];
                 }
-                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, zero3);
+                put3(W.pbR, dst, G);
             }
         }
     } else {
         for (int part = 0; part < 2; part++) {
             real CR[NB];
-            contract(M.cR + (2 + part) * NR * NB, Fp + D_R, NR, CR);
+            contract((C + P_CR) + (2 + part) * NR * NB, Fp + D_R, NR, CR);
             const int b = part ? nfe : 0, e = part ? cnt : nfe;
             for (int s = b; s < e; s++) {
                 const int j = S.nbrR[s * ld + i];
+                const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
                 const real r2 = geom(S, R, pi, j, d);
                 if (r2 >= rc2) {
-                    put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, zero3, zero3);
+                    put3(W.pbR, dst, zero3);
                     continue;
                 }
                 real r, ir;
-            r_and_inv(r2, r, ir);
+                r_and_inv(r2, r, ir);
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
                 const real g = dotk(CR, df) * ir;
@@ -691,11 +655,83 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, ModelDev<real> M, Wor
                 F[0] += G[0];
                 F[1] += G[1];
                 F[2] += G[2];
-                put_pair(W.pbR, (size_t)S.revR[s * ld + i] * ld + j, G, zero3);
+                put3(W.pbR, dst, G);
             }
         }
     }
     put_pair(W.ownR, (size_t)i, F, h);
+}
+
+// Magnetic pair part of the radial-set backward pass: exchange, DMI and
+// anisotropic exchange over the spin-carrying neighbours of spin-carrying
+// centres, lane per atom. Record of pair (i,j): dE_i/dd_ij and dE_i/ds_j of
+// these channels at [slot of i in j's row][j] (spin carriers lead every row,
+// so that slot is below the spin-neighbour capacity of a valid list). Own
+// sums: sum_j dE_i/dd_ij and dE_i/ds_i.
+template <typename real>
+__global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__ C, Work<real> W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    const Img R = img_of(S.rep[S.rid[i]]);
+    const d4 pi = S.pos[i];
+    const real rc = (real)RC_R, rc2 = rc * rc;
+    const int nfe = min(S.cntFeR[i], MAXFE);
+    const size_t ld = S.N, lf = S.N_fe;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    const real zero3[3] = {0, 0, 0};
+    real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    real si[3];
+    load_spin(S.spin, i, si);
+    real CE[NB], CD[NB], CA[NB];
+    contract((C + P_CEX), Fp + D_EX, NR, CE);
+    contract((C + P_CDM), Fp + D_DM, NR, CD);
+    contract((C + P_CAN), Fp + D_AN, NR, CA);
+    for (int s = 0; s < nfe; s++) {
+        const int j = S.nbrR[s * ld + i];
+        const int t = S.revR[s * ld + i];
+        const size_t dst = (size_t)t * lf + j;
+        real d[3];
+        const real r2 = geom(S, R, pi, j, d);
+        if (r2 >= rc2) {
+            if (t < MAXFE) put_pair(W.pbM, dst, zero3, zero3);
+            continue;
+        }
+        real r, ir;
+        r_and_inv(r2, r, ir);
+        const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+        real f[NB], df[NB];
+        radial_basis_d(r, rc, f, df);
+        real sj[3];
+        load_spin(S.spin, j, sj);
+        const real gE = dotk(CE, f), dgE = dotk(CE, df);
+        const real gD = dotk(CD, f), dgD = dotk(CD, df);
+        const real gA = dotk(CA, f), dgA = dotk(CA, df);
+        const real ss = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
+        const real c[3] = {si[1] * sj[2] - si[2] * sj[1], si[2] * sj[0] - si[0] * sj[2],
+                           si[0] * sj[1] - si[1] * sj[0]};
+        const real w = rh[0] * c[0] + rh[1] * c[1] + rh[2] * c[2];
+        const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
+        const real b = sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2];
+        const real radial = dgE * ss + dgD * w + dgA * a * b;
+        const real sjxr[3] = {sj[1] * rh[2] - sj[2] * rh[1], sj[2] * rh[0] - sj[0] * rh[2],
+                              sj[0] * rh[1] - sj[1] * rh[0]};
+        real G[3], hq[3];
+        const real kd = gD * ir, ka = gA * ir;
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            const real pa = si[x] - a * rh[x], pb = sj[x] - b * rh[x];
+            G[x] = radial * rh[x] + kd * (c[x] - w * rh[x]) + ka * (b * pa + a * pb);
+            h[x] += gE * sj[x] + gD * sjxr[x] + gA * b * rh[x];
+            hq[x] = gE * si[x] + gA * a * rh[x];
+            F[x] += G[x];
+        }
+        // dE_i/ds_j of the DMI term: g (rhat x s_i)
+        hq[0] += gD * (rh[1] * si[2] - rh[2] * si[1]);
+        hq[1] += gD * (rh[2] * si[0] - rh[0] * si[2]);
+        hq[2] += gD * (rh[0] * si[1] - rh[1] * si[0]);
+        if (t < MAXFE) put_pair(W.pbM, dst, G, hq);
+    }
+    put_pair(W.ownM, (size_t)i, F, h);
 }
 
 // -------------------------------------------------------------------------
@@ -897,13 +933,31 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     // partner records sit in this atom's own slots: the reads are coalesced
 #pragma unroll 4
     for (int s = 0; s < nr; s++) {
-        const real *p = W.pbR + ((size_t)s * ld + k) * 6;
+        const real *p = W.pbR + ((size_t)s * ld + k) * 3;
         F[0] -= p[0];
         F[1] -= p[1];
         F[2] -= p[2];
-        h[0] += p[3];
-        h[1] += p[4];
-        h[2] += p[5];
+    }
+    if (fe) {
+        const size_t lf = S.N_fe;
+        const real *a = W.ownM + (size_t)k * 6;
+        F[0] += a[0];
+        F[1] += a[1];
+        F[2] += a[2];
+        h[0] += a[3];
+        h[1] += a[4];
+        h[2] += a[5];
+        const int nm = min(S.cntFeR[k], MAXFE);
+#pragma unroll 4
+        for (int s = 0; s < nm; s++) {
+            const real *p = W.pbM + ((size_t)s * lf + k) * 6;
+            F[0] -= p[0];
+            F[1] -= p[1];
+            F[2] -= p[2];
+            h[0] += p[3];
+            h[1] += p[4];
+            h[2] += p[5];
+        }
     }
 #pragma unroll 4
     for (int s = 0; s < na; s++) {
@@ -942,7 +996,7 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
 // -------------------------------------------------------------------------
 
 template <typename real>
-__global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M, Work<real> W) {
+__global__ void __launch_bounds__(256) k_assemble_radial(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
     const Img R = img_of(S.rep[S.rid[i]]);
@@ -954,10 +1008,10 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
     real Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
     {
         real CE[NB], CD[NB], CA[NB], CS[NB];
-        contract(M.cEX, Fp + D_EX, NR, CE);
-        contract(M.cDM, Fp + D_DM, NR, CD);
-        contract(M.cAN, Fp + D_AN, NR, CA);
-        contract(M.cSI, Fp + D_SI, NR, CS);
+        contract((C + P_CEX), Fp + D_EX, NR, CE);
+        contract((C + P_CDM), Fp + D_DM, NR, CD);
+        contract((C + P_CAN), Fp + D_AN, NR, CA);
+        contract((C + P_CSI), Fp + D_SI, NR, CS);
         for (int s = 0; s < nfe; s++) {
             const int j = S.nbrR[s * ld + i];
             real d[3];
@@ -986,7 +1040,7 @@ __global__ void __launch_bounds__(256) k_assemble_radial(Sys S, ModelDev<real> M
     }
     {
         real CS[NB];
-        contract(M.cSI + 1 * NR * NB, Fp + D_SI, NR, CS);
+        contract((C + P_CSI) + 1 * NR * NB, Fp + D_SI, NR, CS);
         for (int s = nfe_all; s < cnt; s++) {
             const int j = S.nbrR[s * ld + i];
             real d[3];
@@ -1123,7 +1177,7 @@ void launch_desc_radial(const Sys &S, const ModelDev<real> &M, const Work<real> 
     if (S.N == 0) return;
     NEP_SPLIT(256)
     const int nb = mode == PASS_FULL ? nb_fe + nb_ge : nb_fe;
-    if (nb) hipLaunchKernelGGL(k_desc_radial<real>, dim3(nb), dim3(256), 0, st, S, M, W, spin, nb_fe);
+    if (nb) hipLaunchKernelGGL(k_desc_radial<real>, dim3(nb), dim3(256), 0, st, S, M.cR, W, spin, nb_fe);
 }
 
 template <typename real>
@@ -1148,7 +1202,8 @@ template <typename real>
 void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(256)
-    hipLaunchKernelGGL(k_bwd_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M, W, nb_fe);
+    hipLaunchKernelGGL(k_bwd_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M.cR, W, nb_fe);
+    if (nb_fe) hipLaunchKernelGGL(k_bwd_mag<real>, dim3(nb_fe), dim3(256), 0, st, S, M.cR, W);
 }
 
 template <typename real>
@@ -1167,7 +1222,7 @@ void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st) {
 template <typename real>
 void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N_fe == 0) return;
-    hipLaunchKernelGGL(k_assemble_radial<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M, W);
+    hipLaunchKernelGGL(k_assemble_radial<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, ANG_ATOMS)), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_assemble_sym<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, W);
 }
