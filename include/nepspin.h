@@ -281,6 +281,11 @@ typedef struct {
  * not depend on which other replicas share the device. */
 int sl_server_create(const nep_model *m, const sl_server_config *cfg, sl_server **out);
 
+/* Device memory a replica of n_atoms is charged against the server's HBM
+ * budget in the given precision (work arrays, lists, state; the same figure
+ * sizes a single-system simulation). */
+size_t sl_replica_bytes(int64_t n_atoms, sl_precision prec);
+
 /* Queue a replica (inputs copied; colour may be NULL). ip->K_corr must equal
  * the server's. Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the
  * whole budget). */

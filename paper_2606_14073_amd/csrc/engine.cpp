@@ -172,6 +172,11 @@ static size_t bytes_per_atom(sl_precision prec) {
     return b;
 }
 
+extern "C" size_t sl_replica_bytes(int64_t n_atoms, sl_precision prec) {
+    if (n_atoms < 0) return 0;
+    return bytes_per_atom(prec) * (size_t)n_atoms + 4096;
+}
+
 struct Engine {
     nep_model *M = nullptr;
     sl_precision prec = SL_FP64;
@@ -333,8 +338,8 @@ struct Engine {
     static size_t work_count(size_t c, size_t cf) {
         auto r = [](size_t n) { return (n + 63) & ~(size_t)63; };
         return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r((size_t)MAXR * c * 3) + r((size_t)MAXFE * cf * 6) +
-               r(cf * 6) + r((size_t)MAXA * c * 4) +
-               2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) + r(cf * 8);
+               r(cf * 6) + r((size_t)MAXA * c * 4) + 2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) +
+               r(cf * 8);
     }
 
     int reserve(size_t n, size_t nfe, size_t ncell, size_t nrep, size_t nchunk) {
@@ -1575,7 +1580,7 @@ extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const
     int rc = make_replica(sys, vel, colour, ip, true, *r);
     if (rc) return rc;
     r->n_steps = n_steps;
-    r->bytes = bytes_per_atom(sv->cfg.precision) * (size_t)r->n + 4096;
+    r->bytes = sl_replica_bytes(r->n, sv->cfg.precision);
     if (r->bytes > sv->budget) return fail(SL_E_OOM, "replica larger than the whole HBM budget");
     r->step0 = r->dev.step;
     r->dev.step_end = r->dev.step + n_steps;

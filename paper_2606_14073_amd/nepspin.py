@@ -24,10 +24,15 @@ PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED, "bf16h": SL_FP32_BF16H}
 EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
            "sl_replica_submit", "sl_replica_poll", "sl_replica_fetch", "sl_server_drain", "sl_server_stats",
-           "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour"]
+           "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour", "sl_replica_bytes"]
 
 PROFILE_GROUPS = ["desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "gather", "couplings",
                   "sweep", "nlist", "integrate"]
+
+
+def replica_bytes(n_atoms, precision="fp64"):
+    """Device bytes a replica of n_atoms is charged against a server's HBM budget."""
+    return int(load().sl_replica_bytes(int(n_atoms), PRECISION[precision]))
 
 
 class NepError(RuntimeError):
@@ -115,6 +120,8 @@ def load():
         L.sl_profile_enable.argtypes = [P, ct.c_uint]
         L.sl_profile_read.argtypes = [P, P, P]
         L.sl_get_colour.argtypes = [P, P, ct.POINTER(I64)]
+        L.sl_replica_bytes.argtypes = [I64, ct.c_int]
+        L.sl_replica_bytes.restype = ct.c_size_t
         _lib = L
     return _lib
 

@@ -79,8 +79,8 @@ def test_alone_equals_mix_equals_direct(model, precision):
 def test_budget_admission_and_oom(model):
     from paper_2606_14073_amd import nepspin
     reqs = [_request(4, 100.0 + 20 * k, 0.2 * k, 20 + k) for k in range(4)]
-    # a budget that holds about two 512-atom replicas at a time
-    per = 512 * 12000
+    # a budget that holds two 512-atom replicas at a time
+    per = nepspin.replica_bytes(512, "fp32")
     sv = nepspin.Server(model, precision="fp32", steps_per_batch=2, max_slots=8, hbm_budget_bytes=2 * per + 10000)
     ids = [_submit(sv, r, 6) for r in reqs]
     big = _request(8, 100.0, 0.0, 9)
