@@ -282,11 +282,14 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
     }
     __syncthreads();
     const int n = lane < NA ? lane : NA - 1;
+    const int m0 = 3 * lane;                 // this lane's three harmonics, for every n
     const real rc = (real)RC_A, rc2 = rc * rc;
     const size_t ld = S.N;
-    real A[NLM], B[NLM];
+    real A[NA][3], B[NA][3];
 #pragma unroll
-    for (int m = 0; m < NLM; m++) A[m] = B[m] = 0;
+    for (int x = 0; x < NA; x++)
+#pragma unroll
+        for (int m = 0; m < 3; m++) A[x][m] = B[x][m] = 0;
     real *my = tile + slot * ANG_TS;
     const int nparts = reuse ? 1 : 2;
     for (int part = 0; part < nparts; part++) {
@@ -332,44 +335,82 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
             if (spins && !reuse) {
                 for (int q = 0; q < qn; q++) {
                     const real *e2 = my + q * ANG_TW;
-                    const real ga = e2[n], gs = e2[NA + n];
+                    const real y0 = e2[2 * NA + m0], y1 = e2[2 * NA + m0 + 1], y2 = e2[2 * NA + m0 + 2];
 #pragma unroll
-                    for (int m = 0; m < NLM; m++) {
-                        const real y = e2[2 * NA + m];
-                        A[m] += ga * y;
-                        B[m] += gs * y;
+                    for (int x = 0; x < NA; x++) {
+                        const real ga = e2[x], gs = e2[NA + x];
+                        A[x][0] += ga * y0;
+                        A[x][1] += ga * y1;
+                        A[x][2] += ga * y2;
+                        B[x][0] += gs * y0;
+                        B[x][1] += gs * y1;
+                        B[x][2] += gs * y2;
                     }
                 }
             } else if (spins) {
                 for (int q = 0; q < qn; q++) {
                     const real *e2 = my + q * ANG_TW;
-                    const real gs = e2[NA + n];
+                    const real y0 = e2[2 * NA + m0], y1 = e2[2 * NA + m0 + 1], y2 = e2[2 * NA + m0 + 2];
 #pragma unroll
-                    for (int m = 0; m < NLM; m++) B[m] += gs * e2[2 * NA + m];
+                    for (int x = 0; x < NA; x++) {
+                        const real gs = e2[NA + x];
+                        B[x][0] += gs * y0;
+                        B[x][1] += gs * y1;
+                        B[x][2] += gs * y2;
+                    }
                 }
             } else {
                 for (int q = 0; q < qn; q++) {
                     const real *e2 = my + q * ANG_TW;
-                    const real ga = e2[n];
+                    const real y0 = e2[2 * NA + m0], y1 = e2[2 * NA + m0 + 1], y2 = e2[2 * NA + m0 + 2];
 #pragma unroll
-                    for (int m = 0; m < NLM; m++) A[m] += ga * e2[2 * NA + m];
+                    for (int x = 0; x < NA; x++) {
+                        const real ga = e2[x];
+                        A[x][0] += ga * y0;
+                        A[x][1] += ga * y1;
+                        A[x][2] += ga * y2;
+                    }
                 }
             }
             __syncthreads();
         }
+    }
+    // regroup through LDS: lane n takes A_n and B_n over all 24 harmonics
+    real An[NLM], Bn[NLM];
+    if (!reuse) {
+#pragma unroll
+        for (int x = 0; x < NA; x++)
+#pragma unroll
+            for (int m = 0; m < 3; m++) my[x * NLM + m0 + m] = A[x][m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NLM; m++) An[m] = my[n * NLM + m];
+        __syncthreads();
+    }
+    if (fe) {
+#pragma unroll
+        for (int x = 0; x < NA; x++)
+#pragma unroll
+            for (int m = 0; m < 3; m++) my[x * NLM + m0 + m] = B[x][m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NLM; m++) Bn[m] = my[n * NLM + m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < NLM; m++) Bn[m] = 0;
     }
     if (i < 0 || lane >= NA) return;
     real *ab = W.AB + ((size_t)i * NA + n) * NAB;
     real *q = W.q + (size_t)i * DP;
     if (reuse) {
 #pragma unroll
-        for (int m = 0; m < NLM; m++) A[m] = ab[m];
+        for (int m = 0; m < NLM; m++) An[m] = ab[m];
     }
     real qa[4] = {0, 0, 0, 0}, qs[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int m = 0; m < NLM; m++) {
-        qa[l_of_lm(m) - 1] += A[m] * A[m];
-        qs[l_of_lm(m) - 1] += A[m] * B[m];
+        qa[l_of_lm(m) - 1] += An[m] * An[m];
+        qs[l_of_lm(m) - 1] += An[m] * Bn[m];
     }
 #pragma unroll
     for (int l = 0; l < 4; l++) {
@@ -378,11 +419,11 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
     }
     if (!reuse) {
 #pragma unroll
-        for (int m = 0; m < NLM; m++) ab[m] = A[m];
+        for (int m = 0; m < NLM; m++) ab[m] = An[m];
     }
     if (fe && mode == PASS_FULL) {
 #pragma unroll
-        for (int m = 0; m < NLM; m++) ab[NLM + m] = B[m];
+        for (int m = 0; m < NLM; m++) ab[NLM + m] = Bn[m];
     }
 }
 
@@ -441,8 +482,9 @@ template <typename real>
 __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
     typedef typename MF<real>::acc_t acc_t;
     constexpr int WLD = MlpLds<real>::LD, GLD = MlpLds<real>::LD;
+    constexpr bool f64 = sizeof(real) == 8;
     __shared__ real sW[DPT * WLD];
-    __shared__ real sG[MLP_WAVES * 16 * GLD];
+    __shared__ real sG[f64 ? 1 : MLP_WAVES * 16 * GLD];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool fe = (int)blockIdx.x < nbFe;
     const int t = fe ? 0 : 1;
@@ -458,6 +500,69 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
     const int arow = a0 + i16;
     const bool rv = arow < end;
     const real *qrow = W.q + (size_t)(rv ? arow : 0) * DP;
+    if constexpr (f64) {
+        // Transposed form: Z^T = W0 Q^T + b0 (hidden x atoms). With the FP64
+        // accumulator layout, element r of tile mt in lane l is Z^T[16 mt +
+        // l/16 + 4 r][l % 16], which is exactly the B operand lane l supplies
+        // for k-step ks = 4 mt + r of Fp^T = W0^T G^T: no transposition.
+        real qa[DP / 4];
+#pragma unroll
+        for (int ks = 0; ks < DP / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
+        acc_t z[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) z[mt][r] = M.b0[t * NH + 16 * mt + kq + 4 * r];
+#pragma unroll
+        for (int ks = 0; ks < DP / 4; ks++) {
+#pragma unroll
+            for (int mt = 0; mt < 4; mt++)
+                z[mt] = MF<real>::mma(sW[(ks * 4 + kq) * WLD + mt * 16 + i16], qa[ks], z[mt]);
+        }
+        real e = 0;
+        acc_t g[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int hh = 16 * mt + kq + 4 * r;
+                const real w = M.w1[t * NH + hh];
+                const real a = dtanh<real>(z[mt][r]);
+                e += w * a;
+                g[mt][r] = w * (real(1) - a * a);
+            }
+        e += __shfl_xor(e, 16);
+        e += __shfl_xor(e, 32);
+        if (kq == 0 && rv) W.Ei[arow] = M.b1[t] + e;
+        // Fp^T = W0^T G^T: A = W0^T tile from LDS, B = this lane's g; the
+        // seven descriptor tiles in two passes (4 + 3) to bound the registers
+        real *fp = W.Fp + (size_t)(rv ? arow : 0) * DP;
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            constexpr int H0 = 4;
+            const int d0 = half ? H0 : 0, nd = half ? DPT / 16 - H0 : H0;
+            acc_t f[H0];
+#pragma unroll
+            for (int x = 0; x < H0; x++) f[x] = acc_t{0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < NH / 4; ks++) {
+#pragma unroll
+                for (int x = 0; x < H0; x++)
+                    if (x < nd)
+                        f[x] = MF<real>::mma(sW[((d0 + x) * 16 + i16) * WLD + ks * 4 + kq], g[ks >> 2][ks & 3], f[x]);
+            }
+            if (rv) {
+#pragma unroll
+                for (int x = 0; x < H0; x++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int d = (d0 + x) * 16 + kq + 4 * r;
+                        if (x < nd && d < DP) fp[d] = f[x][r];
+                    }
+            }
+        }
+        return;
+    }
     acc_t acc[4];
 #pragma unroll
     for (int jt = 0; jt < 4; jt++) {
