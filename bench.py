@@ -324,9 +324,10 @@ def main():
     ms_dom, nl_dom = prof.get(dom, (0.0, 0))
     fl = None if fs_dom is None or not nl_dom else fs_dom * K / nl_dom     # mean FLOPs per launch
     if dom == "sweep" and nl_dom:
-        # one profiled sweep = 2 x n_colours launches of k_sweep (ascending, descending)
+        # one profiled sweep = 2 x n_colours - 1 launches of k_sweep (ascending, then
+        # descending; the last colour's two visits share one launch)
         ncol = int(s.colour.max()) + 1
-        nk = nl_dom * 2 * ncol
+        nk = nl_dom * (2 * ncol - 1)
         avg = ms_dom / nk
         by = sweep_bytes_per_launch(pc, ncol)
         ach = by / (avg * 1e-3) / 1e9

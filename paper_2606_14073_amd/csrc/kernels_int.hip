@@ -148,8 +148,11 @@ __device__ inline double rsqrt_nr(double x) {
 // neighbours' spins, the spin itself, its noise and the replica record.
 constexpr int SWEEP_R0 = 4;    // coupling slots per lane loaded up front (32 per spin)
 
+// turns = 2 takes the colour twice in a row (the end of the ascending and the
+// start of the descending pass): the neighbour field is the same for both
+// rotations, the second starts from the first one's result.
 template <typename real>
-__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count) {
+__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count, int turns) {
     const int lane = threadIdx.x & 7;
     const int t = blockIdx.x * 32 + (threadIdx.x >> 3);
     if (t >= count) return;
@@ -213,8 +216,14 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     const double al = R.alpha, inv = 1.0 / (1.0 + al * al), tau = 0.5 * R.dt / HBAR;
     const double tol = R.mid_tol;
     const int cap = R.mid_cap;
-    const double sx = s4.x, sy = s4.y, sz = s4.z;
+    double sx = s4.x, sy = s4.y, sz = s4.z;
     double yx = sx, yy = sy, yz = sz;
+    for (int turn = 0; turn < turns; turn++) {
+    if (turn) {
+        sx = yx;
+        sy = yy;
+        sz = yz;
+    }
     for (int it = 0; it < cap; it++) {
         double mx = sx + yx, my = sy + yy, mz = sz + yz;
         const double mn = rsqrt_nr(mx * mx + my * my + mz * mz);
@@ -259,6 +268,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         yy = ny;
         yz = nz;
         if (diff <= tol) break;
+    }
     }
     if (lane == 0) {
         d4 out = {yx, yy, yz, 0.0};
@@ -371,13 +381,17 @@ void launch_step_end(const Sys &S, hipStream_t st) {
     if (S.n_rep) hipLaunchKernelGGL(k_step_end, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S);
 }
 
+// colours 0, 1, .., C-1 and then C-1, .., 0; the two visits of colour C-1 are
+// one launch
 template <typename real>
 void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, int n_colours, hipStream_t st) {
     for (int pass = 0; pass < 2; pass++)
         for (int cc = 0; cc < n_colours; cc++) {
+            if (pass == 1 && cc == 0) continue;       // done as the second turn of the last ascending launch
             const int c = pass == 0 ? cc : n_colours - 1 - cc;
+            const int turns = (pass == 0 && cc == n_colours - 1) ? 2 : 1;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
-            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 32)), dim3(256), 0, st, S, W, b, n);
+            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 32)), dim3(256), 0, st, S, W, b, n, turns);
         }
 }
 

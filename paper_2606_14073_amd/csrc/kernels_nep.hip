@@ -55,6 +55,17 @@ __device__ inline real geom(const Sys &S, const Img &R, const d4 &pi, int j, rea
     return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
 }
 
+// displacement to an already loaded neighbour position
+template <typename real>
+__device__ inline real geom_p(const Img &R, const d4 &pi, const d4 &pj, real d[3]) {
+    double dx, dy, dz;
+    min_image(R, pi, pj, dx, dy, dz);
+    d[0] = (real)dx;
+    d[1] = (real)dy;
+    d[2] = (real)dz;
+    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
 // C[k] = sum_n Fp[n] c[n][k]  (coefficients wave-uniform)
 template <typename real>
 __device__ inline void contract(const real *c, const real *Fp, int nn, real C[NB]) {
@@ -110,18 +121,25 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
         real FR[NB], FE[NB], FD[NB], FA[NB], FS[NB];
 #pragma unroll
         for (int k = 0; k < NB; k++) FR[k] = FE[k] = FD[k] = FA[k] = FS[k] = 0;
+        // neighbour index two slots ahead, position and spin one slot ahead
+        int j1 = 0 < nfe ? S.nbrR[i] : 0;
+        int j2 = 1 < nfe ? S.nbrR[ld + i] : j1;
+        d4 p1 = S.pos[j1], v1 = spin[j1];
         for (int s = 0; s < nfe; s++) {
-            const int j = S.nbrR[s * ld + i];
+            const d4 pj = p1, vj = v1;
+            j1 = j2;
+            p1 = S.pos[j1];
+            v1 = spin[j1];
+            if (s + 2 < nfe) j2 = S.nbrR[(size_t)(s + 2) * ld + i];
             real d[3];
-            const real r2 = geom(S, R, pi, j, d);
+            const real r2 = geom_p(R, pi, pj, d);
             if (r2 >= rc2) continue;
             real r, ir;
             r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
             real f[NB];
             radial_basis(r, rc, f);
-            real sj[3];
-            load_spin(spin, j, sj);
+            const real sj[3] = {(real)vj.x, (real)vj.y, (real)vj.z};
             const real ss = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
             const real cx = si[1] * sj[2] - si[2] * sj[1], cy = si[2] * sj[0] - si[0] * sj[2],
                        cz = si[0] * sj[1] - si[1] * sj[0];
@@ -159,10 +177,17 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
         // non-magnetic neighbours: only the radial and single-ion channels survive
 #pragma unroll
         for (int k = 0; k < NB; k++) FR[k] = FS[k] = 0;
+        int j1_ = nfe < cnt ? S.nbrR[(size_t)(nfe) * ld + i] : 0;
+        int j2_ = nfe + 1 < cnt ? S.nbrR[(size_t)(nfe + 1) * ld + i] : j1_;
+        d4 p1_ = S.pos[j1_];
         for (int s = nfe; s < cnt; s++) {
-            const int j = S.nbrR[s * ld + i];
+            const int j = j1_;
+            const d4 pj_ = p1_;
+            j1_ = j2_;
+            p1_ = S.pos[j1_];
+            if (s + 2 < cnt) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
             real d[3];
-            const real r2 = geom(S, R, pi, j, d);
+            const real r2 = geom_p(R, pi, pj_, d);
             if (r2 >= rc2) continue;
             real r, ir;
             r_and_inv(r2, r, ir);
@@ -194,10 +219,17 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
 #pragma unroll
             for (int k = 0; k < NB; k++) FR[k] = 0;
             const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            int j1_ = b < e ? S.nbrR[(size_t)(b) * ld + i] : 0;
+            int j2_ = b + 1 < e ? S.nbrR[(size_t)(b + 1) * ld + i] : j1_;
+            d4 p1_ = S.pos[j1_];
             for (int s = b; s < e; s++) {
-                const int j = S.nbrR[s * ld + i];
+                const int j = j1_;
+                const d4 pj_ = p1_;
+                j1_ = j2_;
+                p1_ = S.pos[j1_];
+                if (s + 2 < e) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
                 real d[3];
-                const real r2 = geom(S, R, pi, j, d);
+                const real r2 = geom_p(R, pi, pj_, d);
                 if (r2 >= rc2) continue;
                 real f[NB], r, ir;
                 r_and_inv(r2, r, ir);
@@ -708,11 +740,18 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
             contract((C + P_CR) + part * NR * NB, Fp + D_R, NR, CR);
             contract((C + P_CSI) + part * NR * NB, Fp + D_SI, NR, CS);
             const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            int j1_ = b < e ? S.nbrR[(size_t)(b) * ld + i] : 0;
+            int j2_ = b + 1 < e ? S.nbrR[(size_t)(b + 1) * ld + i] : j1_;
+            d4 p1_ = S.pos[j1_];
             for (int s = b; s < e; s++) {
-                const int j = S.nbrR[s * ld + i];
+                const int j = j1_;
+                const d4 pj_ = p1_;
+                j1_ = j2_;
+                p1_ = S.pos[j1_];
+                if (s + 2 < e) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
                 const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
-                const real r2 = geom(S, R, pi, j, d);
+                const real r2 = geom_p(R, pi, pj_, d);
                 if (r2 >= rc2) {
                     put3(W.pbR, dst, zero3);
                     continue;
@@ -742,11 +781,18 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
             real CR[NB];
             contract((C + P_CR) + (2 + part) * NR * NB, Fp + D_R, NR, CR);
             const int b = part ? nfe : 0, e = part ? cnt : nfe;
+            int j1_ = b < e ? S.nbrR[(size_t)(b) * ld + i] : 0;
+            int j2_ = b + 1 < e ? S.nbrR[(size_t)(b + 1) * ld + i] : j1_;
+            d4 p1_ = S.pos[j1_];
             for (int s = b; s < e; s++) {
-                const int j = S.nbrR[s * ld + i];
+                const int j = j1_;
+                const d4 pj_ = p1_;
+                j1_ = j2_;
+                p1_ = S.pos[j1_];
+                if (s + 2 < e) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
                 const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
-                const real r2 = geom(S, R, pi, j, d);
+                const real r2 = geom_p(R, pi, pj_, d);
                 if (r2 >= rc2) {
                     put3(W.pbR, dst, zero3);
                     continue;
