@@ -330,21 +330,30 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
         const bool spins = fe && part == 0;
         const int b = part ? nfe : 0, e = part ? cnt : nfe;
         const int rounds = (smax[part] + 7) >> 3;
+        // this lane's neighbour index two rounds ahead, position and spin one round ahead
+        const int s0 = b + lane;
+        int jc = s0 < e ? S.nbrA[(size_t)s0 * ld + i] : 0;
+        int jn = s0 + 8 < e ? S.nbrA[(size_t)(s0 + 8) * ld + i] : jc;
+        d4 pc = S.pos[jc], vc = {0, 0, 0, 0};
+        if (spins) vc = spin[jc];
         for (int rd = 0; rd < rounds; rd++) {
             const int s = b + rd * 8 + lane;
+            const d4 pj = pc, vj = vc;
+            jc = jn;
+            pc = S.pos[jc];
+            if (spins) vc = spin[jc];
+            if (s + 16 < e) jn = S.nbrA[(size_t)(s + 16) * ld + i];
             real *en = my + lane * ANG_TW;
             if (s < e) {
-                const int j = S.nbrA[s * ld + i];
                 real d[3];
-                const real r2 = geom(S, R, pi, j, d);
+                const real r2 = geom_p(R, pi, pj, d);
                 if (r2 < rc2) {
                     real r, ir;
                     r_and_inv(r2, r, ir);
                     real f[NB];
                     radial_basis(r, rc, f);
                     if (spins) {
-                        real sj[3];
-                        load_spin(spin, j, sj);
+                        const real sj[3] = {(real)vj.x, (real)vj.y, (real)vj.z};
                         const real sig = si[0] * sj[0] + si[1] * sj[1] + si[2] * sj[2];
 #pragma unroll
                         for (int nn = 0; nn < NA; nn++) en[NA + nn] = sig * dotc(cS + nn * NB, f);
@@ -837,12 +846,21 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
     contract((C + P_CEX), Fp + D_EX, NR, CE);
     contract((C + P_CDM), Fp + D_DM, NR, CD);
     contract((C + P_CAN), Fp + D_AN, NR, CA);
+    // neighbour index two slots ahead, its position and spin one slot ahead
+    int j1_ = 0 < nfe ? S.nbrR[i] : 0;
+    int j2_ = 1 < nfe ? S.nbrR[ld + i] : j1_;
+    d4 p1_ = S.pos[j1_], v1_ = S.spin[j1_];
     for (int s = 0; s < nfe; s++) {
-        const int j = S.nbrR[s * ld + i];
+        const int j = j1_;
+        const d4 pj_ = p1_, vj_ = v1_;
+        j1_ = j2_;
+        p1_ = S.pos[j1_];
+        v1_ = S.spin[j1_];
+        if (s + 2 < nfe) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
         const int t = S.revR[s * ld + i];
         const size_t dst = (size_t)t * lf + j;
         real d[3];
-        const real r2 = geom(S, R, pi, j, d);
+        const real r2 = geom_p(R, pi, pj_, d);
         if (r2 >= rc2) {
             if (t < MAXFE) put_pair(W.pbM, dst, zero3, zero3);
             continue;
@@ -852,8 +870,7 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
         const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
         real f[NB], df[NB];
         radial_basis_d(r, rc, f, df);
-        real sj[3];
-        load_spin(S.spin, j, sj);
+        const real sj[3] = {(real)vj_.x, (real)vj_.y, (real)vj_.z};
         const real gE = dotk(CE, f), dgE = dotk(CE, df);
         const real gD = dotk(CD, f), dgD = dotk(CD, df);
         const real gA = dotk(CA, f), dgA = dotk(CA, df);
@@ -938,15 +955,21 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
         const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
         const bool spins = fe && part == 0;
         const int b = part ? nfe : 0, e = part ? cnt : nfe;
+        // this lane's neighbour index two rounds ahead, its position one round ahead
+        int jc = b + lane < e ? S.nbrA[(size_t)(b + lane) * ld + i] : 0;
+        int jn = b + lane + 8 < e ? S.nbrA[(size_t)(b + lane + 8) * ld + i] : jc;
+        d4 pc = S.pos[jc];
 #pragma unroll 1
         for (int base = b; base < e; base += 8) {
             const int s0 = base + lane;
-            int j0 = 0;
+            int j0 = jc;
+            const d4 pj = pc;
+            jc = jn;
+            pc = S.pos[jc];
+            if (s0 + 16 < e) jn = S.nbrA[(size_t)(s0 + 16) * ld + i];
             real d0[3] = {0, 0, 0}, r20 = rc2;
-            if (s0 < e) {
-                j0 = S.nbrA[s0 * ld + i];
-                r20 = geom(S, R, pi, j0, d0);
-            }
+            if (s0 < e) r20 = geom_p(R, pi, pj, d0);
+            else j0 = 0;
             const bool in = s0 < e && r20 < rc2;
             // records of listed pairs beyond the cutoff are zero; each record
             // goes where the partner's gather reads it
