@@ -793,6 +793,11 @@ typedef struct {
     int64_t n_ramp;
     uint64_t seed;
     int ensemble, K_corr, mid_cap, act, sequential;
+    /* self-consistent midpoint (sc_tol > 0): corrector passes are repeated
+     * until max over spins of |S^(p) - S^(p-1)| <= sc_tol, at most sc_max
+     * passes after the predictor; K_corr is then not used */
+    int sc_max;
+    double sc_tol;
 } or_step_params;
 
 typedef struct {
@@ -944,7 +949,9 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         }
         memcpy(Sn, spin, sizeof(double) * 3 * n);
         memcpy(Sh, spin, sizeof(double) * 3 * n);
-        for (int pc = 0; pc <= sp->K_corr; pc++) {
+        const int self_consistent = sp->sc_tol > 0;
+        const int last = self_consistent ? sp->sc_max : sp->K_corr;
+        for (int pc = 0; pc <= last; pc++) {
             /* Fp* at (R_mid, S_hat) */
             ctx_init(&C, n, type, pos, Sh, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
             forward_all(&C, q, Fp, Ei);
@@ -970,8 +977,17 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
                     }
                 }
             }
+            /* self-consistent midpoint: change of the spins since the previous pass */
+            double change = 0;
+            for (int i = 0; i < n; i++)
+                if (type[i] == 0)
+                    for (int a = 0; a < 3; a++) {
+                        const double d = fabs(C.spin[3 * i + a] - spin[3 * i + a]);
+                        if (d > change) change = d;
+                    }
             memcpy(spin, C.spin, sizeof(double) * 3 * n);
             ctx_free(&C);
+            if (self_consistent && pc >= 1 && change <= sp->sc_tol) break;
             /* S_hat = normalise((S^n + S^(p))/2) on spin-carrying atoms */
             for (int i = 0; i < n; i++) {
                 if (type[i] != 0) continue;

@@ -36,7 +36,8 @@ class StepParams(ct.Structure):
                 ("gammaL", ct.c_double), ("mu_s", ct.c_double), ("mid_tol", ct.c_double),
                 ("rcR", ct.c_double), ("rcA", ct.c_double), ("n_ramp", ct.c_int64),
                 ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
-                ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int)]
+                ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int), ("sc_max", ct.c_int),
+                ("sc_tol", ct.c_double)]
 
 
 class Obs(ct.Structure):
@@ -148,7 +149,7 @@ def normals(seed, atom, step, stream):
 
 def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
                 mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
-                K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A) -> StepParams:
+                K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30) -> StepParams:
     sp = StepParams()
     sp.dt = dt
     sp.T0 = T0
@@ -160,6 +161,8 @@ def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, ga
     sp.gammaL = gammaL
     sp.mu_s = mu_s
     sp.mid_tol = mid_tol
+    sp.sc_tol = sc_tol
+    sp.sc_max = sc_max
     sp.mid_cap = mid_cap
     sp.rcR = rcR
     sp.rcA = rcA

@@ -446,6 +446,37 @@ def test_reversibility_selfconsistent_midpoint(oracle):
     assert np.abs(spin - s.spin).max() <= 1e-10
 
 
+def test_selfconsistent_midpoint_stopping_rule(oracle):
+    """Self-consistent midpoint with a tolerance: a tolerance nothing can miss
+    stops after the first corrector (the K_corr = 1 step); a tolerance nothing
+    can meet stops at the cap (the K_corr = cap step); iterated to 1e-14 the
+    step is time-reversible for the full model."""
+    s = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
+    p = W.random_params()
+    box = np.array([500.0] * 3)
+    pos0 = s.pos + 100
+    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    kw = dict(dt=1.0, T0=200.0, alpha=0.1, gammaL=0.01, ensemble=1)
+    ref1 = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour, oracle.step_params(K_corr=1, **kw), 2)
+    got1 = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour,
+                      oracle.step_params(sc_tol=1e3, sc_max=9, **kw), 2)
+    for a, b in zip(ref1[:3], got1[:3]):
+        assert np.array_equal(a, b)
+    ref3 = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour, oracle.step_params(K_corr=3, **kw), 2)
+    got3 = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour,
+                      oracle.step_params(sc_tol=1e-300, sc_max=3, **kw), 2)
+    for a, b in zip(ref3[:3], got3[:3]):
+        assert np.array_equal(a, b)
+    n = 4
+    sp = oracle.step_params(dt=1.0, sc_tol=1e-14, sc_max=60)
+    pos, vel, spin, _, _ = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour, sp, n)
+    sp = oracle.step_params(dt=-1.0, sc_tol=1e-14, sc_max=60)
+    pos, vel, spin, _, _ = oracle.run(s.types, pos, vel, spin, box, s.pbc, p, s.colour, sp, n)
+    assert np.abs(pos - pos0).max() <= 1e-10
+    assert np.abs(vel - v0).max() <= 1e-10
+    assert np.abs(spin - s.spin).max() <= 1e-10
+
+
 def test_nve_energy_drift(oracle):
     s = W.fege_lattice(3, 3, 3)
     p = W.random_params()
