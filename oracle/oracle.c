@@ -798,11 +798,85 @@ typedef struct {
      * passes after the predictor; K_corr is then not used */
     int sc_max;
     double sc_tol;
+    /* accelerated variant (sc_depth > 0): Anderson mixing over the last
+     * sc_depth differences of residuals, Tikhonov-regularised by sc_reg times
+     * the mean diagonal of their Gram matrix */
+    int sc_depth;
+    double sc_reg;
 } or_step_params;
 
 typedef struct {
     double step, E_nep, E_kin, E_z, T_lat, T_spin, M[3];
+    double passes;   /* sweeps of the spin step (predictor + correctors)      */
+    double change;   /* max |g - x| of its last pass                         */
 } or_obs;
+
+/* Anderson mixing (type II) for a fixed point x = g(x) of dimension n.
+ * Given the current residual f = g(x_k) - x_k and the value g = g(x_k), and
+ * m columns of differences dF[a] = f_j - f_{j-1}, dG[a] = g_j - g_{j-1}
+ * (column a at dF + a*n), the coefficients minimise
+ * |f - sum_a gam_a dF[a]|^2 + lam |gam|^2, lam = reg * trace(dF^T dF) / m,
+ * and the next iterate is x_{k+1} = g - sum_a gam_a dG[a]. The normal
+ * equations are solved by Cholesky; without a positive definite system (no
+ * differences, or a pivot below 1e-13 of its diagonal entry: a column in the
+ * span of the others, possible with reg = 0) the step is the plain one,
+ * x_{k+1} = g. Returns the number of columns used (0 or m). */
+int or_anderson_mix(int n, int m, const double *dF, const double *dG, const double *f, const double *g,
+                    double reg, double *x_next, double *gam_out) {
+    double G[8][8], r[8], L[8][8], y[8], gam[8];
+    int used = 0;
+    if (m > 8) m = 8;
+    for (int a = 0; a < m; a++) {
+        for (int b = 0; b < m; b++) {
+            double acc = 0;
+            for (int i = 0; i < n; i++) acc += dF[(size_t)a * n + i] * dF[(size_t)b * n + i];
+            G[a][b] = acc;
+        }
+        double acc = 0;
+        for (int i = 0; i < n; i++) acc += dF[(size_t)a * n + i] * f[i];
+        r[a] = acc;
+    }
+    double tr = 0;
+    for (int a = 0; a < m; a++) tr += G[a][a];
+    if (m > 0 && tr > 0) {
+        const double lam = reg * tr / m;
+        int ok = 1;
+        for (int a = 0; a < m && ok; a++) {
+            for (int b = 0; b <= a; b++) {
+                double v = G[a][b] + (a == b ? lam : 0.0);
+                for (int c = 0; c < b; c++) v -= L[a][c] * L[b][c];
+                if (a == b) {
+                    /* a column (numerically) in the span of the earlier ones */
+                    if (!(v > 1e-13 * (G[a][a] + lam))) { ok = 0; break; }
+                    L[a][a] = sqrt(v);
+                } else {
+                    L[a][b] = v / L[b][b];
+                }
+            }
+        }
+        if (ok) {
+            for (int a = 0; a < m; a++) {
+                double v = r[a];
+                for (int c = 0; c < a; c++) v -= L[a][c] * y[c];
+                y[a] = v / L[a][a];
+            }
+            for (int a = m - 1; a >= 0; a--) {
+                double v = y[a];
+                for (int c = a + 1; c < m; c++) v -= L[c][a] * gam[c];
+                gam[a] = v / L[a][a];
+            }
+            used = m;
+        }
+    }
+    for (int a = 0; a < m; a++)
+        if (gam_out) gam_out[a] = used ? gam[a] : 0.0;
+    for (int i = 0; i < n; i++) {
+        double v = g[i];
+        for (int a = 0; a < used; a++) v -= gam[a] * dG[(size_t)a * n + i];
+        x_next[i] = v;
+    }
+    return used;
+}
 
 /* field of the frozen-Fp magnetic energy on spin i, split into the part that
  * does not involve s_i (bilinear terms with neighbour spins) and the part
@@ -905,6 +979,17 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
     double *Sh = malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *eta = calloc(3 * (size_t)(n + 1), sizeof(double));
     double *snew = malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    /* self-consistent iteration: the iterate x (end-of-step spins whose
+     * midpoint the pass uses) and, for the accelerated variant, the history */
+    const int depth = sp->sc_tol > 0 && sp->sc_depth > 0 ? (sp->sc_depth < 8 ? sp->sc_depth : 8) : 0;
+    int nfe_all = 0;
+    for (int i = 0; i < n; i++) nfe_all += type[i] == 0;
+    const size_t nv = 3 * (size_t)nfe_all + 1;
+    double *X = malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    double *fk = malloc(sizeof(double) * nv), *gk = malloc(sizeof(double) * nv);
+    double *fprev = malloc(sizeof(double) * nv), *gprev = malloc(sizeof(double) * nv);
+    double *xnew = malloc(sizeof(double) * nv);
+    double *dF = malloc(sizeof(double) * nv * (depth + 1)), *dG = malloc(sizeof(double) * nv * (depth + 1));
     double dt = sp->dt;
     for (int i = 0; i < n; i++)
         if (type[i] != 0) spin[3 * i] = spin[3 * i + 1] = spin[3 * i + 2] = 0.0;
@@ -949,8 +1034,11 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         }
         memcpy(Sn, spin, sizeof(double) * 3 * n);
         memcpy(Sh, spin, sizeof(double) * 3 * n);
+        memcpy(X, spin, sizeof(double) * 3 * n);   /* x^(0) = S^n: the predictor */
         const int self_consistent = sp->sc_tol > 0;
         const int last = self_consistent ? sp->sc_max : sp->K_corr;
+        int passes = 0, ncols = 0;
+        double change = 0;
         for (int pc = 0; pc <= last; pc++) {
             /* Fp* at (R_mid, S_hat) */
             ctx_init(&C, n, type, pos, Sh, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
@@ -977,22 +1065,56 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
                     }
                 }
             }
-            /* self-consistent midpoint: change of the spins since the previous pass */
-            double change = 0;
+            passes = pc + 1;
+            /* residual of the pass: g - x, with g the swept spins (for the
+             * plain iteration x is the previous pass's g, S^n for the first) */
+            change = 0;
             for (int i = 0; i < n; i++)
                 if (type[i] == 0)
                     for (int a = 0; a < 3; a++) {
-                        const double d = fabs(C.spin[3 * i + a] - spin[3 * i + a]);
+                        const double d = fabs(C.spin[3 * i + a] - X[3 * i + a]);
                         if (d > change) change = d;
                     }
             memcpy(spin, C.spin, sizeof(double) * 3 * n);
             ctx_free(&C);
             if (self_consistent && pc >= 1 && change <= sp->sc_tol) break;
-            /* S_hat = normalise((S^n + S^(p))/2) on spin-carrying atoms */
+            if (pc == last) break;
+            /* next iterate: plain, x = g; accelerated, Anderson mixing of the
+             * last depth residual differences */
+            if (depth == 0) {
+                memcpy(X, spin, sizeof(double) * 3 * n);
+            } else {
+                size_t k = 0;
+                for (int i = 0; i < n; i++)
+                    if (type[i] == 0)
+                        for (int a = 0; a < 3; a++, k++) {
+                            gk[k] = spin[3 * i + a];
+                            fk[k] = spin[3 * i + a] - X[3 * i + a];
+                        }
+                if (pc >= 1) {
+                    /* newest difference in front, the oldest dropped */
+                    const int keep = ncols < depth ? ncols : depth - 1;
+                    memmove(dF + k, dF, sizeof(double) * k * keep);
+                    memmove(dG + k, dG, sizeof(double) * k * keep);
+                    for (size_t e = 0; e < k; e++) {
+                        dF[e] = fk[e] - fprev[e];
+                        dG[e] = gk[e] - gprev[e];
+                    }
+                    ncols = keep + 1;
+                }
+                memcpy(fprev, fk, sizeof(double) * k);
+                memcpy(gprev, gk, sizeof(double) * k);
+                or_anderson_mix((int)k, ncols, dF, dG, fk, gk, sp->sc_reg, xnew, NULL);
+                k = 0;
+                for (int i = 0; i < n; i++)
+                    if (type[i] == 0)
+                        for (int a = 0; a < 3; a++, k++) X[3 * i + a] = xnew[k];
+            }
+            /* S_hat = normalise((S^n + x)/2) on spin-carrying atoms */
             for (int i = 0; i < n; i++) {
                 if (type[i] != 0) continue;
                 double m[3], nn;
-                for (int a = 0; a < 3; a++) m[a] = 0.5 * (Sn[3 * i + a] + spin[3 * i + a]);
+                for (int a = 0; a < 3; a++) m[a] = 0.5 * (Sn[3 * i + a] + X[3 * i + a]);
                 nn = sqrt(dot3(m, m));
                 for (int a = 0; a < 3; a++) Sh[3 * i + a] = m[a] / nn;
             }
@@ -1033,9 +1155,12 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
             o->T_lat = 2.0 * ek / (3.0 * n * KB);
             o->T_spin = den != 0 ? num / (2.0 * KB * den) : 0.0;
             for (int a = 0; a < 3; a++) o->M[a] = nfe ? M[a] / nfe : 0.0;
+            o->passes = passes;
+            o->change = change;
         }
     }
     free(q); free(Fp); free(Ei); free(F); free(H); free(Sn); free(Sh); free(eta); free(snew);
+    free(X); free(fk); free(gk); free(fprev); free(gprev); free(xnew); free(dF); free(dG);
     return 0;
 }
 

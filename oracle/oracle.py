@@ -37,13 +37,13 @@ class StepParams(ct.Structure):
                 ("rcR", ct.c_double), ("rcA", ct.c_double), ("n_ramp", ct.c_int64),
                 ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
                 ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int), ("sc_max", ct.c_int),
-                ("sc_tol", ct.c_double)]
+                ("sc_tol", ct.c_double), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
 
 
 class Obs(ct.Structure):
     _fields_ = [("step", ct.c_double), ("E_nep", ct.c_double), ("E_kin", ct.c_double),
                 ("E_z", ct.c_double), ("T_lat", ct.c_double), ("T_spin", ct.c_double),
-                ("M", ct.c_double * 3)]
+                ("M", ct.c_double * 3), ("passes", ct.c_double), ("change", ct.c_double)]
 
 
 _lib = None
@@ -63,6 +63,7 @@ def lib():
         L.or_field_lin.argtypes = [ct.c_int, P, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
                                    ct.c_double, P, P]
         L.or_normals.argtypes = [ct.c_uint64, ct.c_uint32, ct.c_uint64, ct.c_uint32, P]
+        L.or_anderson_mix.argtypes = [ct.c_int, ct.c_int, P, P, P, P, ct.c_double, P, P]
         L.or_run.argtypes = [ct.c_int, P, P, P, P, P, P, P, P, ct.c_int, ct.POINTER(StepParams),
                              ct.POINTER(ct.c_int64), ct.c_int64, P]
         _lib = L
@@ -141,6 +142,17 @@ def philox(ctr, key):
     return o
 
 
+def anderson_mix(dF, dG, f, g, reg):
+    """One Anderson mixing step (see or_anderson_mix): dF, dG [m][n]; returns (x_next, gamma, used)."""
+    dF = _f64(np.atleast_2d(dF))
+    dG = _f64(np.atleast_2d(dG))
+    m, n = dF.shape if dF.size else (0, len(f))
+    x = np.zeros(n)
+    gam = np.zeros(max(m, 1))
+    used = lib().or_anderson_mix(n, m, _p(dF), _p(dG), _p(_f64(f)), _p(_f64(g)), ct.c_double(reg), _p(x), _p(gam))
+    return x, gam[:m], used
+
+
 def normals(seed, atom, step, stream):
     xi = np.zeros(3)
     lib().or_normals(seed, atom, step, stream, _p(xi))
@@ -149,7 +161,8 @@ def normals(seed, atom, step, stream):
 
 def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
                 mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
-                K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30) -> StepParams:
+                K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30, sc_depth=0,
+                sc_reg=1e-10) -> StepParams:
     sp = StepParams()
     sp.dt = dt
     sp.T0 = T0
@@ -163,6 +176,8 @@ def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, ga
     sp.mid_tol = mid_tol
     sp.sc_tol = sc_tol
     sp.sc_max = sc_max
+    sp.sc_depth = sc_depth
+    sp.sc_reg = sc_reg
     sp.mid_cap = mid_cap
     sp.rcR = rcR
     sp.rcA = rcA
@@ -176,7 +191,8 @@ def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, ga
 
 
 def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps, step0=0):
-    """n_steps of the spin-lattice step; returns (pos, vel, spin, step, obs[n_steps])."""
+    """n_steps of the spin-lattice step; returns (pos, vel, spin, step, obs[n_steps]), obs columns
+    step, E_nep, E_kin, E_z, T_lattice, T_spin, M[3], sweep passes, last change."""
     types = _i32(types)
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
@@ -188,6 +204,6 @@ def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps
     lib().or_run(types.shape[0], _p(types), _p(pos), _p(vel), _p(spin), _p(_f64(box)), _p(_i32(pbc)),
                  _p(_f64(params)), _p(colour), ncol, ct.byref(sp), ct.byref(st), n_steps,
                  ct.cast(obs, ct.c_void_p))
-    ob = np.array([[o.step, o.E_nep, o.E_kin, o.E_z, o.T_lat, o.T_spin, o.M[0], o.M[1], o.M[2]]
-                   for o in obs[:n_steps]]).reshape(n_steps, 9)
+    ob = np.array([[o.step, o.E_nep, o.E_kin, o.E_z, o.T_lat, o.T_spin, o.M[0], o.M[1], o.M[2], o.passes, o.change]
+                   for o in obs[:n_steps]]).reshape(n_steps, 11)
     return pos, vel, spin, st.value, ob

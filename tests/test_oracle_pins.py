@@ -607,3 +607,92 @@ def test_normals_statistics(oracle):
     assert not np.allclose(oracle.normals(1, 0, 0, 0), oracle.normals(1, 0, 0, 1))
     assert not np.allclose(oracle.normals(1, 0, 0, 0), oracle.normals(1, 0, 1, 0))
     assert not np.allclose(oracle.normals(1, 0, 0, 0), oracle.normals(1, 1, 0, 0))
+
+
+def _anderson_run(oracle, gfun, x0, depth, n_iter, reg=0.0):
+    """drive oracle.anderson_mix on a map g, newest difference first"""
+    x = np.array(x0, dtype=float)
+    dF, dG, fprev, gprev = [], [], None, None
+    for k in range(n_iter):
+        g = gfun(x)
+        f = g - x
+        if k >= 1:
+            dF.insert(0, f - fprev)
+            dG.insert(0, g - gprev)
+            del dF[depth:], dG[depth:]
+        fprev, gprev = f, g
+        if dF:
+            x, _, _ = oracle.anderson_mix(np.array(dF), np.array(dG), f, g, reg)
+        else:
+            x = g
+    return x
+
+
+def test_anderson_mix_closed_forms(oracle):
+    """Anderson mixing against what the mathematics fixes: on a scalar linear
+    map depth 1 is the secant step, exact after two evaluations; on a linear
+    map of dimension d with full depth it matches GMRES and reaches the fixed
+    point after d + 2 evaluations, where the plain iteration is still far;
+    a huge regularisation gives the plain step; a singular system without
+    regularisation falls back to it."""
+    # scalar: x = 0.7 x + 3, fixed point 10
+    x = _anderson_run(oracle, lambda x: 0.7 * x + 3.0, [1.0], 1, 3)
+    assert abs(x[0] - 10.0) <= 1e-12
+    # d = 5, spectral radius 0.6
+    rng = np.random.default_rng(11)
+    d = 5
+    A = rng.normal(size=(d, d))
+    A *= 0.6 / np.abs(np.linalg.eigvals(A)).max()
+    c = rng.normal(size=d)
+    xs = np.linalg.solve(np.eye(d) - A, c)
+    xa = _anderson_run(oracle, lambda x: A @ x + c, np.zeros(d), d, d + 2)
+    xp = np.zeros(d)
+    for _ in range(d + 2):
+        xp = A @ xp + c
+    assert np.abs(xa - xs).max() <= 1e-9 * np.abs(xs).max()
+    assert np.abs(xp - xs).max() >= 1e-3 * np.abs(xs).max()
+    # one column by hand: gamma = dF.f / (dF.dF + lam), lam = reg * dF.dF
+    dF = rng.normal(size=(1, 7))
+    dG = rng.normal(size=(1, 7))
+    f, g = rng.normal(size=7), rng.normal(size=7)
+    for reg in (0.0, 0.5):
+        x, gam, used = oracle.anderson_mix(dF, dG, f, g, reg)
+        want = dF[0] @ f / (dF[0] @ dF[0] * (1 + reg))
+        assert used == 1 and abs(gam[0] - want) <= 1e-14 * abs(want)
+        np.testing.assert_allclose(x, g - want * dG[0], rtol=0, atol=1e-14)
+    x, gam, used = oracle.anderson_mix(np.vstack([dF, dF]), np.vstack([dG, dG]), f, g, 1e14)
+    assert np.abs(x - g).max() <= 1e-12
+    x, gam, used = oracle.anderson_mix(np.vstack([dF, dF]), np.vstack([dG, dG]), f, g, 0.0)
+    assert used == 0 and np.array_equal(x, g)
+
+
+def test_accelerated_midpoint_same_fixed_point(oracle):
+    """The accelerated iteration converges to the same midpoint as the plain
+    one (one Langevin step, both to 1e-14), reports its passes, and is
+    time-reversible for the full model; fixed corrector counts report
+    K_corr + 1 passes."""
+    s = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
+    p = W.random_params()
+    box = np.array([500.0] * 3)
+    pos0 = s.pos + 100
+    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    kw = dict(dt=2.0, T0=300.0, alpha=0.1, gammaL=0.01, ensemble=1, B0=(0, 0, 1.0))
+    plain = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour,
+                       oracle.step_params(sc_tol=1e-14, sc_max=60, **kw), 2)
+    acc = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour,
+                     oracle.step_params(sc_tol=1e-14, sc_max=60, sc_depth=3, **kw), 2)
+    assert np.abs(plain[2] - acc[2]).max() <= 1e-12
+    assert np.abs(plain[1] - acc[1]).max() <= 1e-12
+    for ob in (plain[4], acc[4]):
+        assert np.all(ob[:, 9] >= 3) and np.all(ob[:, 9] <= 61) and np.all(ob[:, 10] <= 1e-14)
+    k3 = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour, oracle.step_params(K_corr=3, **kw), 2)
+    assert np.array_equal(k3[4][:, 9], [4, 4])
+    n = 3
+    sc = dict(B0=(0, 0, 1.0), sc_tol=1e-14, sc_max=60, sc_depth=3)
+    pos, vel, spin, _, _ = oracle.run(s.types, pos0, v0, s.spin, box, s.pbc, p, s.colour,
+                                      oracle.step_params(dt=1.0, **sc), n)
+    pos, vel, spin, _, _ = oracle.run(s.types, pos, vel, spin, box, s.pbc, p, s.colour,
+                                      oracle.step_params(dt=-1.0, **sc), n)
+    assert np.abs(pos - pos0).max() <= 1e-10
+    assert np.abs(vel - v0).max() <= 1e-10
+    assert np.abs(spin - s.spin).max() <= 1e-10
