@@ -193,6 +193,20 @@ typedef struct {
     uint64_t seed;       /* Philox key                                        */
     double skin;         /* Verlet skin (A); lists rebuilt when an atom moved
                             more than skin/2 since the last build             */
+    double sc_tol;       /* > 0: self-consistent midpoint (Sec. 5.1): pass p
+                            sweeps from S^n at the midpoint of S^n and x^(p)
+                            (x^(0) = S^n; plain iteration: x^(p) = S^(p-1));
+                            passes repeat until max over spins of
+                            |S^(p) - x^(p)| <= sc_tol (p >= 1) or p = sc_max.
+                            K_corr is then not used. 0: off. Single-system
+                            simulations only (sl_create); the host reads one
+                            small decision per pass.                         */
+    int sc_max;          /* cap on corrector passes when sc_tol > 0          */
+    int sc_depth;        /* accelerated variant (Sec. 5.1), 0..8: the next
+                            iterate mixes the last sc_depth residual
+                            differences (Anderson); 0: plain iteration       */
+    double sc_reg;       /* Tikhonov regularisation of the mixing, relative
+                            to the mean diagonal of the residual Gram matrix */
 } sl_integrator_params;
 
 typedef struct {
@@ -203,6 +217,11 @@ typedef struct {
     double T_lattice;    /* 2 E_kin / (3 N kB)                               */
     double T_spin;       /* sum|s x H|^2 / (2 kB sum s.H) over spins          */
     double M[3];         /* mean spin                                         */
+    int32_t spin_passes; /* sweeps of the spin step: K_corr + 1, or the number
+                            the self-consistent iteration took               */
+    double spin_change;  /* self-consistent: max |S^(p) - x^(p)| of the last
+                            pass (x^(p): the spins whose midpoint it used);
+                            0 otherwise                                      */
 } sl_observables;
 
 /* Create a simulation of one system: copies the state to the device and

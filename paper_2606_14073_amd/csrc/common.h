@@ -55,6 +55,9 @@ struct RepDev {
     int pbc[3], nc[3];
     int ensemble, mid_cap, active, failed;
     int cell_base, n_atoms, fe_off, n_fe, ge_off, n_ge;
+    double sc_tol;                  // self-consistent midpoint tolerance (0: fixed K_corr)
+    unsigned long long sc_delta;    // max |S^(p) - S^(p-1)| of the current pass, as bits
+    int sc_max, sc_done;            // pass cap; converged in this step
 };
 
 __device__ inline double ramp_frac(const RepDev &R) {

@@ -168,7 +168,7 @@ static size_t bytes_per_atom(sl_precision prec) {
     const size_t rs = prec == SL_FP64 ? 8 : 4;
     size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
     b += rs * (2 * DP + 1 + NA * NAB + 12 + 3 * MAXR + 4 * MAXA);
-    b += (rs * (MAXFE * 15 + 14) + 4 * (MAXFE + 3)) / 2 + 64;   // per spin carrier, half the atoms
+    b += (rs * (MAXFE * 15 + 14) + 4 * (MAXFE + 3) + sizeof(d4)) / 2 + 64;   // per spin carrier, half the atoms
     return b;
 }
 
@@ -181,6 +181,12 @@ struct Engine {
     nep_model *M = nullptr;
     sl_precision prec = SL_FP64;
     int K_corr = 1;
+    double sc_tol = 0;     // > 0: corrector passes repeated until the spins settle (single replica)
+    int sc_max = 0;
+    int sc_depth = 0;      // > 0: Anderson mixing over that many residual differences
+    double sc_reg = 0;
+    std::vector<int> log_passes;       // self-consistent: per step since the last clear, sweep passes
+    std::vector<double> log_change;    // and the residual of the last pass
     hipStream_t st = nullptr;
     bool own_stream = false;
 
@@ -193,6 +199,8 @@ struct Engine {
     RepDev *rep = nullptr;
     d4 *pos = nullptr, *vel = nullptr, *spin = nullptr, *force = nullptr, *field = nullptr, *pos_ref = nullptr,
        *spin_n = nullptr, *spin_hat = nullptr, *eta = nullptr;
+    d4 *sc_x = nullptr, *sc_f = nullptr, *sc_g = nullptr, *sc_dF = nullptr, *sc_dG = nullptr;
+    double *sc_part = nullptr, *sc_out = nullptr;
     int *nbrR = nullptr, *cntR = nullptr, *cntFeR = nullptr, *revR = nullptr;
     int *nbrA = nullptr, *cntA = nullptr, *cntFeA = nullptr, *revA = nullptr, *a2r = nullptr;
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
@@ -262,6 +270,7 @@ struct Engine {
         dfree(rid); dfree(orig); dfree(colour); dfree(rep);
         dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
         dfree(spin_n); dfree(spin_hat); dfree(eta);
+        dfree(sc_x); dfree(sc_f); dfree(sc_g); dfree(sc_dF); dfree(sc_dG); dfree(sc_part); dfree(sc_out);
         dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
         dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
         dfree(cell_of); dfree(cell_cnt); dfree(cell_start); dfree(cell_fill); dfree(cell_atoms);
@@ -288,6 +297,8 @@ struct Engine {
         S.rep = rep;
         S.pos = pos; S.vel = vel; S.spin = spin; S.force = force; S.field = field; S.pos_ref = pos_ref;
         S.spin_n = spin_n; S.spin_hat = spin_hat; S.eta = eta;
+        S.sc_x = sc_x; S.sc_f = sc_f; S.sc_g = sc_g; S.sc_dF = sc_dF; S.sc_dG = sc_dG;
+        S.sc_part = sc_part; S.sc_out = sc_out;
         S.colour = colour;
         S.col_idx = col_idx;
         S.colpos = colpos;
@@ -351,6 +362,7 @@ struct Engine {
             dfree(rid); dfree(orig); dfree(colour);
             dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
             dfree(spin_n); dfree(spin_hat); dfree(eta);
+            dfree(sc_x); dfree(sc_f); dfree(sc_g); dfree(sc_dF); dfree(sc_dG); dfree(sc_part);
             dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
             dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
             dfree(cell_of); dfree(cell_atoms); dfree(cpl_j); dfree(cpl_n);
@@ -366,7 +378,12 @@ struct Engine {
                 (rc = dalloc(&cntA, c)) || (rc = dalloc(&cntFeA, c)) || (rc = dalloc(&revA, (size_t)MAXA * c)) ||
                 (rc = dalloc(&a2r, (size_t)MAXA * c)) || (rc = dalloc(&cell_of, c)) ||
                 (rc = dalloc(&cell_atoms, c)) || (rc = dalloc(&cpl_j, (size_t)MAXFE * cf)) ||
-                (rc = dalloc(&cpl_n, cf)))
+                (rc = dalloc(&cpl_n, cf)) || (rc = dalloc(&sc_x, cf)))
+                return rc;
+            if (sc_tol > 0 && sc_depth > 0 &&
+                ((rc = dalloc(&sc_f, cf)) || (rc = dalloc(&sc_g, cf)) || (rc = dalloc(&sc_dF, (size_t)sc_depth * cf)) ||
+                 (rc = dalloc(&sc_dG, (size_t)sc_depth * cf)) ||
+                 (rc = dalloc(&sc_part, (size_t)sc_part_blocks((int)cf) * SC_NK))))
                 return rc;
             const size_t rs = prec == SL_FP64 ? 8 : 4;
             work_bytes = work_count(c, cf) * rs;
@@ -402,7 +419,7 @@ struct Engine {
             cap_chunks = c;
         }
         if (!flags) {
-            if ((rc = dalloc(&flags, NFLAGS))) return rc;
+            if ((rc = dalloc(&flags, NFLAGS)) || (rc = dalloc(&sc_out, SC_OUT))) return rc;
             HIPCHK(hipMemset(flags, 0, NFLAGS * sizeof(int)));
         }
         if (!col_idx || cap_col < cap_fe) {
@@ -664,7 +681,11 @@ struct Engine {
     void spin_step(const ModelDev<real> &m, const Work<real> &w) {
         const Sys S = sys();
         { ProfScope q(this, 9); launch_spin_prep(S, st); }
-        for (int p = 0; p <= K_corr; p++) {
+        const bool sc = sc_tol > 0;
+        const int last = sc ? sc_max : K_corr;
+        int passes = 0;
+        double change = 0;
+        for (int p = 0; p <= last; p++) {
             // every pass sits at the same mid positions: the structural terms of the first are reused
             forward(m, w, spin_hat, p == 0 ? PASS_SPIN : PASS_SPIN_REUSE);
             { ProfScope q(this, 6); launch_assemble(S, m, w, st); }
@@ -676,10 +697,29 @@ struct Engine {
                 ProfScope q(this, 7);
                 launch_sweep(S, w, col_ptr.data(), (int)col_ptr.size() - 1, st);
             }
-            if (p < K_corr) {
-                ProfScope q(this, 9);
-                launch_spin_mid(S, st);
+            passes = p + 1;
+            if (sc) {
+                // the host waits for the decision: one small read per pass
+                double out[2] = {0, 0};
+                {
+                    ProfScope q(this, 9);
+                    launch_sc_check(S, p, sc_depth, sc_reg, st);
+                }
+                if (hipMemcpyAsync(out, sc_out, sizeof(out), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    out[0] = 0;   // the step's own error checks report the failure
+                change = out[1];
+                if (out[0] == 0) break;
             }
+            if (p < last) {
+                ProfScope q(this, 9);
+                if (sc && sc_depth > 0) launch_sc_mix(S, p, sc_depth, st);
+                else launch_spin_mid(S, st);
+            }
+        }
+        if (sc) {
+            log_passes.push_back(passes);
+            log_change.push_back(change);
         }
     }
 
@@ -984,6 +1024,12 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
         if (!(ip->dt != 0 && std::isfinite(ip->dt))) return fail(SL_E_INVALID, "dt must be finite and non-zero");
         if (ip->mid_cap < 1 || ip->mid_cap > 1000) return fail(SL_E_INVALID, "mid_cap must be in [1, 1000]");
         if (ip->K_corr < 0 || ip->K_corr > 64) return fail(SL_E_INVALID, "K_corr must be in [0, 64]");
+        if (!(ip->sc_tol >= 0 && std::isfinite(ip->sc_tol))) return fail(SL_E_INVALID, "sc_tol must be finite, >= 0");
+        if (ip->sc_tol > 0 && (ip->sc_max < 1 || ip->sc_max > 1000))
+            return fail(SL_E_INVALID, "sc_max must be in [1, 1000]");
+        if (ip->sc_tol > 0 && (ip->sc_depth < 0 || ip->sc_depth > SC_MAXD || !(ip->sc_reg >= 0) ||
+                               !std::isfinite(ip->sc_reg)))
+            return fail(SL_E_INVALID, "sc_depth must be in [0, 8] and sc_reg finite and >= 0");
         if (ip->alpha_s < 0 || ip->T0 < 0 || ip->T1 < 0 || ip->gamma_L < 0)
             return fail(SL_E_INVALID, "alpha_s, temperatures and gamma_L must be non-negative");
         d.dt = ip->dt;
@@ -993,6 +1039,8 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
         d.gammaL = ip->gamma_L;
         d.mid_tol = ip->mid_tol;
         d.mid_cap = ip->mid_cap;
+        d.sc_tol = ip->sc_tol;
+        d.sc_max = ip->sc_max;
         d.n_ramp = ip->n_ramp;
         d.seed = ip->seed;
         d.ensemble = ip->ensemble;
@@ -1199,8 +1247,11 @@ struct sl_sim {
     Replica r;
 };
 
-static void fill_obs(const double *o, double nfe, int64_t step, int64_t n_atoms, sl_observables *out) {
+static void fill_obs(const double *o, double nfe, int64_t step, int64_t n_atoms, sl_observables *out, int passes,
+                     double change) {
     out->step = step;
+    out->spin_passes = passes;
+    out->spin_change = change;
     out->E_pot = o[0];
     out->E_kin = o[1];
     out->E_zeeman = o[2];
@@ -1221,6 +1272,10 @@ extern "C" int sl_create(const nep_model *m, const sl_system_view *sys, const do
     s->eng.M = const_cast<nep_model *>(m);
     s->eng.prec = prec;
     s->eng.K_corr = ip->K_corr;
+    s->eng.sc_tol = ip->sc_tol;
+    s->eng.sc_max = ip->sc_max;
+    s->eng.sc_depth = ip->sc_tol > 0 ? ip->sc_depth : 0;
+    s->eng.sc_reg = ip->sc_reg;
     if ((rc = s->eng.set_layout({&s->r}))) return rc;
     std::vector<int> bad;
     if ((rc = settle_layout(s->eng, bad))) return rc;
@@ -1244,6 +1299,8 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
     int64_t done = 0;
     while (done < n_steps) {
         const int64_t k = std::min(chunk, n_steps - done);
+        e.log_passes.clear();
+        e.log_change.clear();
         for (int64_t q = 0; q < k; q++) e.step(e.obs + q * NOBS);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(h.data(), e.obs, k * NOBS * 8, hipMemcpyDeviceToHost, e.st));
@@ -1254,7 +1311,10 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
         const int64_t ran = d[0].step - step;       // steps completed in this chunk
         for (int64_t q = 0; q < ran; q++) {
             const double *o = h.data() + q * NOBS;
-            if (per_step_out) fill_obs(o, (double)s->r.n_fe, step + q + 1, s->r.n, per_step_out + done + q);
+            const bool sc = e.sc_tol > 0 && q < (int64_t)e.log_passes.size();
+            if (per_step_out)
+                fill_obs(o, (double)s->r.n_fe, step + q + 1, s->r.n, per_step_out + done + q,
+                         sc ? e.log_passes[q] : e.K_corr + 1, sc ? e.log_change[q] : 0.0);
             if (o[NOBS - 1] != 0) return fail(SL_E_NONFINITE, "state became non-finite at step " + std::to_string(step + q + 1));
         }
         done += ran;
@@ -1575,6 +1635,7 @@ extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const
                                  const sl_integrator_params *ip, int64_t n_steps, uint64_t *id_out) {
     if (!sv || !ip || !id_out) return fail(SL_E_INVALID, "server, params and id_out are required");
     if (ip->K_corr != sv->cfg.K_corr) return fail(SL_E_INVALID, "K_corr must equal the server's");
+    if (ip->sc_tol != 0) return fail(SL_E_INVALID, "the replica server runs a fixed number of corrector passes");
     if (n_steps < 1) return fail(SL_E_INVALID, "n_steps must be >= 1");
     auto r = std::make_unique<Replica>();
     int rc = make_replica(sys, vel, colour, ip, true, *r);
@@ -1628,7 +1689,7 @@ extern "C" int sl_replica_fetch(sl_server *sv, uint64_t id, double *pos, double 
     if (vel) std::memcpy(vel, r->vel.data(), 24 * r->n);
     if (spin) std::memcpy(spin, r->spin.data(), 24 * r->n);
     if (obs) {
-        fill_obs(r->obs_last, (double)r->n_fe, r->obs_step, r->n, obs);
+        fill_obs(r->obs_last, (double)r->n_fe, r->obs_step, r->n, obs, sv->eng.K_corr + 1, 0.0);
     }
     return SL_OK;
 }

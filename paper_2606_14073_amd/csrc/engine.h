@@ -19,6 +19,10 @@ struct Sys {
     const int *orig;       // [N] index in the replica's caller order
     RepDev *rep;           // [n_rep]
     d4 *pos, *vel, *spin, *force, *field, *pos_ref, *spin_n, *spin_hat, *eta;
+    // self-consistent midpoint: iterate x, previous residual and sweep result,
+    // difference ring [depth][N_fe] (mixing only), Gram partials, decisions
+    d4 *sc_x, *sc_f, *sc_g, *sc_dF, *sc_dG;
+    double *sc_part, *sc_out;
     const int *colour;     // [N] colour on spin carriers, -1 elsewhere
     const int *col_idx;    // [N_fe] spin carriers grouped by colour
     const int *colpos;     // [N_fe] position of each spin carrier in col_idx
@@ -88,6 +92,15 @@ void launch_spin_prep(const Sys &S, hipStream_t st);
 void launch_spin_restore(const Sys &S, hipStream_t st);
 void launch_spin_mid(const Sys &S, hipStream_t st);
 void launch_step_end(const Sys &S, hipStream_t st);
+// self-consistent midpoint: residual of the pass, per replica converged or
+// not, and with depth > 0 the mixing coefficients; sc_out[0] = replicas still
+// iterating, sc_out[1] = largest change, sc_out[2] = columns used, then gam
+constexpr int SC_OUT = 12;
+constexpr int SC_MAXD = 8;                                     // deepest mixing history
+constexpr int SC_NK = SC_MAXD * (SC_MAXD + 1) / 2 + SC_MAXD;   // Gram entries + right-hand side
+int sc_part_blocks(int n_fe);
+void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st);
+void launch_sc_mix(const Sys &S, int pass, int depth, hipStream_t st);
 
 // per-replica fixed-order reductions: out[r][NOBS]
 constexpr int NOBS = 9;   // E_nep, E_kin, E_z, Ts_num, Ts_den, Mx, My, Mz, nonfinite

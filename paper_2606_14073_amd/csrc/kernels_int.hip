@@ -81,17 +81,20 @@ __global__ void k_spin_prep(Sys S) {
     S.spin_hat[i] = s;
 }
 
+// replicas whose self-consistent iteration has converged keep their spins
+__device__ inline bool spin_pass_on(const RepDev &R) { return R.active && !R.sc_done; }
+
 __global__ void k_spin_restore(Sys S) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
-    if (!S.rep[S.rid[i]].active) return;
+    if (!spin_pass_on(S.rep[S.rid[i]])) return;
     S.spin[i] = S.spin_n[i];
 }
 
 __global__ void k_spin_mid(Sys S) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
-    if (!S.rep[S.rid[i]].active) return;
+    if (!spin_pass_on(S.rep[S.rid[i]])) return;
     const d4 a = S.spin_n[i], b = S.spin[i];
     const double x = 0.5 * (a.x + b.x), y = 0.5 * (a.y + b.y), z = 0.5 * (a.z + b.z);
     const double n = sqrt(x * x + y * y + z * z);
@@ -208,7 +211,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         hy += __shfl_xor(hy, m);
         hz += __shfl_xor(hz, m);
     }
-    if (!R.active) return;
+    if (!spin_pass_on(R)) return;
     const double fr = ramp_frac(R), zs = R.mu_s * MUB;
     hx += zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr) + e.x;
     hy += zs * (R.B0[1] + (R.B1[1] - R.B0[1]) * fr) + e.y;
@@ -244,13 +247,13 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
             nz = sz;
         } else {
             const double iw = rsqrt_nr(w2);
-            const double th = w2 * iw * tau;
+            const double th = w2 * iw * tau, ath = fabs(th);   // negative for a backward step
             double sn, cs, omc;
-            if (th < 1e-8) {
+            if (ath < 1e-8) {
                 sn = th - th * th * th / 6.0;
                 omc = th * th / 2.0;
                 cs = 1.0 - omc;
-            } else if (th <= 1.0) {
+            } else if (ath <= 1.0) {
                 sin_omc_taylor(th, sn, omc);
                 cs = 1.0 - omc;
             } else {
@@ -286,8 +289,202 @@ __global__ void k_step_end(Sys S) {
         return;
     }
     R.step += 1;
+    R.sc_done = 0;
     // a replica waiting for a new colouring stops after this (exact) step
     if (R.step >= R.step_end || (R.failed & 4)) R.active = 0;
+}
+
+// Self-consistent midpoint (Sec. 5.1): the corrector is a fixed-point
+// iteration x -> g(x) on the end-of-step spins, g being the sweep at the
+// midpoint normalise((S^n + x)/2); x^(0) = S^n. After each sweep, per spin
+// carrier of an iterating replica: the residual f = g - x and its max norm
+// (non-negative doubles order like their bit patterns, so an integer max over
+// the bits is the max; a wave reduces first and issues one atomic when all its
+// lanes belong to one replica). Plain iteration keeps x = g for the next pass.
+// The accelerated variant (depth > 0, one replica) stores the differences
+// dF = f - f_prev, dG = g - g_prev in a ring of depth slots and sums, per
+// workgroup in a fixed order, the Gram entries dF_a . dF_b and dF_a . f of
+// the mk newest columns.
+__device__ inline int sc_slot(int pass, int age, int depth) {   // ring slot of the column made `age` passes ago
+    return ((pass - 1 - age) % depth + depth) % depth;
+}
+
+__global__ void __launch_bounds__(256) k_sc_check(Sys S, int pass, int depth, int mk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int r = -1;
+    double d = 0;
+    double3 f = {0, 0, 0};
+    bool on = false;
+    const size_t lf = S.N_fe;
+    if (i < S.N_fe) {
+        const int ri = S.rid[i];
+        const RepDev &R = S.rep[ri];
+        if (spin_pass_on(R) && R.sc_tol > 0) {
+            on = true;
+            const d4 g = S.spin[i];
+            const d4 x = pass == 0 ? S.spin_n[i] : S.sc_x[i];
+            f = make_double3(g.x - x.x, g.y - x.y, g.z - x.z);
+            d = fmax(fabs(f.x), fmax(fabs(f.y), fabs(f.z)));
+            r = pass > 0 ? ri : -1;
+            if (depth == 0) {
+                S.sc_x[i] = g;
+            } else {
+                if (pass > 0) {
+                    const int sl = sc_slot(pass, 0, depth);
+                    const d4 fp = S.sc_f[i], gp = S.sc_g[i];
+                    S.sc_dF[sl * lf + i] = d4{f.x - fp.x, f.y - fp.y, f.z - fp.z, 0.0};
+                    S.sc_dG[sl * lf + i] = d4{g.x - gp.x, g.y - gp.y, g.z - gp.z, 0.0};
+                }
+                S.sc_f[i] = d4{f.x, f.y, f.z, 0.0};
+                S.sc_g[i] = g;
+            }
+        }
+    }
+    const int r0 = __shfl(r, 0);
+    if (__all(r == r0)) {
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) d = fmax(d, __shfl_xor(d, m));
+        if ((threadIdx.x & 63) == 0 && r0 >= 0)
+            atomicMax(&S.rep[r0].sc_delta, (unsigned long long)__double_as_longlong(d));
+    } else if (r >= 0) {
+        atomicMax(&S.rep[r].sc_delta, (unsigned long long)__double_as_longlong(d));
+    }
+    if (mk == 0) return;   // uniform over the grid
+    // Gram entries of the mk newest columns (age order), this workgroup's atoms
+    __shared__ double red[4][SC_NK];
+    double3 c[SC_MAXD];
+#pragma unroll
+    for (int a = 0; a < SC_MAXD; a++) {
+        c[a] = make_double3(0, 0, 0);
+        if (a < mk && on) {
+            const d4 v = S.sc_dF[sc_slot(pass, a, depth) * lf + i];
+            c[a] = make_double3(v.x, v.y, v.z);
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < SC_MAXD; a++) {
+        if (a >= mk) break;
+#pragma unroll
+        for (int b = 0; b <= a; b++) {
+            double v = c[a].x * c[b].x + c[a].y * c[b].y + c[a].z * c[b].z;
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+            if (lane == 0) red[wv][k] = v;
+            k++;
+        }
+        double v = c[a].x * f.x + c[a].y * f.y + c[a].z * f.z;
+#pragma unroll
+        for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m);
+        if (lane == 0) red[wv][k] = v;
+        k++;
+    }
+    __syncthreads();
+    const int nk = mk * (mk + 1) / 2 + mk;
+    if (threadIdx.x < nk) {
+        const int t = threadIdx.x;
+        S.sc_part[(size_t)blockIdx.x * SC_NK + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    }
+}
+
+// One workgroup: converged or capped replicas stop; count the others. With
+// mixing, the Gram matrix is summed over the workgroups in order and the
+// regularised normal equations (G + lam I) gam = r, lam = reg * trace(G) / mk,
+// are solved by Cholesky; a pivot below 1e-13 of its diagonal entry (a column
+// in the span of the others) gives the plain step. sc_out: pending replicas,
+// largest change of this pass, used columns, gam[mk].
+__global__ void __launch_bounds__(256) k_sc_decide(Sys S, int pass, int mk, int nblocks, double reg) {
+    __shared__ int cnt;
+    __shared__ unsigned long long dmax;
+    __shared__ double sum[SC_NK];
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        dmax = 0;
+    }
+    __syncthreads();
+    int mine = 0;
+    for (int r = threadIdx.x; r < S.n_rep; r += blockDim.x) {
+        RepDev &R = S.rep[r];
+        if (!R.active || R.sc_tol <= 0 || R.sc_done) continue;
+        const double dl = __longlong_as_double((long long)R.sc_delta);
+        if (pass >= 1) atomicMax(&dmax, R.sc_delta);
+        if (pass >= 1 && (dl <= R.sc_tol || pass >= R.sc_max)) R.sc_done = 1;
+        R.sc_delta = 0;
+        mine += !R.sc_done;
+    }
+    if (mine) atomicAdd(&cnt, mine);
+    const int nk = mk * (mk + 1) / 2 + mk;
+    if (threadIdx.x < nk) {
+        double v = 0;
+        for (int b = 0; b < nblocks; b++) v += S.sc_part[(size_t)b * SC_NK + threadIdx.x];
+        sum[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double *out = S.sc_out;
+    out[0] = cnt;
+    out[1] = __longlong_as_double((long long)dmax);
+    out[2] = 0;
+    if (mk == 0 || cnt == 0) return;
+    double G[SC_MAXD][SC_MAXD], rh[SC_MAXD], L[SC_MAXD][SC_MAXD], y[SC_MAXD], gam[SC_MAXD];
+    int k = 0;
+    for (int a = 0; a < mk; a++) {
+        for (int b = 0; b <= a; b++) G[a][b] = G[b][a] = sum[k++];
+        rh[a] = sum[k++];
+    }
+    double tr = 0;
+    for (int a = 0; a < mk; a++) tr += G[a][a];
+    if (!(tr > 0)) return;
+    const double lam = reg * tr / mk;
+    for (int a = 0; a < mk; a++) {
+        for (int b = 0; b <= a; b++) {
+            double v = G[a][b] + (a == b ? lam : 0.0);
+            for (int c = 0; c < b; c++) v -= L[a][c] * L[b][c];
+            if (a == b) {
+                if (!(v > 1e-13 * (G[a][a] + lam))) return;
+                L[a][a] = sqrt(v);
+            } else {
+                L[a][b] = v / L[b][b];
+            }
+        }
+    }
+    for (int a = 0; a < mk; a++) {
+        double v = rh[a];
+        for (int c = 0; c < a; c++) v -= L[a][c] * y[c];
+        y[a] = v / L[a][a];
+    }
+    for (int a = mk - 1; a >= 0; a--) {
+        double v = y[a];
+        for (int c = a + 1; c < mk; c++) v -= L[c][a] * gam[c];
+        gam[a] = v / L[a][a];
+    }
+    for (int a = 0; a < mk; a++) out[3 + a] = gam[a];
+    out[2] = mk;
+}
+
+// mixed iterate x = g - sum_a gam_a dG_a (the plain x = g when no columns are
+// used) and the midpoint spins normalise((S^n + x)/2) of the next pass
+__global__ void __launch_bounds__(256) k_sc_mix(Sys S, int pass, int depth) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    if (!spin_pass_on(S.rep[S.rid[i]])) return;
+    const size_t lf = S.N_fe;
+    const int used = (int)S.sc_out[2];
+    const d4 g = S.spin[i];
+    double x = g.x, y = g.y, z = g.z;
+    for (int a = 0; a < used; a++) {
+        const double ga = S.sc_out[3 + a];
+        const d4 v = S.sc_dG[sc_slot(pass, a, depth) * lf + i];
+        x -= ga * v.x;
+        y -= ga * v.y;
+        z -= ga * v.z;
+    }
+    S.sc_x[i] = d4{x, y, z, 0.0};
+    const d4 a = S.spin_n[i];
+    const double mx = 0.5 * (a.x + x), my = 0.5 * (a.y + y), mz = 0.5 * (a.z + z);
+    const double n = sqrt(mx * mx + my * my + mz * mz);
+    S.spin_hat[i] = d4{mx / n, my / n, mz / n, 0.0};
 }
 
 // per-chunk partial sums of the observables (fixed tree), then per replica
@@ -379,6 +576,16 @@ void launch_spin_mid(const Sys &S, hipStream_t st) {
 }
 void launch_step_end(const Sys &S, hipStream_t st) {
     if (S.n_rep) hipLaunchKernelGGL(k_step_end, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S);
+}
+int sc_part_blocks(int n_fe) { return nblk(n_fe, 256); }
+void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st) {
+    const int mk = depth > 0 ? (pass < depth ? pass : depth) : 0;
+    const int nb = nblk(S.N_fe, 256);
+    if (S.N_fe) hipLaunchKernelGGL(k_sc_check, dim3(nb), dim3(256), 0, st, S, pass, depth, mk);
+    hipLaunchKernelGGL(k_sc_decide, dim3(1), dim3(256), 0, st, S, pass, S.N_fe ? mk : 0, nb, reg);
+}
+void launch_sc_mix(const Sys &S, int pass, int depth, hipStream_t st) {
+    if (S.N_fe) hipLaunchKernelGGL(k_sc_mix, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, pass, depth);
 }
 
 // colours 0, 1, .., C-1 and then C-1, .., 0; the two visits of colour C-1 are

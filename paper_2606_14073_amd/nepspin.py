@@ -59,12 +59,14 @@ class IntegratorParams(ct.Structure):
     _fields_ = [("dt", ct.c_double), ("T0", ct.c_double), ("T1", ct.c_double), ("B0", ct.c_double * 3),
                 ("B1", ct.c_double * 3), ("alpha_s", ct.c_double), ("gamma_L", ct.c_double),
                 ("n_ramp", ct.c_int64), ("ensemble", ct.c_int), ("K_corr", ct.c_int), ("mid_tol", ct.c_double),
-                ("mid_cap", ct.c_int), ("seed", ct.c_uint64), ("skin", ct.c_double)]
+                ("mid_cap", ct.c_int), ("seed", ct.c_uint64), ("skin", ct.c_double), ("sc_tol", ct.c_double),
+                ("sc_max", ct.c_int), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
 
 
 class Observables(ct.Structure):
     _fields_ = [("step", ct.c_int64), ("E_pot", ct.c_double), ("E_kin", ct.c_double), ("E_zeeman", ct.c_double),
-                ("T_lattice", ct.c_double), ("T_spin", ct.c_double), ("M", ct.c_double * 3)]
+                ("T_lattice", ct.c_double), ("T_spin", ct.c_double), ("M", ct.c_double * 3),
+                ("spin_passes", ct.c_int32), ("spin_change", ct.c_double)]
 
 
 class ServerConfig(ct.Structure):
@@ -160,7 +162,8 @@ def system_view(types, pos, spin, box, pbc=(1, 1, 1), mu_s=1.0, B=(0.0, 0.0, 0.0
 
 
 def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s=0.0, gamma_L=0.0, n_ramp=0,
-                      ensemble=0, K_corr=1, mid_tol=1e-15, mid_cap=50, seed=0x5EED, skin=0.5):
+                      ensemble=0, K_corr=1, mid_tol=1e-15, mid_cap=50, seed=0x5EED, skin=0.5, sc_tol=0.0,
+                      sc_max=30, sc_depth=0, sc_reg=1e-10):
     ip = IntegratorParams()
     ip.dt, ip.T0, ip.T1 = dt, T0, T0 if T1 is None else T1
     for a in range(3):
@@ -168,6 +171,7 @@ def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s
         ip.B1[a] = (B0 if B1 is None else B1)[a]
     ip.alpha_s, ip.gamma_L, ip.n_ramp, ip.ensemble = alpha_s, gamma_L, n_ramp, ensemble
     ip.K_corr, ip.mid_tol, ip.mid_cap, ip.seed, ip.skin = K_corr, mid_tol, mid_cap, seed, skin
+    ip.sc_tol, ip.sc_max, ip.sc_depth, ip.sc_reg = sc_tol, sc_max, sc_depth, sc_reg
     return ip
 
 
@@ -226,8 +230,9 @@ class Model:
 
 
 def _obs_array(obs, n):
-    return np.array([[o.step, o.E_pot, o.E_kin, o.E_zeeman, o.T_lattice, o.T_spin, o.M[0], o.M[1], o.M[2]]
-                     for o in obs[:n]]).reshape(n, 9)
+    """columns: step, E_pot, E_kin, E_zeeman, T_lattice, T_spin, M[3], spin sweep passes, last change"""
+    return np.array([[o.step, o.E_pot, o.E_kin, o.E_zeeman, o.T_lattice, o.T_spin, o.M[0], o.M[1], o.M[2],
+                      o.spin_passes, o.spin_change] for o in obs[:n]]).reshape(n, 11)
 
 
 class Sim:

@@ -47,11 +47,17 @@ def _compare_step(oracle, s, p, colour, state0, state1, kw):
 
 SCHEDULES = {
     "nve": dict(dt=1.0, B0=(0, 0, 1.0)),
+    "nve_backward": dict(dt=-1.0, B0=(0, 0, 1.0)),
     "langevin": dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, 1.0)),
     "ramp": dict(dt=1.0, T0=150.0, T1=280.0, n_ramp=20, alpha_s=0.1, gamma_L=0.01, ensemble=1,
                  B0=(0, 0, 0.0), B1=(0, 0, 1.0)),
     "kcorr0": dict(dt=1.0, T0=300.0, alpha_s=0.05, gamma_L=0.01, ensemble=1, K_corr=0),
     "kcorr3": dict(dt=0.5, T0=100.0, alpha_s=0.2, gamma_L=0.02, ensemble=1, K_corr=3),
+    # corrector iterated until the spins change by at most 1e-13: whichever
+    # side stops one pass earlier, the two stay within 1e-12
+    "selfconsistent": dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, sc_tol=1e-13, sc_max=40),
+    "accelerated": dict(dt=2.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, sc_tol=1e-13, sc_max=40,
+                        sc_depth=3),
 }
 
 
@@ -238,3 +244,157 @@ def test_fp32_mixed_step_error(model, oracle):
     assert ep < 1e-8 and ev < 1e-5 and es < 1e-5
     fe = s.types == 0
     assert np.abs(np.linalg.norm(b[2][fe], axis=1) - 1).max() <= 1e-14
+
+
+def test_selfconsistent_limits_are_fixed_pass_counts(model, oracle):
+    """A tolerance every pass meets stops after the first corrector: bitwise the
+    K_corr = 1 step. A tolerance no pass meets runs to the cap: bitwise the
+    K_corr = 3 step for a cap of 3. Iterated to 1e-13 the step differs from
+    both, and matches the oracle's self-consistent step."""
+    from paper_2606_14073_amd import nepspin
+    kw = dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1)
+    s = W.config_small()
+    p = W.random_params()
+    v = W.maxwell_boltzmann(s.types, 300.0)
+
+    def run(**extra):
+        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour,
+                          params=_params(nepspin, **kw, **extra))
+        ob = sim.integrate(3)
+        out = sim.state()
+        sim.close()
+        passes = extra.get("K_corr", 1) + 1 if "sc_tol" not in extra else None
+        if passes is not None:
+            assert np.all(ob[:, 9] == passes) and np.all(ob[:, 10] == 0)
+        elif extra["sc_tol"] >= 1.0:
+            assert np.all(ob[:, 9] == 2)
+        elif extra["sc_tol"] < 1e-200:
+            assert np.all(ob[:, 9] == extra["sc_max"] + 1)
+        return out
+
+    k1, k3 = run(K_corr=1), run(K_corr=3)
+    s1, s3 = run(sc_tol=1e3, sc_max=1), run(sc_tol=1e-300, sc_max=3)
+    for a, b in ((k1, s1), (k3, s3)):
+        for x, y in zip(a[:3], b[:3]):
+            assert np.array_equal(x, y)
+    # an accelerated run with nothing to mix (cap 1) is the plain one
+    a1 = run(sc_tol=1e-300, sc_max=1, sc_depth=4)
+    for x, y in zip(k1[:3], a1[:3]):
+        assert np.array_equal(x, y)
+    sc = run(sc_tol=1e-13, sc_max=40)
+    assert np.abs(sc[2] - k1[2]).max() > 1e-9
+    rp, rv, rs, _, _ = oracle.run(s.types, s.pos, v, s.spin, s.box, s.pbc, p, s.colour,
+                                  _oracle_params(oracle, sc_tol=1e-13, sc_max=40, **kw), 3)
+    es = np.abs(sc[2] - rs).max()
+    ev = rel_inf(sc[1], rv)
+    print(f"self-consistent, 3 steps: spin {es:.2e} vel {ev:.2e}; differs from K_corr=1 by "
+          f"{np.abs(sc[2] - k1[2]).max():.2e}", flush=True)
+    assert es <= 1e-11 and ev <= 1e-11
+
+
+def test_selfconsistent_reversible(model):
+    """NVE with the corrector iterated to 1e-14: n steps with dt, then n with
+    -dt, return to the start (full model, periodic crystal)"""
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    n = 6
+    sc = dict(B0=(0, 0, 2.0), sc_tol=1e-14, sc_max=80)
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v0, colour=s.colour,
+                      params=_params(nepspin, dt=1.0, **sc))
+    sim.integrate(n)
+    pos, vel, spin, _ = sim.state()
+    sim.close()
+    sim = nepspin.Sim(model, s.types, pos, spin, s.box, s.pbc, vel=vel, colour=s.colour,
+                      params=_params(nepspin, dt=-1.0, **sc))
+    sim.integrate(n)
+    pos1, vel1, spin1, _ = sim.state()
+    sim.close()
+    dp = np.abs(min_image_delta(pos1, s.pos, s.box, s.pbc)).max()
+    dv, ds = np.abs(vel1 - v0).max(), np.abs(spin1 - s.spin).max()
+    print(f"self-consistent reversibility over {n} steps: pos {dp:.2e} vel {dv:.2e} spin {ds:.2e}", flush=True)
+    assert dp <= 1e-10 and dv <= 1e-10 and ds <= 1e-10
+
+
+def test_selfconsistent_rejected_by_server(model):
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    srv = nepspin.Server(model, hbm_budget_bytes=1 << 30, max_slots=2, precision="fp64", steps_per_batch=4)
+    try:
+        with pytest.raises(nepspin.NepError) as e:
+            srv.submit(s.types, s.pos, s.spin, s.box, s.pbc, colour=s.colour, n_steps=2,
+                       params=_params(nepspin, sc_tol=1e-12))
+        assert e.value.code == nepspin.SL_E_INVALID
+    finally:
+        srv.close()
+
+
+def _strong_params(scale):
+    """the random model with its magnetic coefficient blocks scaled: stronger
+    feedback of the spins on their own field"""
+    p = W.random_params().copy()
+    p[576:2124] *= scale
+    return p
+
+
+def test_accelerated_iteration_strong_feedback(oracle):
+    """Magnetic coefficients x4, dt 2 fs: the plain iteration needs many
+    passes. Plain and accelerated (depth 4) both match their oracle runs step
+    by step, report the same pass counts as the oracle to within one, reach the
+    same midpoint, and the accelerated one takes fewer passes."""
+    from paper_2606_14073_amd import nepspin
+    p = _strong_params(4.0)
+    model = nepspin.Model(p)
+    s = W.config_small()
+    v = W.maxwell_boltzmann(s.types, 300.0)
+    kw = dict(dt=2.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, 1.0), sc_tol=1e-13, sc_max=100)
+    res = {}
+    for depth in (0, 4):
+        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour,
+                          params=_params(nepspin, sc_depth=depth, **kw))
+        prev = sim.state()
+        worst, passes, opasses = [0, 0, 0], [], []
+        for k in range(3):
+            ob = sim.integrate(1)
+            cur = sim.state()
+            pos0, vel0, spin0, k0 = prev
+            rp, rv, rs, _, rob = oracle.run(s.types, pos0, vel0, spin0, s.box, s.pbc, p, s.colour,
+                                            _oracle_params(oracle, sc_depth=depth, **kw), 1, step0=k0)
+            dpos = min_image_delta(cur[0], rp, s.box, s.pbc)
+            e = (np.abs(dpos).max() / np.abs(rp).max(), rel_inf(cur[1], rv), np.abs(cur[2] - rs).max())
+            worst = [max(a, b) for a, b in zip(worst, e)]
+            passes.append(int(ob[0, 9]))
+            opasses.append(int(rob[0, 9]))
+            assert ob[0, 10] <= 1e-13
+            prev = cur
+        sim.close()
+        res[depth] = (prev, passes)
+        print(f"depth {depth}: passes {passes} (oracle {opasses}), worst per-step pos {worst[0]:.2e} "
+              f"vel {worst[1]:.2e} spin {worst[2]:.2e}", flush=True)
+        assert max(worst) <= TOL64
+        assert all(abs(a - b) <= 1 for a, b in zip(passes, opasses))
+    assert sum(res[4][1]) < sum(res[0][1])
+    assert np.abs(res[4][0][2] - res[0][0][2]).max() <= 1e-11
+
+
+def test_accelerated_reversible(model):
+    """NVE, accelerated iteration to 1e-14: n steps with dt then n with -dt"""
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    n = 4
+    sc = dict(B0=(0, 0, 2.0), sc_tol=1e-14, sc_max=80, sc_depth=3)
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v0, colour=s.colour,
+                      params=_params(nepspin, dt=1.0, **sc))
+    sim.integrate(n)
+    pos, vel, spin, _ = sim.state()
+    sim.close()
+    sim = nepspin.Sim(model, s.types, pos, spin, s.box, s.pbc, vel=vel, colour=s.colour,
+                      params=_params(nepspin, dt=-1.0, **sc))
+    sim.integrate(n)
+    pos1, vel1, spin1, _ = sim.state()
+    sim.close()
+    dp = np.abs(min_image_delta(pos1, s.pos, s.box, s.pbc)).max()
+    dv, ds = np.abs(vel1 - v0).max(), np.abs(spin1 - s.spin).max()
+    print(f"accelerated reversibility over {n} steps: pos {dp:.2e} vel {dv:.2e} spin {ds:.2e}", flush=True)
+    assert dp <= 1e-10 and dv <= 1e-10 and ds <= 1e-10
