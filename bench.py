@@ -94,6 +94,16 @@ def flops_per_step(group, pc, k_corr=1):
         # per pair: geometry/basis+derivative 115, radial dg 18, record 20; Fe-Fe: 8 more
         # channel values 144 + force/field terms 90; Fe-Ge: 36 + 30; per atom contractions
         return pc["R"] * 153 + fe_centre_fe * 234 + fe_centre_ge * 66 + Nfe * 5 * 162 + N * 2 * 162
+    if group == "couplings":
+        # per spin-step pass. Radial-set assembly: per spin carrier the four channel
+        # contractions 810; per Fe-Fe pair geometry/basis 80, three coupling values and
+        # the single-ion weight 72, its tensor 21; per Fe-Ge pair 80 + 18 + 21.
+        # Spin-angular part: per spin carrier P = Fp^sa A 168; per Fe-Fe pair inside
+        # rc_A geometry/basis 75, g^sa 126, harmonics 50, contraction 336 + 48.
+        # Symmetrisation: per Fe-Fe pair geometry and rhat 33
+        per_pass = (Nfe * (810 + 168) + fe_centre_fe * (173 + 33) + fe_centre_ge * 119
+                    + pc["A_fefe"] * 635)
+        return (1 + k_corr) * per_pass
     if group == "readout":
         # 2 x (104 x 64) FMA per atom + tanh, energy and gradient
         per = 2 * 2 * 104 * 64 + 64 * 30
@@ -155,6 +165,28 @@ def run_slab(model, nepspin, n_steps):
     return {"workload": "FeGe B20 slab 256x256x8 cells, 4,194,304 atoms, periodic x,y, free z, helix 700 A, "
                         "T 150->280 K, B 0->1 T over 20,000 steps", "steps": n_steps,
             "fp32_mixed": sim_rate(model, nepspin, s, v, ip, "fp32", n_steps)}
+
+
+def run_self_consistent(model, nepspin, s, v, kw, n_steps, k1_ms_per_step, tol=1e-12):
+    """The spin step iterated to a tolerance on the same workload, plain and
+    with Anderson mixing (depth 3): passes per step and the cost of a step
+    against the fixed K_corr = 1 step."""
+    out = {"workload": "same system and schedule, FP64, spin residual <= %g" % tol, "steps": n_steps}
+    for key, depth in (("plain", 0), ("anderson_depth3", 3)):
+        ip = nepspin.integrator_params(**dict(kw, sc_tol=tol, sc_max=50, sc_depth=depth))
+        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                          precision="fp64")
+        sim.integrate(2, observables=False)
+        t0 = time.perf_counter()
+        ob = sim.integrate(n_steps)
+        t1 = time.perf_counter()
+        sim.close()
+        ms = 1e3 * (t1 - t0) / n_steps
+        out[key] = {"value": s.n * n_steps / (t1 - t0), "unit": "atom-steps/s", "ms_per_step": round(ms, 3),
+                    "passes_mean": float(ob[:, 9].mean()), "passes_min": int(ob[:, 9].min()),
+                    "passes_max": int(ob[:, 9].max()), "final_change_max": float(ob[:, 10].max()),
+                    "cost_vs_kcorr1": round(ms / k1_ms_per_step, 3)}
+    return out
 
 
 def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
@@ -251,6 +283,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent midpoint leg")
+    ap.add_argument("--sc-steps", type=int, default=20)
     ap.add_argument("--no-large", action="store_true", help="skip the 7.1M-atom precision form and the 4.2M slab")
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--serving-requests", type=int, default=24)
@@ -378,6 +412,10 @@ def main():
         extra["fp32_mixed"] = f32
         print(f"fp32-mixed: {K} steps in {dt32:.3f} s -> {s.n * K / dt32:.4e} atom-steps/s (dominant: {dom32})",
               file=sys.stderr, flush=True)
+
+    if not args.no_sc:
+        extra["self_consistent"] = run_self_consistent(model, nepspin, s, v0, kw, args.sc_steps, 1e3 * dt64 / K)
+        print(f"self-consistent: {extra['self_consistent']}", file=sys.stderr, flush=True)
 
     if not args.no_serving:
         extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)

@@ -114,18 +114,21 @@ def fege_lattice(nx: int, ny: int, nz: int, *, seed: int = SEED_STATE,
 
 
 def colour_periodic(nx: int, ny: int, nz: int, pbc) -> np.ndarray | None:
-    """colour = site + 4*(cx%2 + 2*(cy%2) + 4*(cz%2)) on Fe, -1 on Ge (32 colours).
+    """colour = site + 4*k on Fe, -1 on Ge (16 colours), k = ((cx - cz) % 2) +
+    2*((cy - cz) % 2): the cells of one class k form a body-centred lattice of
+    cell offsets (all three even or all three odd), so two Fe of one colour are
+    one site apart by at least a*sqrt(3) = 8.14 A, beyond rc_R + skin.
 
-    Valid only when every periodic cell count is even (the parity classes must
-    wrap consistently); returns None otherwise.
+    Valid only when every periodic cell count is even (the classes must wrap
+    consistently); returns None otherwise.
     """
     for c, p in zip((nx, ny, nz), pbc):
         if p and c % 2:
             return None
     cx, cy, cz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
-    par = (cx % 2 + 2 * (cy % 2) + 4 * (cz % 2)).ravel()
+    k = (((cx - cz) % 2) + 2 * ((cy - cz) % 2)).ravel()
     site = np.arange(8)
-    col = site[None, :] + 4 * par[:, None]
+    col = site[None, :] + 4 * k[:, None]
     col[:, 4:] = -1
     return col.reshape(-1).astype(np.int32)
 
