@@ -6,6 +6,7 @@
 namespace nep {
 
 constexpr int MAXFE = 64;     // listed spin-carrying neighbours kept for the spin couplings
+constexpr int RCOEF = 4 * NB; // per-atom contracted radial-set coefficients
 
 // flags[] words
 enum { F_REBUILD = 0, F_OVERFLOW = 1, F_COLOUR = 2, F_NONFINITE = 3, NFLAGS = 8 };
@@ -44,7 +45,7 @@ struct ModelDev {
 template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
-    real *pbR;                  // radial pair records [MAXR][N][3]: dE_i/dd_ij (radial, single-ion) at [slot of i in j's row][j]
+    real *rcoef;                // [N][2][2 NB]: radial and single-ion coefficients contracted with the atom's Fp, per neighbour species
     real *pbM;                  // magnetic pair records [MAXFE][N_fe][6]: dE_i/dd_ij, dE_i/ds_j (exchange, DMI, anisotropic), likewise
     real *ownM;                 // [N_fe][6]: magnetic-pair sum_j dE_i/dd_ij, dE_i/ds_i
     real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise

@@ -720,10 +720,63 @@ __device__ inline void put3(real *pb, size_t idx, const real G[3]) {
     p[2] = G[2];
 }
 
+// Per atom i of species t, its radial-set coefficients contracted with its
+// own Fp, for each neighbour species p: CR_p[k] = sum_n c^R_{2t+p}[n][k] Fp^R_n
+// and, on spin carriers, CS_p[k] = sum_n c^si_{2t+p}[n][k] Fp^si_n (zero on
+// the others). Block [N][p][CR, CS]: a neighbour reads the NB or 2 NB values
+// of its own species.
+template <typename real>
+__global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restrict__ C, Work<real> W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N) return;
+    const bool fe = i < S.N_fe;
+    const int t = fe ? 0 : 1;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    real *o = W.rcoef + (size_t)i * RCOEF;
+#pragma unroll 1
+    for (int p = 0; p < 2; p++) {
+        real CR[NB], CS[NB];
+        contract((C + P_CR) + (2 * t + p) * NR * NB, Fp + D_R, NR, CR);
+        if (fe) {
+            contract((C + P_CSI) + p * NR * NB, Fp + D_SI, NR, CS);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NB; k++) CS[k] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            o[p * 2 * NB + k] = CR[k];
+            o[p * 2 * NB + NB + k] = CS[k];
+        }
+    }
+}
+
 // Structural part of the radial-set backward pass: the radial channel of
 // every pair and the single-ion term of spin-carrying centres, lane per atom.
-// Record of pair (i,j): dE_i/dd_ij (these channels), stored where j's gather
-// reads it. Own sums: sum_j dE_i/dd_ij and dE_i/ds_i (single-ion and onsite).
+// Both halves of each pair come from this lane: G_ij = dE_i/dd_ij from the
+// atom's own coefficients and G_ji = dE_j/dd_ji from the neighbour's
+// contracted block (and its spin), so F_i = sum_j (G_ij - G_ji) needs no
+// pair records. Own sums: F_i and dE_i/ds_i (single-ion and onsite).
+template <typename real>
+__device__ inline void partner_radial(const real *cj, bool fe_j, const d4 *spin, int j, real r, real ir,
+                                      const real rh[3], const real f[NB], const real df[NB], real Gj[3]) {
+    const real dgR = dotc(cj, df);
+    if (fe_j) {
+        real sj[3];
+        load_spin(spin, j, sj);
+        const real gS = dotc(cj + NB, f), dgS = dotc(cj + NB, df);
+        // rhat_ji = -rhat_ij
+        const real a = -(sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2]);
+        const real radial = dgR + dgS * a * a;
+        const real ks = real(2) * gS * a * ir;
+#pragma unroll
+        for (int x = 0; x < 3; x++) Gj[x] = -radial * rh[x] + ks * (sj[x] + a * rh[x]);
+    } else {
+#pragma unroll
+        for (int x = 0; x < 3; x++) Gj[x] = -dgR * rh[x];
+    }
+}
+
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
     bool fe;
@@ -735,7 +788,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
     const int cnt = S.cntR[i], nfe = S.cntFeR[i];
     const size_t ld = S.N;
     const real *Fp = W.Fp + (size_t)i * DP;
-    const real zero3[3] = {0, 0, 0};
+    const int toff = (fe ? 0 : 1) * 2 * NB;   // the neighbours' blocks for this species
     real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
     if (fe) {
         real si[3];
@@ -758,13 +811,9 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 j1_ = j2_;
                 p1_ = S.pos[j1_];
                 if (s + 2 < e) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
-                const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
                 const real r2 = geom_p(R, pi, pj_, d);
-                if (r2 >= rc2) {
-                    put3(W.pbR, dst, zero3);
-                    continue;
-                }
+                if (r2 >= rc2) continue;
                 real r, ir;
                 r_and_inv(r2, r, ir);
                 const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
@@ -775,14 +824,14 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 const real a = si[0] * rh[0] + si[1] * rh[1] + si[2] * rh[2];
                 const real radial = dgR + dgS * a * a;
                 const real ks = real(2) * gS * a * ir;
-                real G[3];
+                real Gj[3];
+                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) {
-                    G[x] = radial * rh[x] + ks * (si[x] - a * rh[x]);
+                    const real G = radial * rh[x] + ks * (si[x] - a * rh[x]);
                     h[x] += real(2) * gS * a * rh[x];
-                    F[x] += G[x];
+                    F[x] += G - Gj[x];
                 }
-                put3(W.pbR, dst, G);
             }
         }
     } else {
@@ -799,23 +848,19 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 j1_ = j2_;
                 p1_ = S.pos[j1_];
                 if (s + 2 < e) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
-                const size_t dst = (size_t)S.revR[s * ld + i] * ld + j;
                 real d[3];
                 const real r2 = geom_p(R, pi, pj_, d);
-                if (r2 >= rc2) {
-                    put3(W.pbR, dst, zero3);
-                    continue;
-                }
+                if (r2 >= rc2) continue;
                 real r, ir;
                 r_and_inv(r2, r, ir);
+                const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
                 real f[NB], df[NB];
                 radial_basis_d(r, rc, f, df);
-                const real g = dotk(CR, df) * ir;
-                const real G[3] = {g * d[0], g * d[1], g * d[2]};
-                F[0] += G[0];
-                F[1] += G[1];
-                F[2] += G[2];
-                put3(W.pbR, dst, G);
+                const real g = dotk(CR, df);
+                real Gj[3];
+                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, part == 0, S.spin, j, r, ir, rh, f, df, Gj);
+#pragma unroll
+                for (int x = 0; x < 3; x++) F[x] += g * rh[x] - Gj[x];
             }
         }
     }
@@ -1094,7 +1139,7 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[1] = a[4];
         h[2] = a[5];
     }
-    const int nr = S.cntR[k], na = S.cntA[k];
+    const int na = S.cntA[k];
     {
         const real *a = W.ownA + (size_t)k * 6;
         F[0] += a[0];
@@ -1105,13 +1150,6 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[2] += a[5];
     }
     // partner records sit in this atom's own slots: the reads are coalesced
-#pragma unroll 4
-    for (int s = 0; s < nr; s++) {
-        const real *p = W.pbR + ((size_t)s * ld + k) * 3;
-        F[0] -= p[0];
-        F[1] -= p[1];
-        F[2] -= p[2];
-    }
     if (fe) {
         const size_t lf = S.N_fe;
         const real *a = W.ownM + (size_t)k * 6;
@@ -1376,6 +1414,7 @@ template <typename real>
 void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(256)
+    hipLaunchKernelGGL(k_radial_coef<real>, dim3(nblk(S.N, 256)), dim3(256), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_bwd_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M.cR, W, nb_fe);
     if (nb_fe) hipLaunchKernelGGL(k_bwd_mag<real>, dim3(nb_fe), dim3(256), 0, st, S, M.cR, W);
 }
