@@ -7,6 +7,7 @@ namespace nep {
 
 constexpr int MAXFE = 64;     // listed spin-carrying neighbours kept for the spin couplings
 constexpr int RCOEF = 4 * NB; // per-atom contracted radial-set coefficients
+constexpr int MCOEF = 3 * NB; // per-spin-carrier contracted magnetic pair coefficients
 
 // flags[] words
 enum { F_REBUILD = 0, F_OVERFLOW = 1, F_COLOUR = 2, F_NONFINITE = 3, NFLAGS = 8 };
@@ -46,7 +47,7 @@ template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
     real *rcoef;                // [N][2][2 NB]: radial and single-ion coefficients contracted with the atom's Fp, per neighbour species
-    real *pbM;                  // magnetic pair records [MAXFE][N_fe][6]: dE_i/dd_ij, dE_i/ds_j (exchange, DMI, anisotropic), likewise
+    real *mcoef;                // [N_fe][3 NB]: exchange, DMI, anisotropic-exchange coefficients contracted with the atom's Fp
     real *ownM;                 // [N_fe][6]: magnetic-pair sum_j dE_i/dd_ij, dE_i/ds_i
     real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise
     real *ownR;                 // [N][6]: radial and single-ion sum_j dE_i/dd_ij, dE_i/ds_i

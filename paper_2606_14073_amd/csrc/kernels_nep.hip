@@ -712,19 +712,12 @@ __device__ inline void put_pair(real *pb, size_t idx, const real G[3], const rea
     p[5] = h[2];
 }
 
-template <typename real>
-__device__ inline void put3(real *pb, size_t idx, const real G[3]) {
-    real *p = pb + idx * 3;
-    p[0] = G[0];
-    p[1] = G[1];
-    p[2] = G[2];
-}
-
 // Per atom i of species t, its radial-set coefficients contracted with its
 // own Fp, for each neighbour species p: CR_p[k] = sum_n c^R_{2t+p}[n][k] Fp^R_n
 // and, on spin carriers, CS_p[k] = sum_n c^si_{2t+p}[n][k] Fp^si_n (zero on
 // the others). Block [N][p][CR, CS]: a neighbour reads the NB or 2 NB values
-// of its own species.
+// of its own species. Spin carriers also get the exchange, DMI and
+// anisotropic-exchange coefficients (Fe-Fe pairs), [N_fe][CE, CD, CA].
 template <typename real>
 __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -748,6 +741,19 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
             o[p * 2 * NB + k] = CR[k];
             o[p * 2 * NB + NB + k] = CS[k];
         }
+    }
+    if (fe) {
+        real CX[NB];
+        real *m = W.mcoef + (size_t)i * MCOEF;
+        contract((C + P_CEX), Fp + D_EX, NR, CX);
+#pragma unroll
+        for (int k = 0; k < NB; k++) m[k] = CX[k];
+        contract((C + P_CDM), Fp + D_DM, NR, CX);
+#pragma unroll
+        for (int k = 0; k < NB; k++) m[NB + k] = CX[k];
+        contract((C + P_CAN), Fp + D_AN, NR, CX);
+#pragma unroll
+        for (int k = 0; k < NB; k++) m[2 * NB + k] = CX[k];
     }
 }
 
@@ -869,10 +875,11 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
 
 // Magnetic pair part of the radial-set backward pass: exchange, DMI and
 // anisotropic exchange over the spin-carrying neighbours of spin-carrying
-// centres, lane per atom. Record of pair (i,j): dE_i/dd_ij and dE_i/ds_j of
-// these channels at [slot of i in j's row][j] (spin carriers lead every row,
-// so that slot is below the spin-neighbour capacity of a valid list). Own
-// sums: sum_j dE_i/dd_ij and dE_i/ds_i.
+// centres, lane per atom. The partner's pair energy e_ji has the form of e_ij
+// in terms of d_ij (r_hat_ji.(s_j x s_i) = r_hat_ij.(s_i x s_j), and likewise
+// for the anisotropic product), so a pair's force on i and field on s_i are
+// the formulas of e_ij with the summed coefficients C_i + C_j: no records.
+// Sums: F_i and dE/ds_i of these channels.
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -881,16 +888,16 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc;
     const int nfe = min(S.cntFeR[i], MAXFE);
-    const size_t ld = S.N, lf = S.N_fe;
-    const real *Fp = W.Fp + (size_t)i * DP;
-    const real zero3[3] = {0, 0, 0};
+    const size_t ld = S.N;
     real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
     real si[3];
     load_spin(S.spin, i, si);
-    real CE[NB], CD[NB], CA[NB];
-    contract((C + P_CEX), Fp + D_EX, NR, CE);
-    contract((C + P_CDM), Fp + D_DM, NR, CD);
-    contract((C + P_CAN), Fp + D_AN, NR, CA);
+    real Ci[3 * NB];
+    {
+        const real *m = W.mcoef + (size_t)i * MCOEF;
+#pragma unroll
+        for (int k = 0; k < 3 * NB; k++) Ci[k] = m[k];
+    }
     // neighbour index two slots ahead, its position and spin one slot ahead
     int j1_ = 0 < nfe ? S.nbrR[i] : 0;
     int j2_ = 1 < nfe ? S.nbrR[ld + i] : j1_;
@@ -902,19 +909,22 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
         p1_ = S.pos[j1_];
         v1_ = S.spin[j1_];
         if (s + 2 < nfe) j2_ = S.nbrR[(size_t)(s + 2) * ld + i];
-        const int t = S.revR[s * ld + i];
-        const size_t dst = (size_t)t * lf + j;
         real d[3];
         const real r2 = geom_p(R, pi, pj_, d);
-        if (r2 >= rc2) {
-            if (t < MAXFE) put_pair(W.pbM, dst, zero3, zero3);
-            continue;
-        }
+        if (r2 >= rc2) continue;
         real r, ir;
         r_and_inv(r2, r, ir);
         const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
         real f[NB], df[NB];
         radial_basis_d(r, rc, f, df);
+        const real *mj = W.mcoef + (size_t)j * MCOEF;
+        real CE[NB], CD[NB], CA[NB];
+#pragma unroll
+        for (int k = 0; k < NB; k++) {
+            CE[k] = Ci[k] + mj[k];
+            CD[k] = Ci[NB + k] + mj[NB + k];
+            CA[k] = Ci[2 * NB + k] + mj[2 * NB + k];
+        }
         const real sj[3] = {(real)vj_.x, (real)vj_.y, (real)vj_.z};
         const real gE = dotk(CE, f), dgE = dotk(CE, df);
         const real gD = dotk(CD, f), dgD = dotk(CD, df);
@@ -928,21 +938,13 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
         const real radial = dgE * ss + dgD * w + dgA * a * b;
         const real sjxr[3] = {sj[1] * rh[2] - sj[2] * rh[1], sj[2] * rh[0] - sj[0] * rh[2],
                               sj[0] * rh[1] - sj[1] * rh[0]};
-        real G[3], hq[3];
         const real kd = gD * ir, ka = gA * ir;
 #pragma unroll
         for (int x = 0; x < 3; x++) {
             const real pa = si[x] - a * rh[x], pb = sj[x] - b * rh[x];
-            G[x] = radial * rh[x] + kd * (c[x] - w * rh[x]) + ka * (b * pa + a * pb);
+            F[x] += radial * rh[x] + kd * (c[x] - w * rh[x]) + ka * (b * pa + a * pb);
             h[x] += gE * sj[x] + gD * sjxr[x] + gA * b * rh[x];
-            hq[x] = gE * si[x] + gA * a * rh[x];
-            F[x] += G[x];
         }
-        // dE_i/ds_j of the DMI term: g (rhat x s_i)
-        hq[0] += gD * (rh[1] * si[2] - rh[2] * si[1]);
-        hq[1] += gD * (rh[2] * si[0] - rh[0] * si[2]);
-        hq[2] += gD * (rh[0] * si[1] - rh[1] * si[0]);
-        if (t < MAXFE) put_pair(W.pbM, dst, G, hq);
     }
     put_pair(W.ownM, (size_t)i, F, h);
 }
@@ -1151,7 +1153,6 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     }
     // partner records sit in this atom's own slots: the reads are coalesced
     if (fe) {
-        const size_t lf = S.N_fe;
         const real *a = W.ownM + (size_t)k * 6;
         F[0] += a[0];
         F[1] += a[1];
@@ -1159,17 +1160,6 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
         h[0] += a[3];
         h[1] += a[4];
         h[2] += a[5];
-        const int nm = min(S.cntFeR[k], MAXFE);
-#pragma unroll 4
-        for (int s = 0; s < nm; s++) {
-            const real *p = W.pbM + ((size_t)s * lf + k) * 6;
-            F[0] -= p[0];
-            F[1] -= p[1];
-            F[2] -= p[2];
-            h[0] += p[3];
-            h[1] += p[4];
-            h[2] += p[5];
-        }
     }
 #pragma unroll 4
     for (int s = 0; s < na; s++) {
