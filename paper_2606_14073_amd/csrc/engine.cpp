@@ -168,7 +168,7 @@ static size_t bytes_per_atom(sl_precision prec) {
     const size_t rs = prec == SL_FP64 ? 8 : 4;
     size_t b = 9 * sizeof(d4) + 9 * 4 + 2 * MAXR * 4 + 3 * MAXA * 4;
     b += rs * (2 * DP + 1 + NA * NAB + 12 + RCOEF + 4 * MAXA);
-    b += (rs * (MAXFE * 9 + MCOEF + 14) + 4 * (MAXFE + 3) + sizeof(d4)) / 2 + 64;   // per spin carrier, half the atoms
+    b += (rs * (MAXFE * 7 + MCOEF + 14) + 4 * (MAXFE + 3) + sizeof(d4)) / 2 + 64;   // per spin carrier, half the atoms
     return b;
 }
 
@@ -338,7 +338,7 @@ struct Engine {
         w.pbA = take((size_t)MAXA * c * 4);
         w.ownR = take(c * 6);
         w.ownA = take(c * 6);
-        w.craw = take((size_t)MAXFE * cf * 3);
+        w.csa = take((size_t)MAXFE * cf);
         w.cpl = take((size_t)MAXFE * cf * 6);
         w.selfc = take(cf * 8);
         w.cpl_j = cpl_j;
@@ -349,7 +349,7 @@ struct Engine {
     static size_t work_count(size_t c, size_t cf) {
         auto r = [](size_t n) { return (n + 63) & ~(size_t)63; };
         return r(c * DP) * 2 + r(c) + r(c * NA * NAB) + r(c * RCOEF) + r(cf * MCOEF) +
-               r(cf * 6) + r((size_t)MAXA * c * 4) + 2 * r(c * 6) + r((size_t)MAXFE * cf * 3) + r((size_t)MAXFE * cf * 6) +
+               r(cf * 6) + r((size_t)MAXA * c * 4) + 2 * r(c * 6) + r((size_t)MAXFE * cf) + r((size_t)MAXFE * cf * 6) +
                r(cf * 8);
     }
 

@@ -52,7 +52,7 @@ struct Work {
     real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise
     real *ownR;                 // [N][6]: radial and single-ion sum_j dE_i/dd_ij, dE_i/ds_i
     real *ownA;                 // [N][6]: angular-set sum_j dE_i/dd_ij, sum_j h_ij s_j
-    real *craw;                 // [MAXFE][N_fe][3]: a_ij, d_ij, b_ij (atom order)
+    real *csa;                  // [MAXFE][N_fe]: spin-angular part of a_ij at j's slot in i's rc_R row (atom order)
     real *cpl;                  // [MAXFE][N_fe][6]: J, D, K, rhat (colour-list order)
     real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i (colour-list order)
     int *cpl_j;                 // [MAXFE][N_fe]: neighbour of each coupling (colour-list order)

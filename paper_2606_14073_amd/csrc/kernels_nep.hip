@@ -719,6 +719,20 @@ __device__ inline void put_pair(real *pb, size_t idx, const real G[3], const rea
 // of its own species. Spin carriers also get the exchange, DMI and
 // anisotropic-exchange coefficients (Fe-Fe pairs), [N_fe][CE, CD, CA].
 template <typename real>
+__device__ inline void mag_coef(const real *__restrict__ C, const real *Fp, real *m) {
+    real CX[NB];
+    contract((C + P_CEX), Fp + D_EX, NR, CX);
+#pragma unroll
+    for (int k = 0; k < NB; k++) m[k] = CX[k];
+    contract((C + P_CDM), Fp + D_DM, NR, CX);
+#pragma unroll
+    for (int k = 0; k < NB; k++) m[NB + k] = CX[k];
+    contract((C + P_CAN), Fp + D_AN, NR, CX);
+#pragma unroll
+    for (int k = 0; k < NB; k++) m[2 * NB + k] = CX[k];
+}
+
+template <typename real>
 __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N) return;
@@ -742,19 +756,16 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
             o[p * 2 * NB + NB + k] = CS[k];
         }
     }
-    if (fe) {
-        real CX[NB];
-        real *m = W.mcoef + (size_t)i * MCOEF;
-        contract((C + P_CEX), Fp + D_EX, NR, CX);
-#pragma unroll
-        for (int k = 0; k < NB; k++) m[k] = CX[k];
-        contract((C + P_CDM), Fp + D_DM, NR, CX);
-#pragma unroll
-        for (int k = 0; k < NB; k++) m[NB + k] = CX[k];
-        contract((C + P_CAN), Fp + D_AN, NR, CX);
-#pragma unroll
-        for (int k = 0; k < NB; k++) m[2 * NB + k] = CX[k];
-    }
+    if (fe) mag_coef(C, Fp, W.mcoef + (size_t)i * MCOEF);
+}
+
+// the exchange, DMI and anisotropic-exchange coefficients alone, spin carriers
+// (the spin-step passes)
+template <typename real>
+__global__ void __launch_bounds__(256) k_mag_coef(Sys S, const real *__restrict__ C, Work<real> W) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.N_fe) return;
+    mag_coef(C, W.Fp + (size_t)i * DP, W.mcoef + (size_t)i * MCOEF);
 }
 
 // Structural part of the radial-set backward pass: the radial channel of
@@ -1197,82 +1208,6 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
 //           + sum_i s_i^T A_i s_i + o_i |s_i|^2  (+ Zeeman)
 // -------------------------------------------------------------------------
 
-template <typename real>
-__global__ void __launch_bounds__(256) k_assemble_radial(Sys S, const real *__restrict__ C, Work<real> W) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N_fe) return;
-    const Img R = img_of(S.rep[S.rid[i]]);
-    const d4 pi = S.pos[i];
-    const real rc = (real)RC_R, rc2 = rc * rc;
-    const int cnt = S.cntR[i], nfe_all = S.cntFeR[i], nfe = min(nfe_all, MAXFE);
-    const size_t ld = S.N, lf = S.N_fe;
-    const real *Fp = W.Fp + (size_t)i * DP;
-    real Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
-    {
-        real CE[NB], CD[NB], CA[NB], CS[NB];
-        contract((C + P_CEX), Fp + D_EX, NR, CE);
-        contract((C + P_CDM), Fp + D_DM, NR, CD);
-        contract((C + P_CAN), Fp + D_AN, NR, CA);
-        contract((C + P_CSI), Fp + D_SI, NR, CS);
-        for (int s = 0; s < nfe; s++) {
-            const int j = S.nbrR[s * ld + i];
-            real d[3];
-            const real r2 = geom(S, R, pi, j, d);
-            real *c = W.craw + ((size_t)s * lf + i) * 3;
-            if (r2 >= rc2) {
-                c[0] = c[1] = c[2] = 0;
-                continue;
-            }
-            real r, ir;
-            r_and_inv(r2, r, ir);
-            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-            real f[NB];
-            radial_basis(r, rc, f);
-            c[0] = dotk(CE, f);
-            c[1] = dotk(CD, f);
-            c[2] = dotk(CA, f);
-            const real g = dotk(CS, f);
-            Axx += g * rh[0] * rh[0];
-            Ayy += g * rh[1] * rh[1];
-            Azz += g * rh[2] * rh[2];
-            Axy += g * rh[0] * rh[1];
-            Axz += g * rh[0] * rh[2];
-            Ayz += g * rh[1] * rh[2];
-        }
-    }
-    {
-        real CS[NB];
-        contract((C + P_CSI) + 1 * NR * NB, Fp + D_SI, NR, CS);
-        for (int s = nfe_all; s < cnt; s++) {
-            const int j = S.nbrR[s * ld + i];
-            real d[3];
-            const real r2 = geom(S, R, pi, j, d);
-            if (r2 >= rc2) continue;
-            real r, ir;
-            r_and_inv(r2, r, ir);
-            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-            real f[NB];
-            radial_basis(r, rc, f);
-            const real g = dotk(CS, f);
-            Axx += g * rh[0] * rh[0];
-            Ayy += g * rh[1] * rh[1];
-            Azz += g * rh[2] * rh[2];
-            Axy += g * rh[0] * rh[1];
-            Axz += g * rh[0] * rh[2];
-            Ayz += g * rh[1] * rh[2];
-        }
-    }
-    real *o = W.selfc + (size_t)S.colpos[i] * 8;
-    o[0] = Axx;
-    o[1] = Ayy;
-    o[2] = Azz;
-    o[3] = Axy;
-    o[4] = Axz;
-    o[5] = Ayz;
-    o[6] = Fp[D_OS];
-    o[7] = 0;
-}
-
 // spin-angular part of a_ij: sum_n g^sa_n(r_ij) sum_lm Fp^sa_nl A_nlm Y_lm(rhat_ij);
 // lanes take the atom's spin-carrying neighbours round robin, P = Fp^sa A in LDS
 constexpr int PSTRIDE = NA * NLM + 1;
@@ -1321,45 +1256,111 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
             a += w * Y[m];
         }
         const int sr = S.a2r[s * ld + i];
-        if (sr < MAXFE) W.craw[((size_t)sr * lf + i) * 3] += a;
+        if (sr < MAXFE) W.csa[(size_t)sr * lf + i] = a;
     }
 }
 
-// J_ij = a_ij + a_ji, D_ij = d_ij + d_ji, K_ij = b_ij + b_ji, with rhat_ij,
-// stored compactly for the pairs inside rc_R only (in list order), so the
-// sweep's split of a spin's couplings over lanes depends on the positions
-// alone and not on which farther atoms the Verlet list happens to hold
+// Couplings of the spin-carrying pairs inside rc_R, J_ij = a_ij + a_ji,
+// D_ij = d_ij + d_ji, K_ij = b_ij + b_ji: the radial-set parts are sums over
+// the basis with the summed contracted coefficients of both spins, the
+// spin-angular parts (inside rc_A) the two atoms' records. Stored with rhat_ij
+// compactly in list order, so the sweep's split of a spin's couplings over
+// lanes depends on the positions alone and not on which farther atoms the
+// Verlet list happens to hold. The same pass sums the single-ion tensor
+// A_i = sum_j g^si(r_ij) rhat rhat^T over all neighbours.
 template <typename real>
-__global__ void __launch_bounds__(256) k_assemble_sym(Sys S, Work<real> W) {
+__global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N_fe) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
-    const int nfe = min(S.cntFeR[i], MAXFE);
+    const real rc = (real)RC_R, rc2 = rc * rc, rca = (real)RC_A, rca2 = rca * rca;   // as the angular pass
+    const int cnt = S.cntR[i], nfe_all = S.cntFeR[i], nfe = min(nfe_all, MAXFE);
     const size_t ld = S.N, lf = S.N_fe;
     const int p = S.colpos[i];
-    const real rc2 = (real)(RC_R * RC_R);
-    int cs = 0;
-    for (int s = 0; s < nfe; s++) {
-        const int j = S.nbrR[s * ld + i];
-        real d[3];
-        const real r2 = geom(S, R, pi, j, d);
-        if (r2 >= rc2) continue;
-        const int t = min(S.revR[s * ld + i], MAXFE - 1);
-        const real *a = W.craw + ((size_t)s * lf + i) * 3;
-        const real *b = W.craw + ((size_t)t * lf + j) * 3;
-        real r, ir;
-        r_and_inv(r2, r, ir);
-        real *c = W.cpl + ((size_t)cs * lf + p) * 6;
-        c[0] = a[0] + b[0];
-        c[1] = a[1] + b[1];
-        c[2] = a[2] + b[2];
-        c[3] = d[0] * ir;
-        c[4] = d[1] * ir;
-        c[5] = d[2] * ir;
-        W.cpl_j[(size_t)cs * lf + p] = j;
-        cs++;
+    const real *Fp = W.Fp + (size_t)i * DP;
+    real Ci[MCOEF];
+    {
+        const real *m = W.mcoef + (size_t)i * MCOEF;
+#pragma unroll
+        for (int k = 0; k < MCOEF; k++) Ci[k] = m[k];
     }
+    real Axx = 0, Ayy = 0, Azz = 0, Axy = 0, Axz = 0, Ayz = 0;
+    int cs = 0;
+    {
+        real CS[NB];
+        contract((C + P_CSI), Fp + D_SI, NR, CS);
+        for (int s = 0; s < nfe; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            real r, ir;
+            r_and_inv(r2, r, ir);
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB];
+            radial_basis(r, rc, f);
+            const real *mj = W.mcoef + (size_t)j * MCOEF;
+            real J = 0, D = 0, K = 0;
+#pragma unroll
+            for (int k = 0; k < NB; k++) {
+                J += (Ci[k] + mj[k]) * f[k];
+                D += (Ci[NB + k] + mj[NB + k]) * f[k];
+                K += (Ci[2 * NB + k] + mj[2 * NB + k]) * f[k];
+            }
+            if (r2 < rca2) {
+                const int t = min(S.revR[s * ld + i], MAXFE - 1);
+                J += W.csa[(size_t)s * lf + i] + W.csa[(size_t)t * lf + j];
+            }
+            const real g = dotk(CS, f);
+            Axx += g * rh[0] * rh[0];
+            Ayy += g * rh[1] * rh[1];
+            Azz += g * rh[2] * rh[2];
+            Axy += g * rh[0] * rh[1];
+            Axz += g * rh[0] * rh[2];
+            Ayz += g * rh[1] * rh[2];
+            real *c = W.cpl + ((size_t)cs * lf + p) * 6;
+            c[0] = J;
+            c[1] = D;
+            c[2] = K;
+            c[3] = rh[0];
+            c[4] = rh[1];
+            c[5] = rh[2];
+            W.cpl_j[(size_t)cs * lf + p] = j;
+            cs++;
+        }
+    }
+    {
+        real CS[NB];
+        contract((C + P_CSI) + 1 * NR * NB, Fp + D_SI, NR, CS);
+        for (int s = nfe_all; s < cnt; s++) {
+            const int j = S.nbrR[s * ld + i];
+            real d[3];
+            const real r2 = geom(S, R, pi, j, d);
+            if (r2 >= rc2) continue;
+            real r, ir;
+            r_and_inv(r2, r, ir);
+            const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+            real f[NB];
+            radial_basis(r, rc, f);
+            const real g = dotk(CS, f);
+            Axx += g * rh[0] * rh[0];
+            Ayy += g * rh[1] * rh[1];
+            Azz += g * rh[2] * rh[2];
+            Axy += g * rh[0] * rh[1];
+            Axz += g * rh[0] * rh[2];
+            Ayz += g * rh[1] * rh[2];
+        }
+    }
+    real *o = W.selfc + (size_t)p * 8;
+    o[0] = Axx;
+    o[1] = Ayy;
+    o[2] = Azz;
+    o[3] = Axy;
+    o[4] = Axz;
+    o[5] = Ayz;
+    o[6] = Fp[D_OS];
+    o[7] = 0;
     W.cpl_n[p] = cs;
 }
 
@@ -1425,9 +1426,9 @@ void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st) {
 template <typename real>
 void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N_fe == 0) return;
-    hipLaunchKernelGGL(k_assemble_radial<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
+    hipLaunchKernelGGL(k_mag_coef<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, ANG_ATOMS)), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
-    hipLaunchKernelGGL(k_assemble_sym<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, W);
+    hipLaunchKernelGGL(k_assemble_pairs<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
 }
 
 #define NEP_INST(real)                                                                                           \
