@@ -973,23 +973,33 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
 // (dE_i/dd_ij, h_ij); the gather forms every sum in slot order.
 // -------------------------------------------------------------------------
 
-constexpr int QSTRIDE = 2 * NA * NLM + 1;
+// Spin carriers and the other species run as two launches: the latter keep
+// no QS block, so that twice as many of their workgroups fit in a CU's LDS.
+template <bool FE>
+constexpr int qstride() { return (FE ? 2 : 1) * NA * NLM + 1; }
 
-template <typename real>
-__global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
+template <typename real, bool FE>
+__global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restrict__ C, Work<real> W) {
+    constexpr int QSTRIDE = qstride<FE>();
     __shared__ real sQ[ANG_ATOMS * QSTRIDE];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
-    bool fe;
-    const int i = atom_of_block(S, ANG_ATOMS, nbFe, slot, fe);
-    real *Q = sQ + slot * QSTRIDE;   // QA[n][m] then QS[n][m]
+    constexpr bool fe = FE;
+    int i = (FE ? 0 : S.N_fe) + blockIdx.x * ANG_ATOMS + slot;
+    if (i >= (FE ? S.N_fe : S.N)) i = -1;
+    real *Q = sQ + slot * QSTRIDE;   // QA[n][m], then QS[n][m] on spin carriers
     if (i >= 0) {
         const real *Fp = W.Fp + (size_t)i * DP;
         for (int x = lane; x < NA * NLM; x += 8) {
             const int n = x / NLM, m = x - n * NLM, l = l_of_lm(m) - 1;
             const real *ab = W.AB + ((size_t)i * NA + n) * NAB;
-            const real fa = Fp[D_A + 4 * n + l], fs = Fp[D_SA + 4 * n + l];
-            Q[x] = real(2) * fa * ab[m] + (fe ? fs * ab[NLM + m] : real(0));
-            Q[NA * NLM + x] = fs * ab[m];
+            const real fa = Fp[D_A + 4 * n + l];
+            if (FE) {
+                const real fs = Fp[D_SA + 4 * n + l];
+                Q[x] = real(2) * fa * ab[m] + fs * ab[NLM + m];
+                Q[NA * NLM + x] = fs * ab[m];
+            } else {
+                Q[x] = real(2) * fa * ab[m];
+            }
         }
     }
     __syncthreads();
@@ -1092,7 +1102,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
                     qa_g += qa * gA[n];
                     qa_dg += qa * dgA[n];
                 }
-                if (spins) {
+                if (FE && spins) {
 #pragma unroll
                     for (int n = 0; n < NA; n++) {
                         const real qs = Qm[NA * NLM + n * NLM + m];
@@ -1414,7 +1424,8 @@ template <typename real>
 void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(ANG_ATOMS)
-    hipLaunchKernelGGL(k_bwd_angular<real>, dim3(nb_fe + nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, nb_fe);
+    if (nb_fe) hipLaunchKernelGGL((k_bwd_angular<real, true>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
+    if (nb_ge) hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
 }
 
 template <typename real>
