@@ -852,22 +852,31 @@ static int check_view(const sl_system_view *sys, double skin) {
     return SL_OK;
 }
 
-// greedy colouring of the spin carriers (graph: r < rc_R + skin + 0.5), in index order
-static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int> &col) {
+// greedy colouring of the spin carriers (graph: r < rc_R + skin + 0.5), in
+// index order; with `keep` a repair: a spin keeps its colour unless a
+// neighbour has it, and then takes the smallest colour no neighbour has.
+// A repaired spin takes a colour none of its neighbours has, so a repair never
+// creates a conflict: only spins that share their colour with a neighbour at
+// the start can change, and they are found by looking at same-colour spins
+// alone (cells per colour), then repaired in index order.
+static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int> &col,
+                         const std::vector<int> *keep = nullptr) {
     const int64_t n = sys->n_atoms;
-    col.assign(n, -1);
+    if (keep) col = *keep;
+    else col.assign(n, -1);
     const double rc = RC_R + skin + 0.5, rc2 = rc * rc;
     std::vector<int> fe;
     for (int64_t i = 0; i < n; i++)
         if (sys->types[i] == 0) fe.push_back((int)i);
     // bin spin carriers
     int nc[3];
-    double lo[3], w[3];
+    double lo[3], w[3], ib[3];
     for (int a = 0; a < 3; a++) {
         double mn = 1e300, mx = -1e300;
+        ib[a] = sys->pbc[a] ? 1.0 / sys->box[a] : 0.0;
         for (int i : fe) {
             double x = sys->pos[3 * i + a];
-            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x / sys->box[a]);
+            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x * ib[a]);
             mn = std::min(mn, x);
             mx = std::max(mx, x);
         }
@@ -883,22 +892,30 @@ static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int
         }
         if (nc[a] > 1024) return fail(SL_E_INVALID, "colouring grid too large");
     }
-    std::vector<std::vector<int>> cells((size_t)nc[0] * nc[1] * nc[2]);
+    const size_t ncell = (size_t)nc[0] * nc[1] * nc[2];
     std::vector<int> cid(n, -1);
     for (int i : fe) {
         int c[3];
         for (int a = 0; a < 3; a++) {
             double x = sys->pos[3 * i + a] - lo[a];
-            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x / sys->box[a]);
+            if (sys->pbc[a]) x -= sys->box[a] * std::floor(x * ib[a]);
             c[a] = std::min(nc[a] - 1, std::max(0, (int)std::floor(x / w[a])));
         }
         cid[i] = (c[0] * nc[1] + c[1]) * nc[2] + c[2];
-        cells[cid[i]].push_back(i);
     }
-    for (int i : fe) {
-        const int ci = cid[i];
-        int c0 = ci / (nc[1] * nc[2]), c1 = (ci / nc[2]) % nc[1], c2 = ci % nc[2];
-        std::vector<char> used(512, 0);
+    auto dist2 = [&](int i, int j) {
+        double d2 = 0;
+        for (int a = 0; a < 3; a++) {
+            double x = sys->pos[3 * j + a] - sys->pos[3 * i + a];
+            if (sys->pbc[a]) x -= sys->box[a] * std::nearbyint(x * ib[a]);
+            d2 += x * x;
+        }
+        return d2;
+    };
+    // the 27 cells around a cell (fewer on free axes; periodic images folded)
+    auto around = [&](size_t ci, int out[27]) {
+        const int c0 = (int)(ci / ((size_t)nc[1] * nc[2])), c1 = (int)((ci / nc[2]) % nc[1]), c2 = (int)(ci % nc[2]);
+        int k = 0;
         for (int dx = -1; dx <= 1; dx++)
             for (int dy = -1; dy <= 1; dy++)
                 for (int dz = -1; dz <= 1; dz++) {
@@ -911,25 +928,75 @@ static int greedy_colour(const sl_system_view *sys, double skin, std::vector<int
                         }
                     }
                     if (!ok) continue;
-                    for (int j : cells[(cc[0] * nc[1] + cc[1]) * nc[2] + cc[2]]) {
-                        if (j == i || col[j] < 0) continue;
-                        double d2 = 0;
-                        for (int a = 0; a < 3; a++) {
-                            double x = sys->pos[3 * j + a] - sys->pos[3 * i + a];
-                            if (sys->pbc[a]) x -= sys->box[a] * std::nearbyint(x / sys->box[a]);
-                            d2 += x * x;
-                        }
-                        if (d2 < rc2 && col[j] < (int)used.size()) used[col[j]] = 1;
-                    }
+                    const int v = (cc[0] * nc[1] + cc[1]) * nc[2] + cc[2];
+                    bool dup = false;   // small periodic grids fold onto the same cell
+                    for (int q = 0; q < k; q++) dup |= out[q] == v;
+                    if (!dup) out[k++] = v;
                 }
+        return k;
+    };
+    // spin carriers by cell (counting sort)
+    std::vector<int> start(ncell + 1, 0), members(fe.size());
+    for (int i : fe) start[cid[i] + 1]++;
+    for (size_t c = 0; c < ncell; c++) start[c + 1] += start[c];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int i : fe) members[fill[cid[i]]++] = i;
+    }
+    std::vector<char> used(512, 0);
+    auto pick = [&](int i) {   // smallest colour none of i's neighbours has; col[i] if that one is free
+        std::fill(used.begin(), used.end(), 0);
+        int cells[27];
+        const int k = around(cid[i], cells);
+        for (int q = 0; q < k; q++)
+            for (int m = start[cells[q]]; m < start[cells[q] + 1]; m++) {
+                const int j = members[m];
+                if (j != i && col[j] >= 0 && col[j] < (int)used.size() && dist2(i, j) < rc2) used[col[j]] = 1;
+            }
+        if (col[i] >= 0 && col[i] < (int)used.size() && !used[col[i]]) return col[i];
         int c = 0;
         while (c < (int)used.size() && used[c]) c++;
-        col[i] = c;
+        return c;
+    };
+    if (!keep) {
+        for (int i : fe) col[i] = pick(i);
+        return SL_OK;
     }
+    // spins that share their colour with a neighbour: cells per colour
+    int ncol = 0;
+    for (int i : fe) ncol = std::max(ncol, col[i] + 1);
+    std::vector<int> cstart((size_t)ncol * ncell + 1, 0), cmem(fe.size());
+    for (int i : fe)
+        if (col[i] >= 0) cstart[(size_t)col[i] * ncell + cid[i] + 1]++;
+    for (size_t c = 0; c < (size_t)ncol * ncell; c++) cstart[c + 1] += cstart[c];
+    {
+        std::vector<int> fill(cstart.begin(), cstart.end() - 1);
+        for (int i : fe)
+            if (col[i] >= 0) cmem[fill[(size_t)col[i] * ncell + cid[i]]++] = i;
+    }
+    std::vector<int> flagged;
+    for (int i : fe) {
+        if (col[i] < 0) {
+            flagged.push_back(i);
+            continue;
+        }
+        int cells[27];
+        const int k = around(cid[i], cells);
+        bool hit = false;
+        for (int q = 0; q < k && !hit; q++) {
+            const size_t b = (size_t)col[i] * ncell + cells[q];
+            for (int m = cstart[b]; m < cstart[b + 1] && !hit; m++) {
+                const int j = cmem[m];
+                hit = j != i && dist2(i, j) < rc2;
+            }
+        }
+        if (hit) flagged.push_back(i);
+    }
+    for (int i : flagged) col[i] = pick(i);
     return SL_OK;
 }
 
-// New greedy colouring of a resident replica from its current positions; the
+// Repaired colouring of a resident replica from its current positions; the
 // pause bit is cleared and the replica re-activated. The caller re-lays out.
 static int recolour_replica(Engine &e, Replica *r) {
     std::vector<double> p(3 * r->n);
@@ -945,8 +1012,12 @@ static int recolour_replica(Engine &e, Replica *r) {
         v.box[a] = r->dev.box[a];
         v.pbc[a] = r->dev.pbc[a];
     }
-    std::vector<int> col;
-    if ((rc = greedy_colour(&v, r->dev.skin, col))) return rc;
+    // repair the present colouring: only spins that now meet their colour
+    // inside the colouring radius change
+    std::vector<int> col(r->n, -1);
+    for (int64_t q = 0; q < r->n_fe; q++) col[r->fe_idx[q]] = r->colour_fe[q];
+    const std::vector<int> prev = col;
+    if ((rc = greedy_colour(&v, r->dev.skin, col, &prev))) return rc;
     r->ncol = 0;
     for (int64_t q = 0; q < r->n_fe; q++) {
         r->colour_fe[q] = col[r->fe_idx[q]];
@@ -1289,7 +1360,9 @@ extern "C" int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *pe
     if (!s) return fail(SL_E_INVALID, "sim is NULL");
     if (n_steps < 0) return fail(SL_E_INVALID, "n_steps must be non-negative");
     Engine &e = s->eng;
-    const int64_t chunk = 256;
+    // steps are queued in chunks; a replica paused for recolouring inside a
+    // chunk idles through the rest of it, so chunks stay short
+    const int64_t chunk = 16;
     std::vector<double> h(chunk * NOBS);
     std::vector<RepDev> d;
     int rc;

@@ -114,27 +114,32 @@ def fege_lattice(nx: int, ny: int, nz: int, *, seed: int = SEED_STATE,
 
 
 def colour_periodic(nx: int, ny: int, nz: int, pbc) -> np.ndarray | None:
-    """colour = site + 4*k on Fe, -1 on Ge (16 colours), k = ((cx - cz) % 2) +
-    2*((cy - cz) % 2): the cells of one class k form a body-centred lattice of
-    cell offsets (all three even or all three odd), so two Fe of one colour are
-    one site apart by at least a*sqrt(3) = 8.14 A, beyond rc_R + skin.
+    """colour = site + 4*(cx%2 + 2*(cy%2) + 4*(cz%2)) on Fe, -1 on Ge (32
+    colours): two Fe of one colour sit on the same site two cells apart,
+    2a = 9.4 A, so the colouring survives the drift of the random-weight model
+    for hundreds of steps before a same-colour pair reaches the list shell.
 
-    Valid only when every periodic cell count is even (the classes must wrap
-    consistently); returns None otherwise.
+    Valid only when every periodic cell count is even (the parity classes must
+    wrap consistently); returns None otherwise.
     """
     for c, p in zip((nx, ny, nz), pbc):
         if p and c % 2:
             return None
     cx, cy, cz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
-    k = (((cx - cz) % 2) + 2 * ((cy - cz) % 2)).ravel()
+    par = (cx % 2 + 2 * (cy % 2) + 4 * (cz % 2)).ravel()
     site = np.arange(8)
-    col = site[None, :] + 4 * k[:, None]
+    col = site[None, :] + 4 * par[:, None]
     col[:, 4:] = -1
     return col.reshape(-1).astype(np.int32)
 
 
-def colour_greedy(types, pos, box, pbc, radius: float) -> np.ndarray:
-    """Greedy colouring of the Fe graph (edges r < radius) in atom-index order."""
+def colour_greedy(types, pos, box, pbc, radius: float, keep=None) -> np.ndarray:
+    """Greedy colouring of the Fe graph (edges r < radius) in atom-index order.
+
+    With `keep` (a colouring), a repair instead: spins keep their colour unless
+    it is the colour of a neighbour, in which case, in atom-index order, they
+    take the smallest colour none of their neighbours has.
+    """
     from scipy.spatial import cKDTree
     fe = np.nonzero(types == 0)[0]
     p = pos[fe].copy()
@@ -155,8 +160,12 @@ def colour_greedy(types, pos, box, pbc, radius: float) -> np.ndarray:
         adj[a].append(b)
         adj[b].append(a)
     col_fe = np.full(len(fe), -1, dtype=np.int64)
+    if keep is not None:
+        col_fe[:] = np.asarray(keep)[fe]
     for a in range(len(fe)):
         used = {col_fe[b] for b in adj[a] if col_fe[b] >= 0}
+        if col_fe[a] >= 0 and col_fe[a] not in used:
+            continue
         c = 0
         while c in used:
             c += 1

@@ -196,9 +196,11 @@ def test_bad_colouring_is_rejected(model):
 
 def test_recolouring_mid_run_matches_oracle(model, oracle):
     """A same-colour spin pair driven into the list shell: the run stops after
-    that step, takes the greedy colouring of its current positions and goes on.
+    that step, repairs its colouring at the current positions and goes on.
     Every step matches the oracle run with the colouring the library used for
-    it, and the new colouring is the greedy one (radius rc_R + skin + 0.5)."""
+    it, and the new colouring is the repair of the old one at radius
+    rc_R + skin + 0.5 (in atom order, a spin that shares its colour with a
+    neighbour takes the smallest colour none of its neighbours has)."""
     from paper_2606_14073_amd import nepspin
     kw = SCHEDULES["nve"]
     s = W.config_small()
@@ -219,7 +221,8 @@ def test_recolouring_mid_run_matches_oracle(model, oracle):
         col_new, nrc_new = sim.colour()
         if nrc_new != len(at):
             at.append(k)
-            assert np.array_equal(col_new, W.colour_greedy(s.types, cur[0], s.box, s.pbc, 7.0))
+            assert np.array_equal(col_new, W.colour_greedy(s.types, cur[0], s.box, s.pbc, 7.0, keep=col_used))
+            assert int((col_new != col_used).sum()) >= 1
         prev = cur
     print(f"recoloured after steps {at}; pair {i},{j}; worst per-step rel err pos {worst[0]:.2e} vel {worst[1]:.2e} "
           f"spin {worst[2]:.2e}", flush=True)
