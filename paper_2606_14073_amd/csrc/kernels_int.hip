@@ -141,23 +141,24 @@ __device__ inline double rsqrt_nr(double x) {
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
-// Eight lanes share a spin: they split the neighbour gather (couplings stored
+// SWEEP_L lanes share a spin: they split the neighbour gather (couplings stored
 // in colour-list order, so a wavefront reads contiguous records), reduce, and
 // then run the midpoint iteration in lockstep; lane 0 stores the result.
 // Latency is what bounds a colour class, so the loads are issued in two
 // waves: everything indexed by the colour-list position (atom, replica,
-// coupling count, self terms, the first four coupling slots of each lane,
+// coupling count, self terms, the first SWEEP_R0 coupling slots of each lane,
 // read whether or not they are in use and masked afterwards), then the
 // neighbours' spins, the spin itself, its noise and the replica record.
-constexpr int SWEEP_R0 = 4;    // coupling slots per lane loaded up front (32 per spin)
+constexpr int SWEEP_L = 16;    // lanes per spin
+constexpr int SWEEP_R0 = 2;    // coupling slots per lane loaded up front (32 per spin)
 
 // turns = 2 takes the colour twice in a row (the end of the ascending and the
 // start of the descending pass): the neighbour field is the same for both
 // rotations, the second starts from the first one's result.
 template <typename real>
 __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count, int turns) {
-    const int lane = threadIdx.x & 7;
-    const int t = blockIdx.x * 32 + (threadIdx.x >> 3);
+    const int lane = threadIdx.x & (SWEEP_L - 1);
+    const int t = blockIdx.x * (256 / SWEEP_L) + threadIdx.x / SWEEP_L;
     if (t >= count) return;
     const int p = base + t;
     const size_t lf = S.N_fe;
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     double cv[SWEEP_R0][6];
 #pragma unroll
     for (int k = 0; k < SWEEP_R0; k++) {
-        const size_t q = (size_t)(lane + 8 * k) * lf + p;
+        const size_t q = (size_t)(lane + SWEEP_L * k) * lf + p;
         cj[k] = W.cpl_j[q];
         const real *c = W.cpl + q * 6;
 #pragma unroll
@@ -184,18 +185,18 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     double hx = 0, hy = 0, hz = 0;
     d4 sj[SWEEP_R0];
 #pragma unroll
-    for (int k = 0; k < SWEEP_R0; k++) sj[k] = S.spin[lane + 8 * k < nc ? cj[k] : i];
+    for (int k = 0; k < SWEEP_R0; k++) sj[k] = S.spin[lane + SWEEP_L * k < nc ? cj[k] : i];
 #pragma unroll
     for (int k = 0; k < SWEEP_R0; k++) {
-        if (lane + 8 * k >= nc) continue;
+        if (lane + SWEEP_L * k >= nc) continue;
         const double J = cv[k][0], D = cv[k][1], K = cv[k][2], rx = cv[k][3], ry = cv[k][4], rz = cv[k][5];
         const double sr = sj[k].x * rx + sj[k].y * ry + sj[k].z * rz;
         hx -= J * sj[k].x + D * (sj[k].y * rz - sj[k].z * ry) + K * sr * rx;
         hy -= J * sj[k].y + D * (sj[k].z * rx - sj[k].x * rz) + K * sr * ry;
         hz -= J * sj[k].z + D * (sj[k].x * ry - sj[k].y * rx) + K * sr * rz;
     }
-    // spins with more than 8 * SWEEP_R0 couplings
-    for (int s = lane + 8 * SWEEP_R0; s < nc; s += 8) {
+    // spins with more than SWEEP_L * SWEEP_R0 couplings
+    for (int s = lane + SWEEP_L * SWEEP_R0; s < nc; s += SWEEP_L) {
         const int j = W.cpl_j[(size_t)s * lf + p];
         const real *c = W.cpl + ((size_t)s * lf + p) * 6;
         const double J = c[0], D = c[1], K = c[2], rx = c[3], ry = c[4], rz = c[5];
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         hz -= J * v.z + D * (v.x * ry - v.y * rx) + K * sr * rz;
     }
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
+    for (int m = 1; m < SWEEP_L; m <<= 1) {
         hx += __shfl_xor(hx, m);
         hy += __shfl_xor(hy, m);
         hz += __shfl_xor(hz, m);
@@ -598,7 +599,8 @@ void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, in
             const int c = pass == 0 ? cc : n_colours - 1 - cc;
             const int turns = (pass == 0 && cc == n_colours - 1) ? 2 : 1;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
-            if (n > 0) hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 32)), dim3(256), 0, st, S, W, b, n, turns);
+            if (n > 0)
+                hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256 / SWEEP_L)), dim3(256), 0, st, S, W, b, n, turns);
         }
 }
 
