@@ -146,7 +146,7 @@ typedef struct {
  *   force[n][3]    : F_i = -dE/dr_i, or NULL
  *   field[n][3]    : H_i = -dE/ds_i (+ mu_s mu_B B), species-0 rows; or NULL
  * The model keeps the device work arrays of its last evaluation (about
- * 17.3 KB per atom in FP64, 9.8 KB in FP32) for the next call of the same
+ * 11 KB per atom in FP64, 7 KB in FP32) for the next call of the same
  * precision; another precision, a system more than eight times smaller or
  * nep_model_destroy releases them. Calls on one model are serialised.
  * Errors: SL_E_INVALID (bad sizes/types), SL_E_BOX, SL_E_OVERFLOW (more than
@@ -232,8 +232,11 @@ typedef struct {
  * although coupled: SL_E_INVALID. The colouring is kept like a neighbour list:
  * whenever a list rebuild finds two same-colour spins within r_c^R + skin
  * (not yet coupled, and unable to come within r_c^R before the next rebuild),
- * the system stops after that step, is recoloured greedily from its current
- * positions, and goes on; the steps stay exact, only the sweep order changes.
+ * the system stops after that step, its colouring is repaired at the current
+ * positions (in caller order, a spin that shares its colour with a spin
+ * within r_c^R + skin + 0.5 A takes the smallest colour none of those has;
+ * the others keep theirs), and it goes on; the steps stay exact, only the
+ * sweep order changes.
  * Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM, SL_E_OVERFLOW, SL_E_DEVICE. */
 int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel,
               const int32_t *colour, const sl_integrator_params *ip, sl_precision prec,
@@ -245,7 +248,7 @@ int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel,
 int sl_integrate_steps(sl_sim *s, int64_t n_steps, sl_observables *per_step_out);
 
 /* Current colouring in caller order (colour[n], -1 on species 1; may be NULL)
- * and the number of recolourings since creation (may be NULL). */
+ * and the number of colour repairs since creation (may be NULL). */
 int sl_get_colour(const sl_sim *s, int32_t *colour, int64_t *n_recolour);
 
 /* State in caller order: pos, vel, spin [n][3] (any may be NULL), step. */
@@ -306,8 +309,8 @@ int sl_server_create(const nep_model *m, const sl_server_config *cfg, sl_server 
 size_t sl_replica_bytes(int64_t n_atoms, sl_precision prec);
 
 /* Queue a replica (inputs copied; colour may be NULL). ip->K_corr must equal
- * the server's. Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the
- * whole budget). */
+ * the server's and ip->sc_tol be 0 (fixed corrector passes). Errors:
+ * SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the whole budget). */
 int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const double *vel,
                       const int32_t *colour, const sl_integrator_params *ip, int64_t n_steps,
                       uint64_t *id_out);
