@@ -803,6 +803,10 @@ typedef struct {
      * the mean diagonal of their Gram matrix */
     int sc_depth;
     double sc_reg;
+    /* structural-only model (the standard NEP without magnetic channels): no
+     * spins, the step is B A O A B; masses per species (u), 0 = Fe/Ge */
+    int structural;
+    double mass[2];
 } or_step_params;
 
 typedef struct {
@@ -991,8 +995,9 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
     double *xnew = malloc(sizeof(double) * nv);
     double *dF = malloc(sizeof(double) * nv * (depth + 1)), *dG = malloc(sizeof(double) * nv * (depth + 1));
     double dt = sp->dt;
+    const double mt[2] = {sp->mass[0] > 0 ? sp->mass[0] : MASS[0], sp->mass[1] > 0 ? sp->mass[1] : MASS[1]};
     for (int i = 0; i < n; i++)
-        if (type[i] != 0) spin[3 * i] = spin[3 * i + 1] = spin[3 * i + 2] = 0.0;
+        if (sp->structural || type[i] != 0) spin[3 * i] = spin[3 * i + 1] = spin[3 * i + 2] = 0.0;
     double B[3], Bz[3] = {0, 0, 0};
     /* F^0 at the start state */
     {
@@ -1010,7 +1015,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         for (int a = 0; a < 3; a++) B[a] = sp->B0[a] + (sp->B1[a] - sp->B0[a]) * frac;
         /* B: half kick */
         for (int i = 0; i < n; i++)
-            for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * KAPPA * F[3 * i + a] / MASS[type[i]];
+            for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * KAPPA * F[3 * i + a] / mt[type[i]];
         /* A: half drift */
         for (int i = 0; i < n; i++)
             for (int a = 0; a < 3; a++) pos[3 * i + a] += 0.5 * dt * vel[3 * i + a];
@@ -1021,102 +1026,105 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
             for (int i = 0; i < n; i++) {
                 double xi[3];
                 normals3(sp->seed, (uint32_t)i, (uint64_t)st, 0, xi);
-                double sig = sqrt((1.0 - c1 * c1) * KAPPA * KB * T / MASS[type[i]]);
+                double sig = sqrt((1.0 - c1 * c1) * KAPPA * KB * T / mt[type[i]]);
                 for (int a = 0; a < 3; a++) vel[3 * i + a] = c1 * vel[3 * i + a] + sig * xi[a];
             }
         }
-        /* S: spin step at R_mid */
-        double esig = (sp->alpha > 0 && T > 0) ? sqrt(2.0 * sp->alpha * KB * T * HBAR / dt) : 0.0;
-        for (int i = 0; i < n; i++) {
-            double xi[3] = {0, 0, 0};
-            if (esig > 0 && type[i] == 0) normals3(sp->seed, (uint32_t)i, (uint64_t)st, 1, xi);
-            for (int a = 0; a < 3; a++) eta[3 * i + a] = esig * xi[a];
-        }
-        memcpy(Sn, spin, sizeof(double) * 3 * n);
-        memcpy(Sh, spin, sizeof(double) * 3 * n);
-        memcpy(X, spin, sizeof(double) * 3 * n);   /* x^(0) = S^n: the predictor */
-        const int self_consistent = sp->sc_tol > 0;
-        const int last = self_consistent ? sp->sc_max : sp->K_corr;
-        int passes = 0, ncols = 0;
+        int passes = 0;
         double change = 0;
-        for (int pc = 0; pc <= last; pc++) {
-            /* Fp* at (R_mid, S_hat) */
-            ctx_init(&C, n, type, pos, Sh, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
-            forward_all(&C, q, Fp, Ei);
-            /* restart from S^n; C.spin now holds the spins being swept */
-            memcpy(C.spin, Sn, sizeof(double) * 3 * n);
-            env_cache(&C);
-            for (int pass = 0; pass < 2; pass++) {
-                for (int cc = 0; cc < ncol; cc++) {
-                    int c = pass == 0 ? cc : ncol - 1 - cc;
-                    if (sp->sequential) {
-                        for (int i = 0; i < n; i++)
-                            if (colour[i] == c) {
-                                rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
-                                for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
-                            }
-                    } else {
-#pragma omp parallel for schedule(dynamic, 8)
-                        for (int i = 0; i < n; i++)
-                            if (colour[i] == c) rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
-                        for (int i = 0; i < n; i++)
-                            if (colour[i] == c)
-                                for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
-                    }
-                }
-            }
-            passes = pc + 1;
-            /* residual of the pass: g - x, with g the swept spins (for the
-             * plain iteration x is the previous pass's g, S^n for the first) */
-            change = 0;
-            for (int i = 0; i < n; i++)
-                if (type[i] == 0)
-                    for (int a = 0; a < 3; a++) {
-                        const double d = fabs(C.spin[3 * i + a] - X[3 * i + a]);
-                        if (d > change) change = d;
-                    }
-            memcpy(spin, C.spin, sizeof(double) * 3 * n);
-            ctx_free(&C);
-            if (self_consistent && pc >= 1 && change <= sp->sc_tol) break;
-            if (pc == last) break;
-            /* next iterate: plain, x = g; accelerated, Anderson mixing of the
-             * last depth residual differences */
-            if (depth == 0) {
-                memcpy(X, spin, sizeof(double) * 3 * n);
-            } else {
-                size_t k = 0;
-                for (int i = 0; i < n; i++)
-                    if (type[i] == 0)
-                        for (int a = 0; a < 3; a++, k++) {
-                            gk[k] = spin[3 * i + a];
-                            fk[k] = spin[3 * i + a] - X[3 * i + a];
-                        }
-                if (pc >= 1) {
-                    /* newest difference in front, the oldest dropped */
-                    const int keep = ncols < depth ? ncols : depth - 1;
-                    memmove(dF + k, dF, sizeof(double) * k * keep);
-                    memmove(dG + k, dG, sizeof(double) * k * keep);
-                    for (size_t e = 0; e < k; e++) {
-                        dF[e] = fk[e] - fprev[e];
-                        dG[e] = gk[e] - gprev[e];
-                    }
-                    ncols = keep + 1;
-                }
-                memcpy(fprev, fk, sizeof(double) * k);
-                memcpy(gprev, gk, sizeof(double) * k);
-                or_anderson_mix((int)k, ncols, dF, dG, fk, gk, sp->sc_reg, xnew, NULL);
-                k = 0;
-                for (int i = 0; i < n; i++)
-                    if (type[i] == 0)
-                        for (int a = 0; a < 3; a++, k++) X[3 * i + a] = xnew[k];
-            }
-            /* S_hat = normalise((S^n + x)/2) on spin-carrying atoms */
+        /* S: spin step at R_mid (none for a structural-only model) */
+        if (!sp->structural) {
+            double esig = (sp->alpha > 0 && T > 0) ? sqrt(2.0 * sp->alpha * KB * T * HBAR / dt) : 0.0;
             for (int i = 0; i < n; i++) {
-                if (type[i] != 0) continue;
-                double m[3], nn;
-                for (int a = 0; a < 3; a++) m[a] = 0.5 * (Sn[3 * i + a] + X[3 * i + a]);
-                nn = sqrt(dot3(m, m));
-                for (int a = 0; a < 3; a++) Sh[3 * i + a] = m[a] / nn;
+                double xi[3] = {0, 0, 0};
+                if (esig > 0 && type[i] == 0) normals3(sp->seed, (uint32_t)i, (uint64_t)st, 1, xi);
+                for (int a = 0; a < 3; a++) eta[3 * i + a] = esig * xi[a];
+            }
+            memcpy(Sn, spin, sizeof(double) * 3 * n);
+            memcpy(Sh, spin, sizeof(double) * 3 * n);
+            memcpy(X, spin, sizeof(double) * 3 * n);   /* x^(0) = S^n: the predictor */
+            const int self_consistent = sp->sc_tol > 0;
+            const int last = self_consistent ? sp->sc_max : sp->K_corr;
+            int ncols = 0;
+            for (int pc = 0; pc <= last; pc++) {
+                /* Fp* at (R_mid, S_hat) */
+                ctx_init(&C, n, type, pos, Sh, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
+                forward_all(&C, q, Fp, Ei);
+                /* restart from S^n; C.spin now holds the spins being swept */
+                memcpy(C.spin, Sn, sizeof(double) * 3 * n);
+                env_cache(&C);
+                for (int pass = 0; pass < 2; pass++) {
+                    for (int cc = 0; cc < ncol; cc++) {
+                        int c = pass == 0 ? cc : ncol - 1 - cc;
+                        if (sp->sequential) {
+                            for (int i = 0; i < n; i++)
+                                if (colour[i] == c) {
+                                    rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
+                                    for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
+                                }
+                        } else {
+    #pragma omp parallel for schedule(dynamic, 8)
+                            for (int i = 0; i < n; i++)
+                                if (colour[i] == c) rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
+                            for (int i = 0; i < n; i++)
+                                if (colour[i] == c)
+                                    for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
+                        }
+                    }
+                }
+                passes = pc + 1;
+                /* residual of the pass: g - x, with g the swept spins (for the
+                 * plain iteration x is the previous pass's g, S^n for the first) */
+                change = 0;
+                for (int i = 0; i < n; i++)
+                    if (type[i] == 0)
+                        for (int a = 0; a < 3; a++) {
+                            const double d = fabs(C.spin[3 * i + a] - X[3 * i + a]);
+                            if (d > change) change = d;
+                        }
+                memcpy(spin, C.spin, sizeof(double) * 3 * n);
+                ctx_free(&C);
+                if (self_consistent && pc >= 1 && change <= sp->sc_tol) break;
+                if (pc == last) break;
+                /* next iterate: plain, x = g; accelerated, Anderson mixing of the
+                 * last depth residual differences */
+                if (depth == 0) {
+                    memcpy(X, spin, sizeof(double) * 3 * n);
+                } else {
+                    size_t k = 0;
+                    for (int i = 0; i < n; i++)
+                        if (type[i] == 0)
+                            for (int a = 0; a < 3; a++, k++) {
+                                gk[k] = spin[3 * i + a];
+                                fk[k] = spin[3 * i + a] - X[3 * i + a];
+                            }
+                    if (pc >= 1) {
+                        /* newest difference in front, the oldest dropped */
+                        const int keep = ncols < depth ? ncols : depth - 1;
+                        memmove(dF + k, dF, sizeof(double) * k * keep);
+                        memmove(dG + k, dG, sizeof(double) * k * keep);
+                        for (size_t e = 0; e < k; e++) {
+                            dF[e] = fk[e] - fprev[e];
+                            dG[e] = gk[e] - gprev[e];
+                        }
+                        ncols = keep + 1;
+                    }
+                    memcpy(fprev, fk, sizeof(double) * k);
+                    memcpy(gprev, gk, sizeof(double) * k);
+                    or_anderson_mix((int)k, ncols, dF, dG, fk, gk, sp->sc_reg, xnew, NULL);
+                    k = 0;
+                    for (int i = 0; i < n; i++)
+                        if (type[i] == 0)
+                            for (int a = 0; a < 3; a++, k++) X[3 * i + a] = xnew[k];
+                }
+                /* S_hat = normalise((S^n + x)/2) on spin-carrying atoms */
+                for (int i = 0; i < n; i++) {
+                    if (type[i] != 0) continue;
+                    double m[3], nn;
+                    for (int a = 0; a < 3; a++) m[a] = 0.5 * (Sn[3 * i + a] + X[3 * i + a]);
+                    nn = sqrt(dot3(m, m));
+                    for (int a = 0; a < 3; a++) Sh[3 * i + a] = m[a] / nn;
+                }
             }
         }
         /* A: half drift */
@@ -1131,14 +1139,14 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         ctx_free(&C);
         /* B: half kick */
         for (int i = 0; i < n; i++)
-            for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * KAPPA * F[3 * i + a] / MASS[type[i]];
+            for (int a = 0; a < 3; a++) vel[3 * i + a] += 0.5 * dt * KAPPA * F[3 * i + a] / mt[type[i]];
         *step = st + 1;
         if (obs) {
             or_obs *o = obs + it;
             double ek = 0, num = 0, den = 0, M[3] = {0, 0, 0};
             int nfe = 0;
             for (int i = 0; i < n; i++) {
-                ek += 0.5 * MASS[type[i]] * dot3(vel + 3 * i, vel + 3 * i) / KAPPA;
+                ek += 0.5 * mt[type[i]] * dot3(vel + 3 * i, vel + 3 * i) / KAPPA;
                 if (type[i] == 0) {
                     double sxh[3];
                     cross3(spin + 3 * i, H + 3 * i, sxh);

@@ -18,6 +18,43 @@ SRC_PATH = os.path.join(HERE, "oracle.c")
 RC_R = 6.0
 RC_A = 4.5
 N_DESC = 102
+N_PARAMS = 15438
+# The structural-only NEP (no magnetic channels): c^R[4][9][9], c^A[4][7][9],
+# then per species W0[64][37], b0[64], w1[64], b1 -- the descriptor is q^R (9)
+# and q^A (28), the first 37 entries of the spin-aware one.
+N_DESC_STRUCT = 37
+N_PARAMS_STRUCT = 324 + 252 + 2 * (64 * 37 + 64 + 64 + 1)
+
+
+def expand_structural(p):
+    """The structural-only model as the spin-aware one with every magnetic
+    coefficient and every W0 column of a magnetic channel zero: with zero
+    spins the two define the same energy."""
+    p = np.asarray(p, dtype=np.float64)
+    assert p.shape == (N_PARAMS_STRUCT,)
+    out = np.zeros(N_PARAMS)
+    out[:576] = p[:576]
+    o_in, o_out = 576, 576 + 4 * 324 + 252
+    for t in range(2):
+        w0 = p[o_in:o_in + 64 * 37].reshape(64, 37)
+        big = np.zeros((64, N_DESC))
+        big[:, :37] = w0
+        out[o_out:o_out + 64 * N_DESC] = big.ravel()
+        o_in += 64 * 37
+        o_out += 64 * N_DESC
+        out[o_out:o_out + 129] = p[o_in:o_in + 129]
+        o_in += 129
+        o_out += 129
+    assert o_in == N_PARAMS_STRUCT and o_out == N_PARAMS
+    return out
+
+
+def _model(params, spin, n):
+    """spin-aware parameters and spins for either model"""
+    params = np.asarray(params, dtype=np.float64)
+    if params.shape == (N_PARAMS_STRUCT,):
+        return expand_structural(params), np.zeros((n, 3)), True
+    return params, spin, False
 
 
 def build(force: bool = True) -> str:
@@ -37,7 +74,8 @@ class StepParams(ct.Structure):
                 ("rcR", ct.c_double), ("rcA", ct.c_double), ("n_ramp", ct.c_int64),
                 ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
                 ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int), ("sc_max", ct.c_int),
-                ("sc_tol", ct.c_double), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
+                ("sc_tol", ct.c_double), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double),
+                ("structural", ct.c_int), ("mass", ct.c_double * 2)]
 
 
 class Obs(ct.Structure):
@@ -100,11 +138,14 @@ def neighbors(pos, box, pbc, rc, use_cells=False, maxnb=256):
 
 def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0), act=0,
              rcR=RC_R, rcA=RC_A, want=("E", "F", "H")):
-    """Energy, forces, fields (and optionally q, Fp, per-atom E) of one system."""
+    """Energy, forces, fields (and optionally q, Fp, per-atom E) of one system;
+    params of the spin-aware model, or of the structural-only one (spins are
+    then ignored, and q / Fp keep the first 37 columns)."""
     types = _i32(types)
     pos = _f64(pos)
-    spin = _f64(spin)
     n = types.shape[0]
+    params, spin, structural = _model(params, spin, n)
+    spin = _f64(spin)
     out = {}
     E = np.zeros(1)
     Ez = np.zeros(1)
@@ -119,7 +160,7 @@ def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0),
     out["Ez"] = float(Ez[0])
     for k, v in (("Ei", Ei), ("F", F), ("H", H), ("q", q), ("Fp", Fp)):
         if v is not None:
-            out[k] = v
+            out[k] = v[:, :N_DESC_STRUCT] if structural and k in ("q", "Fp") else v
     return out
 
 
@@ -162,7 +203,7 @@ def normals(seed, atom, step, stream):
 def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
                 mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
                 K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30, sc_depth=0,
-                sc_reg=1e-10) -> StepParams:
+                sc_reg=1e-10, structural=0, mass=(0.0, 0.0)) -> StepParams:
     sp = StepParams()
     sp.dt = dt
     sp.T0 = T0
@@ -178,6 +219,8 @@ def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, ga
     sp.sc_max = sc_max
     sp.sc_depth = sc_depth
     sp.sc_reg = sc_reg
+    sp.structural = structural
+    sp.mass[0], sp.mass[1] = mass
     sp.mid_cap = mid_cap
     sp.rcR = rcR
     sp.rcA = rcA
@@ -194,10 +237,14 @@ def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps
     """n_steps of the spin-lattice step; returns (pos, vel, spin, step, obs[n_steps]), obs columns
     step, E_nep, E_kin, E_z, T_lattice, T_spin, M[3], sweep passes, last change."""
     types = _i32(types)
+    n = types.shape[0]
+    params, spin, structural = _model(params, spin, n)
+    if structural:
+        sp.structural = 1
     pos = _f64(pos).copy()
     vel = _f64(vel).copy()
     spin = _f64(spin).copy()
-    colour = _i32(colour)
+    colour = _i32(colour if colour is not None else np.full(n, -1))
     ncol = int(colour.max()) + 1 if colour.size else 0
     st = ct.c_int64(step0)
     obs = (Obs * max(n_steps, 1))()

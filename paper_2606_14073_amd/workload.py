@@ -175,10 +175,10 @@ def colour_greedy(types, pos, box, pbc, radius: float, keep=None) -> np.ndarray:
     return col
 
 
-def maxwell_boltzmann(types: np.ndarray, T: float, seed: int = SEED_STATE + 1) -> np.ndarray:
+def maxwell_boltzmann(types: np.ndarray, T: float, seed: int = SEED_STATE + 1, masses=MASS) -> np.ndarray:
     """Velocities (Angstrom/fs) drawn at temperature T with zero total momentum."""
     rng = np.random.default_rng(seed)
-    m = MASS[types][:, None]
+    m = np.asarray(masses)[types][:, None]
     v = rng.normal(size=(types.shape[0], 3)) * np.sqrt(KAPPA * KB * T / m)
     p = (m * v).sum(axis=0) / m.sum()
     return v - p[None, :]
@@ -187,6 +187,60 @@ def maxwell_boltzmann(types: np.ndarray, T: float, seed: int = SEED_STATE + 1) -
 def random_params(seed: int = SEED_WEIGHTS, sigma: float = 0.1) -> np.ndarray:
     """All model parameters i.i.d. N(0, sigma) in the library's order."""
     return np.random.default_rng(seed).normal(0.0, sigma, N_PARAMS)
+
+
+# Structural-only NEP on a water-like liquid -----------------------------------
+# The paper compares throughput with DeePMD on liquid water using its NEP engine
+# without the magnetic channels; the trained water model is not public, so a
+# seeded random structural model on a synthetic water box stands in for it.
+
+N_PARAMS_STRUCT = 324 + 252 + 2 * (64 * 37 + 64 + 64 + 1)
+MASS_WATER = np.array([15.999, 1.008])   # O, H (u)
+WATER_DENSITY = 0.1003                   # atoms per cubic Angstrom (liquid water, 300 K)
+
+
+def random_params_structural(seed: int = SEED_WEIGHTS, sigma: float = 0.1) -> np.ndarray:
+    """Structural-only model parameters i.i.d. N(0, sigma)."""
+    return np.random.default_rng(seed).normal(0.0, sigma, N_PARAMS_STRUCT)
+
+
+def water_box(n: int, *, seed: int = SEED_STATE, noise: float = 0.02) -> System:
+    """n^3 water molecules, one per cell of a simple cubic grid whose spacing
+    gives liquid-water density, each with a uniformly random orientation
+    (O-H 0.9572 A, H-O-H 104.52 deg), plus N(0, noise) per component.
+    Atom order molecule by molecule (O, H, H); species O = 0, H = 1; periodic;
+    no spins and no colouring."""
+    rng = np.random.default_rng(seed)
+    a = (3.0 / WATER_DENSITY) ** (1.0 / 3.0)
+    g = (np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+         + 0.5) * a
+    nm = g.shape[0]
+    half = np.deg2rad(104.52) / 2
+    local = 0.9572 * np.array([[np.sin(half), np.cos(half), 0.0], [-np.sin(half), np.cos(half), 0.0]])
+    # uniform random rotations from unit quaternions
+    qv = rng.normal(size=(nm, 4))
+    qv /= np.linalg.norm(qv, axis=1, keepdims=True)
+    w, x, y, z = qv.T
+    Rm = np.stack([np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+                   np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+                   np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1)], 1)
+    h = np.einsum("mij,hj->mhi", Rm, local)                       # [nm, 2, 3]
+    pos = np.concatenate([g[:, None, :], g[:, None, :] + h], axis=1).reshape(-1, 3)
+    pos += rng.normal(0.0, noise, size=pos.shape)
+    box = np.full(3, n * a)
+    pos = np.mod(pos, box)
+    types = np.tile(np.array([0, 1, 1], dtype=np.int32), nm)
+    return System(types, pos, np.zeros_like(pos), box, np.ones(3, dtype=np.int32), (n, n, n), None)
+
+
+def config_water_small() -> System:
+    """5^3 molecules = 375 atoms."""
+    return water_box(5)
+
+
+def config_water_bench() -> System:
+    """100^3 molecules = 3,000,000 atoms."""
+    return water_box(100)
 
 
 # Named workloads ------------------------------------------------------------

@@ -696,3 +696,111 @@ def test_accelerated_midpoint_same_fixed_point(oracle):
     assert np.abs(pos - pos0).max() <= 1e-10
     assert np.abs(vel - v0).max() <= 1e-10
     assert np.abs(spin - s.spin).max() <= 1e-10
+
+
+# --------------------------------------------------------------------------
+# Structural-only NEP (no magnetic channels): the read-out over q^R, q^A
+# --------------------------------------------------------------------------
+
+def _struct_readout(p, t, q):
+    """E_i of the structural model from its own parameter layout: W0[64][37],
+    b0, w1, b1 per species after c^R and c^A."""
+    o = 576 + t * (64 * 37 + 129)
+    W0 = p[o:o + 64 * 37].reshape(64, 37)
+    b0 = p[o + 64 * 37:o + 64 * 37 + 64]
+    w1 = p[o + 64 * 37 + 64:o + 64 * 37 + 128]
+    b1 = p[o + 64 * 37 + 128]
+    return b1 + w1 @ np.tanh(b0 + W0 @ q)
+
+
+@pytest.mark.parametrize("types", [(0, 1), (0, 0), (1, 1)])
+def test_structural_dimer_closed_form(oracle, types):
+    """Dimer: q^R_n = g^R_n(r), q^A_nl = g^A_n(r)^2 P_l(1); E_i by the read-out
+    over those 37 values with the structural model's own parameter layout."""
+    rng = np.random.default_rng(13)
+    p = W.random_params_structural(7)
+    assert p.size == oracle.N_PARAMS_STRUCT == 5570
+    box, pbc = free_box()
+    t = np.array(types)
+    for r in (0.96, 1.5, 2.8, 4.2, 5.6):
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        pos = np.array([[50.0, 50.0, 50.0], [50.0, 50.0, 50.0] + r * u])
+        spin = rng.normal(size=(2, 3))   # ignored by the structural model
+        out = oracle.evaluate(t, pos, spin, box, pbc, p, want=("q", "Ei", "H"))
+        assert out["q"].shape == (2, 37) and np.abs(out["H"]).max() == 0.0
+        for i, j in ((0, 1), (1, 0)):
+            tau = 2 * t[i] + t[j]
+            exp = np.zeros(37)
+            exp[D_R:D_R + 9] = gfun(p, P_CR, 9, tau, r, RC_R)
+            gA = gfun(p, P_CA, 7, tau, r, RC_A)
+            for n in range(7):
+                exp[D_A + 4 * n:D_A + 4 * n + 4] = gA[n] ** 2
+            np.testing.assert_allclose(out["q"][i], exp, rtol=1e-13, atol=1e-14 * max(1, np.abs(exp).max()))
+            assert out["Ei"][i] == pytest.approx(_struct_readout(p, t[i], exp), rel=1e-13, abs=1e-14)
+
+
+def test_structural_forces_fd_and_invariances(oracle):
+    """A cluster of eight water molecules: central differences of the energy
+    (rel <= 1e-6), sum of forces, rotation covariance; no fields."""
+    s = W.water_box(2, noise=0.05)
+    p = W.random_params_structural()
+    box, pbc = free_box(300.0)
+    pos = s.pos + 100.0
+    a = oracle.evaluate(s.types, pos, None, box, pbc, p)
+    assert np.abs(a["H"]).max() == 0.0
+    h = 1e-5
+    rng = np.random.default_rng(2)
+    for i in rng.choice(s.n, 6, replace=False):
+        for x in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[i, x] += h
+            pm[i, x] -= h
+            fd = -(oracle.evaluate(s.types, pp, None, box, pbc, p, want=())["E"]
+                   - oracle.evaluate(s.types, pm, None, box, pbc, p, want=())["E"]) / (2 * h)
+            assert abs(fd - a["F"][i, x]) <= 1e-6 * max(1.0, np.abs(a["F"]).max())
+    assert np.abs(a["F"].sum(axis=0)).max() <= 1e-12 * np.abs(a["F"]).sum()
+    R = Rotation.from_euler("zyx", [0.4, 1.1, -0.6]).as_matrix()
+    c = pos.mean(axis=0)
+    b = oracle.evaluate(s.types, (pos - c) @ R.T + c, None, box, pbc, p)
+    assert b["E"] == pytest.approx(a["E"], rel=1e-12)
+    np.testing.assert_allclose(b["F"], a["F"] @ R.T, atol=1e-12 * np.abs(a["F"]).max())
+
+
+def test_structural_step_masses_and_energy(oracle):
+    """The structural step is B A O A B with the given masses: with no
+    Langevin bath, energy is conserved to O(dt^2) (halving dt quarters the
+    drift), the kinetic energy uses the given masses, and spins stay zero.
+    One Langevin O step from rest has the exact variance for each mass."""
+    s = W.water_box(2, noise=0.05)
+    p = W.random_params_structural()
+    box, pbc = free_box(300.0)
+    pos0 = s.pos + 100.0
+    v0 = W.maxwell_boltzmann(s.types, 100.0, masses=W.MASS_WATER)
+    drift = []
+    for dt in (0.2, 0.1):
+        n = int(round(4.0 / dt))
+        sp = oracle.step_params(dt=dt, mass=tuple(W.MASS_WATER))
+        pos, vel, spin, _, ob = oracle.run(s.types, pos0, v0, None, box, pbc, p, None, sp, n)
+        assert np.abs(spin).max() == 0.0
+        ek = 0.5 * (W.MASS_WATER[s.types][:, None] * vel ** 2).sum() / KAPPA
+        assert ob[-1, 2] == pytest.approx(ek, rel=1e-13)
+        e0 = oracle.evaluate(s.types, pos0, None, box, pbc, p, want=())["E"]
+        e0 += 0.5 * (W.MASS_WATER[s.types][:, None] * v0 ** 2).sum() / KAPPA
+        drift.append(np.abs(ob[:, 1] + ob[:, 2] - e0).max())
+    assert drift[1] < 0.4 * drift[0]
+    # O step variance
+    n = 1500
+    rng = np.random.default_rng(9)
+    posr = rng.uniform(0, 400, size=(n, 3))
+    types = (np.arange(n) % 2).astype(np.int32)
+    T, g, dt = 300.0, 0.02, 0.5
+    sp = oracle.step_params(dt=dt, T0=T, gammaL=g, ensemble=1, mass=tuple(W.MASS_WATER))
+    _, vel, _, _, _ = oracle.run(types, posr, np.zeros((n, 3)), None, np.array([1e4] * 3), np.zeros(3, np.int32),
+                                 np.zeros(oracle.N_PARAMS_STRUCT), None, sp, 1)
+    c1 = math.exp(-g * dt)
+    for t in (0, 1):
+        var = (1 - c1 * c1) * KAPPA * KB * T / W.MASS_WATER[t]
+        x = vel[types == t].ravel() / math.sqrt(var)
+        assert abs(x.mean()) < 4 / math.sqrt(x.size)
+        assert abs(x.var() - 1) < 4 * math.sqrt(2 / x.size)
