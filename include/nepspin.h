@@ -88,6 +88,14 @@ typedef struct sl_server sl_server;
 typedef struct {
     int n_max_R, n_max_A, l_max, basis_K, n_hidden, n_species;
     double rc_R, rc_A;
+    int structural;      /* 0: the spin-aware NEP below. 1: the structural-only
+                            NEP it extends (Sec. 5.1: the magnetic groups augment
+                            the structural channels): descriptor q^R (9) and
+                            q^A (28), 5,570 parameters c^R[4][9][9],
+                            c^A[4][7][9], then per species W0[64][37], b0[64],
+                            w1[64], b1[1]. No spins: spin inputs are ignored,
+                            fields are zero, a step is B A O A B, and
+                            nep_spin_descriptors returns [n][37] arrays.       */
 } nep_spin_hparams;
 
 /* params: 15,438 doubles in this order (tau = 2 t_i + t_j is the ordered
@@ -150,7 +158,8 @@ typedef struct {
  * precision; another precision, a system more than eight times smaller or
  * nep_model_destroy releases them. Calls on one model are serialised.
  * Errors: SL_E_INVALID (bad sizes/types), SL_E_BOX, SL_E_OVERFLOW (more than
- * 128 neighbours inside 6.5 A or 64 inside 5 A), SL_E_OOM, SL_E_DEVICE. */
+ * 160 neighbours inside 6.5 A, 96 inside 5 A, or 64 species-0 neighbours of a
+ * spin carrier inside 6.5 A), SL_E_OOM, SL_E_DEVICE. */
 int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec,
                   double *energy, double *energy_atom, double *force, double *field,
                   const sl_exec *ex);
@@ -202,6 +211,7 @@ typedef struct {
                             simulations only (sl_create); the host reads one
                             small decision per pass.                         */
     int sc_max;          /* cap on corrector passes when sc_tol > 0          */
+    double mass[2];      /* per species (u); 0 = 55.845 (species 0), 72.630   */
     int sc_depth;        /* accelerated variant (Sec. 5.1), 0..8: the next
                             iterate mixes the last sc_depth residual
                             differences (Anderson); 0: plain iteration       */

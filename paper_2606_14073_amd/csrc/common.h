@@ -16,6 +16,10 @@ constexpr int NB = 9;      // Chebyshev basis T_0..T_8 (basis size 8, Sec. 5.2)
 constexpr int NH = 64;     // hidden units per species
 constexpr int ND = 102;    // descriptor length
 constexpr int DP = 104;    // padded descriptor row
+// the structural-only NEP (no magnetic channels): q^R and q^A, the first 37
+// entries of the same row; its read-out contracts over 40 (a multiple of 4)
+constexpr int DS = 37, DS_PAD = 40;
+constexpr int N_PARAMS_STRUCT = 324 + 252 + 2 * (NH * DS + NH + NH + 1);
 constexpr int NLM = 24;    // real harmonics l = 1..4
 constexpr int NAB = 2 * NLM;   // angular accumulators per (atom, n): A then B
 
@@ -24,8 +28,8 @@ constexpr int D_R = 0, D_A = 9, D_OS = 37, D_EX = 38, D_DM = 47, D_AN = 56, D_SI
 constexpr int P_CR = 0, P_CA = 324, P_CEX = 576, P_CDM = 900, P_CAN = 1224, P_CSI = 1548,
               P_CSA = 1872, P_MLP = 2124, P_MLP_STRIDE = 6657, N_PARAMS = 15438;
 
-constexpr int MAXR = 128;  // listed neighbours within rc_R + skin
-constexpr int MAXA = 64;   // listed neighbours within rc_A + skin
+constexpr int MAXR = 160;  // listed neighbours within rc_R + skin (liquid water at skin 0.5: ~115)
+constexpr int MAXA = 96;   // listed neighbours within rc_A + skin
 
 constexpr double RC_R = 6.0;
 constexpr double RC_A = 4.5;
@@ -37,6 +41,7 @@ constexpr double HBAR = 0.6582119569;
 constexpr double MUB = 5.7883818060e-5;
 constexpr double PI = 3.14159265358979323846;
 
+// default masses of the two species (Fe, Ge)
 __host__ __device__ inline double mass_of(int t) { return t == 0 ? 55.845 : 72.630; }
 
 struct alignas(32) d4 {
@@ -55,6 +60,7 @@ struct RepDev {
     int pbc[3], nc[3];
     int ensemble, mid_cap, active, failed;
     int cell_base, n_atoms, fe_off, n_fe, ge_off, n_ge;
+    double mass[2];                 // per species (u)
     double sc_tol;                  // self-consistent midpoint tolerance (0: fixed K_corr)
     unsigned long long sc_delta;    // max |S^(p) - S^(p-1)| of the current pass, as bits
     int sc_max, sc_done;            // pass cap; converged in this step

@@ -72,7 +72,8 @@ static double now_s() {
 constexpr size_t MODEL_DEV = 324 + 252 + 4 * 324 + 252 + 2 * DP * NH + 2 * NH + 2 * NH + 2;
 
 struct nep_model {
-    std::vector<double> p;
+    std::vector<double> p;          // spin-aware layout (a structural-only model is expanded)
+    bool structural = false;
     double *d64 = nullptr;
     float *d32 = nullptr;
     float *dbf = nullptr;
@@ -290,6 +291,7 @@ struct Engine {
         Sys S;
         S.N = N;
         S.N_fe = N_fe;
+        S.mag = M && M->structural ? 0 : 1;
         S.n_rep = (int)reps.size();
         S.n_cells = n_cells;
         S.rid = rid;
@@ -729,8 +731,10 @@ struct Engine {
         { ProfScope p(this, 9); launch_kick(S, st); launch_drift(S, st); }
         rebuild_if_needed();
         { ProfScope p(this, 9); launch_langevin(S, st); }
-        if (prec == SL_FP64) spin_step(M->m64, w64);
-        else spin_step(M->m32, w32);
+        if (!M->structural) {
+            if (prec == SL_FP64) spin_step(M->m64, w64);
+            else spin_step(M->m32, w32);
+        }
         { ProfScope p(this, 9); launch_drift(S, st); }
         rebuild_if_needed();
         evaluate(spin);
@@ -751,7 +755,7 @@ struct Engine {
         int h[NFLAGS];
         int rc = read_flags(h);
         if (rc) return rc;
-        if (h[F_OVERFLOW] & 1) return fail(SL_E_OVERFLOW, "neighbour list capacity exceeded (more than 128 atoms within rc_R+skin, 64 within rc_A+skin or 64 spin neighbours)");
+        if (h[F_OVERFLOW] & 1) return fail(SL_E_OVERFLOW, "neighbour list capacity exceeded (more than 160 atoms within rc_R+skin, 96 within rc_A+skin or 64 spin neighbours)");
         if (h[F_OVERFLOW] & 2) return fail(SL_E_OVERFLOW, "asymmetric neighbour lists");
         return SL_OK;
     }
@@ -1061,7 +1065,7 @@ static int settle_layout(Engine &e, std::vector<int> &bad, bool global_flags = t
 static const char *colour_msg = "two spins of the same colour lie within rc_R of each other (invalid colouring)";
 
 static int make_replica(const sl_system_view *sys, const double *vel, const int32_t *colour,
-                        const sl_integrator_params *ip, bool need_colour, Replica &r) {
+                        const sl_integrator_params *ip, bool need_colour, Replica &r, bool structural = false) {
     const double skin = ip ? ip->skin : 0.5;
     if (ip && !(ip->skin >= 0 && ip->skin < 5)) return fail(SL_E_INVALID, "skin must be in [0, 5)");
     int rc = check_view(sys, skin);
@@ -1076,7 +1080,7 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
     r.vel.assign(3 * n, 0.0);
     if (vel) r.vel.assign(vel, vel + 3 * n);
     r.spin.assign(3 * n, 0.0);
-    if (sys->spin) r.spin.assign(sys->spin, sys->spin + 3 * n);
+    if (sys->spin && !structural) r.spin.assign(sys->spin, sys->spin + 3 * n);
     for (int64_t i = 0; i < n; i++)
         if (sys->types[i] != 0) r.spin[3 * i] = r.spin[3 * i + 1] = r.spin[3 * i + 2] = 0.0;
     RepDev &d = r.dev;
@@ -1091,7 +1095,13 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
     d.skin = skin;
     d.active = 1;
     d.step_end = LLONG_MAX;
+    d.mass[0] = mass_of(0);
+    d.mass[1] = mass_of(1);
     if (ip) {
+        for (int t = 0; t < 2; t++) {
+            if (!(ip->mass[t] >= 0 && std::isfinite(ip->mass[t]))) return fail(SL_E_INVALID, "masses must be >= 0");
+            if (ip->mass[t] > 0) d.mass[t] = ip->mass[t];
+        }
         if (!(ip->dt != 0 && std::isfinite(ip->dt))) return fail(SL_E_INVALID, "dt must be finite and non-zero");
         if (ip->mid_cap < 1 || ip->mid_cap > 1000) return fail(SL_E_INVALID, "mid_cap must be in [1, 1000]");
         if (ip->K_corr < 0 || ip->K_corr > 64) return fail(SL_E_INVALID, "K_corr must be in [0, 64]");
@@ -1145,6 +1155,25 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
 // model API
 // ---------------------------------------------------------------------------
 
+// The structural-only model in the spin-aware layout: its radial and angular
+// coefficients, zero magnetic coefficients, and per species W0 with zero
+// columns for the magnetic channels; with no spins both define one energy.
+static std::vector<double> expand_structural(const double *p) {
+    std::vector<double> out(N_PARAMS, 0.0);
+    std::copy(p, p + P_CEX, out.begin());   // c^R, c^A
+    size_t src = P_CEX, dst = P_MLP;
+    for (int t = 0; t < 2; t++) {
+        for (int h = 0; h < NH; h++)
+            for (int d = 0; d < DS; d++) out[dst + (size_t)h * ND + d] = p[src + (size_t)h * DS + d];
+        src += (size_t)NH * DS;
+        dst += (size_t)NH * ND;
+        for (int k = 0; k < 2 * NH + 1; k++) out[dst + k] = p[src + k];   // b0, w1, b1
+        src += 2 * NH + 1;
+        dst += 2 * NH + 1;
+    }
+    return out;
+}
+
 extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params, size_t n_params,
                                 nep_model **out) {
     if (!out) return fail(SL_E_INVALID, "out is NULL");
@@ -1154,7 +1183,11 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
         hp->n_species != 2 || hp->rc_R != RC_R || hp->rc_A != RC_A)
         return fail(SL_E_INVALID, "unsupported hyper-parameters (this build: n_max_R 8, n_max_A 6, l_max 4, "
                                   "basis_K 8, n_hidden 64, 2 species, rc 6.0/4.5)");
-    if (n_params != (size_t)N_PARAMS) return fail(SL_E_INVALID, "expected 15438 parameters");
+    if (hp->structural != 0 && hp->structural != 1) return fail(SL_E_INVALID, "structural must be 0 or 1");
+    const size_t want = hp->structural ? (size_t)N_PARAMS_STRUCT : (size_t)N_PARAMS;
+    if (n_params != want)
+        return fail(SL_E_INVALID, hp->structural ? "expected 5570 parameters (structural-only model)"
+                                                 : "expected 15438 parameters");
     for (size_t k = 0; k < n_params; k++)
         if (!std::isfinite(params[k])) return fail(SL_E_INVALID, "non-finite parameter");
     int ndev = 0;
@@ -1163,7 +1196,9 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
         return fail(SL_E_NOLIB, "no HIP device");
     }
     auto m = std::make_unique<nep_model>();
-    m->p.assign(params, params + n_params);
+    m->structural = hp->structural == 1;
+    if (m->structural) m->p = expand_structural(params);
+    else m->p.assign(params, params + n_params);
     std::vector<double> h64;
     std::vector<float> h32;
     model_layout(m->p, h64);
@@ -1204,7 +1239,7 @@ static int eval_common(const nep_model *mc, const sl_system_view *sys, sl_precis
     nep_model *m = const_cast<nep_model *>(mc);
     int rc = check_prec(prec);
     if (rc) return rc;
-    if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r))) return rc;
+    if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r, m->structural))) return rc;
     // one evaluation engine per model: the work arrays of another precision,
     // or of a system more than eight times larger, are released first
     for (int q = 0; q < 3; q++)
@@ -1290,15 +1325,16 @@ extern "C" int nep_spin_descriptors(const nep_model *m, const sl_system_view *sy
     int rc = eval_common(m, sys, prec, r, e);
     if (rc) return rc;
     const bool dev = ex && ex->device_ptrs;
+    const int nd = m->structural ? DS : ND;   // row width the caller receives
     std::vector<double> qh, fh;
     double *Q = q, *P = Fp;
     if (dev) {
-        if (q) { qh.resize((size_t)r.n * ND); Q = qh.data(); }
-        if (Fp) { fh.resize((size_t)r.n * ND); P = fh.data(); }
+        if (q) { qh.resize((size_t)r.n * nd); Q = qh.data(); }
+        if (Fp) { fh.resize((size_t)r.n * nd); P = fh.data(); }
     }
-    if (Q) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.q, ND, DP, Q) : e->download_rows(&r, e->w32.q, ND, DP, Q);
+    if (Q) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.q, nd, DP, Q) : e->download_rows(&r, e->w32.q, nd, DP, Q);
     if (rc) return rc;
-    if (P) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.Fp, ND, DP, P) : e->download_rows(&r, e->w32.Fp, ND, DP, P);
+    if (P) rc = prec == SL_FP64 ? e->download_rows(&r, e->w64.Fp, nd, DP, P) : e->download_rows(&r, e->w32.Fp, nd, DP, P);
     if (rc) return rc;
     if (dev) {
         hipStream_t ust = ex->hip_stream ? (hipStream_t)ex->hip_stream : e->st;
@@ -1339,7 +1375,7 @@ extern "C" int sl_create(const nep_model *m, const sl_system_view *sys, const do
     int rc = check_prec(prec);
     if (rc) return rc;
     auto s = std::make_unique<sl_sim>();
-    if ((rc = make_replica(sys, vel, colour, ip, true, s->r))) return rc;
+    if ((rc = make_replica(sys, vel, colour, ip, !m->structural, s->r, m->structural))) return rc;
     s->eng.M = const_cast<nep_model *>(m);
     s->eng.prec = prec;
     s->eng.K_corr = ip->K_corr;
@@ -1711,7 +1747,7 @@ extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const
     if (ip->sc_tol != 0) return fail(SL_E_INVALID, "the replica server runs a fixed number of corrector passes");
     if (n_steps < 1) return fail(SL_E_INVALID, "n_steps must be >= 1");
     auto r = std::make_unique<Replica>();
-    int rc = make_replica(sys, vel, colour, ip, true, *r);
+    int rc = make_replica(sys, vel, colour, ip, !sv->m->structural, *r, sv->m->structural);
     if (rc) return rc;
     r->n_steps = n_steps;
     r->bytes = sl_replica_bytes(r->n, sv->cfg.precision);

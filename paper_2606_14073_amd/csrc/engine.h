@@ -17,6 +17,7 @@ enum { F_REBUILD = 0, F_OVERFLOW = 1, F_COLOUR = 2, F_NONFINITE = 3, NFLAGS = 8 
 // Slot-major neighbour arrays are indexed [slot * N + atom].
 struct Sys {
     int N, N_fe, n_rep, n_cells;
+    int mag;               // 1: spin-aware model; 0: structural-only (no spin work, N_fe = species-0 count)
     const int *rid;        // [N]
     const int *orig;       // [N] index in the replica's caller order
     RepDev *rep;           // [n_rep]

@@ -15,7 +15,7 @@ __global__ void k_kick(Sys S) {
     if (i >= S.N) return;
     const RepDev &R = S.rep[S.rid[i]];
     if (!R.active) return;
-    const double c = 0.5 * R.dt * KAPPA / mass_of(i < S.N_fe ? 0 : 1);
+    const double c = 0.5 * R.dt * KAPPA / R.mass[i < S.N_fe ? 0 : 1];
     d4 v = S.vel[i];
     const d4 f = S.force[i];
     v.x += c * f.x;
@@ -49,7 +49,7 @@ __global__ void k_langevin(Sys S) {
     const RepDev &R = S.rep[S.rid[i]];
     if (!R.active || R.ensemble != 1) return;
     const double c1 = exp(-R.gammaL * R.dt);
-    const double sig = sqrt((1.0 - c1 * c1) * KAPPA * KB * temperature(R) / mass_of(i < S.N_fe ? 0 : 1));
+    const double sig = sqrt((1.0 - c1 * c1) * KAPPA * KB * temperature(R) / R.mass[i < S.N_fe ? 0 : 1]);
     double xi[3];
     gauss3(R.seed, (uint32_t)S.orig[i], (unsigned long long)R.step, 0u, xi);
     d4 v = S.vel[i];
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(256) k_obs_partial(Sys S, Work<real> W, const 
         const RepDev &R = S.rep[c.rid];
         const int fe = i < S.N_fe;
         const d4 vel = S.vel[i], s = S.spin[i], H = S.field[i], p = S.pos[i], F = S.force[i];
-        const double m = mass_of(fe ? 0 : 1);
+        const double m = R.mass[fe ? 0 : 1];
         v[0] = (double)W.Ei[i];
         v[1] = 0.5 * m * (vel.x * vel.x + vel.y * vel.y + vel.z * vel.z) / KAPPA;
         if (fe) {

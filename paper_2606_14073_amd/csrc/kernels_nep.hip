@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
     for (int n = 0; n < NR; n++) qR[n] = qE[n] = qD[n] = qA[n] = qS[n] = 0;
     real si[3];
     load_spin(spin, i, si);
-    if (fe) {
+    if (fe && S.mag) {
         real FR[NB], FE[NB], FD[NB], FA[NB], FS[NB];
 #pragma unroll
         for (int k = 0; k < NB; k++) FR[k] = FE[k] = FD[k] = FA[k] = FS[k] = 0;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
 #pragma unroll
                 for (int k = 0; k < NB; k++) FR[k] += f[k];
             }
-            const int tau = 2 + part;
+            const int tau = (fe ? 0 : 2) + part;
             for (int n = 0; n < NR; n++) {
                 const int o = (tau * NR + n) * NB;
                 real r_ = 0;
@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
     for (int part = 0; part < nparts; part++) {
         const int tau = (fe ? 0 : 2) + part;
         const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
-        const bool spins = fe && part == 0;
+        const bool spins = S.mag && fe && part == 0;
         const int b = part ? nfe : 0, e = part ? cnt : nfe;
         const int rounds = (smax[part] + 7) >> 3;
         // this lane's neighbour index two rounds ahead, position and spin one round ahead
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
         for (int m = 0; m < NLM; m++) An[m] = my[n * NLM + m];
         __syncthreads();
     }
-    if (fe) {
+    if (fe && S.mag) {
 #pragma unroll
         for (int x = 0; x < NA; x++)
 #pragma unroll
@@ -503,7 +503,6 @@ typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MLP_WAVES = 8;           // 8 wavefronts x 16 atoms per workgroup
 constexpr int MLP_ATOMS = 16 * MLP_WAVES;
-constexpr int DPT = 112;               // descriptor rows padded to 7 tiles of 16
 // LDS row strides of W0^T and of the per-wave hidden tile. The MFMA operand
 // reads walk 16 rows (lanes i16) and 4 columns (lanes kq); a stride of 2
 // dwords mod 64 for 8-byte and 4 dwords mod 64 for 4-byte elements puts those
@@ -519,12 +518,15 @@ struct MlpLds<float> {
     static constexpr int LD = NH + 4;
 };
 
-template <typename real>
+// KD: descriptor entries the read-out contracts over (104 for the spin-aware
+// model, 40 for the structural-only one, whose 37 entries lead each row)
+template <typename real, int KD>
 __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real> W, int nbFe) {
     typedef typename MF<real>::acc_t acc_t;
     constexpr int WLD = MlpLds<real>::LD, GLD = MlpLds<real>::LD;
     constexpr bool f64 = sizeof(real) == 8;
-    __shared__ real sW[DPT * WLD];
+    constexpr int KDT = (KD + 15) / 16 * 16, NT = KDT / 16;
+    __shared__ real sW[KDT * WLD];
     __shared__ real sG[f64 ? 1 : MLP_WAVES * 16 * GLD];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool fe = (int)blockIdx.x < nbFe;
@@ -532,9 +534,9 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
     const int end = fe ? S.N_fe : S.N;
     const int a0 = (fe ? blockIdx.x * MLP_ATOMS : S.N_fe + (blockIdx.x - nbFe) * MLP_ATOMS) + wave * 16;
     const real *W0 = M.W0 + (size_t)t * DP * NH;
-    for (int x = threadIdx.x; x < DPT * NH; x += blockDim.x) {
+    for (int x = threadIdx.x; x < KDT * NH; x += blockDim.x) {
         const int d = x / NH, h = x - d * NH;
-        sW[d * WLD + h] = d < DP ? W0[d * NH + h] : real(0);
+        sW[d * WLD + h] = d < KD ? W0[d * NH + h] : real(0);
     }
     __syncthreads();
     const int i16 = lane & 15, kq = lane >> 4;
@@ -546,16 +548,16 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
         // accumulator layout, element r of tile mt in lane l is Z^T[16 mt +
         // l/16 + 4 r][l % 16], which is exactly the B operand lane l supplies
         // for k-step ks = 4 mt + r of Fp^T = W0^T G^T: no transposition.
-        real qa[DP / 4];
+        real qa[KD / 4];
 #pragma unroll
-        for (int ks = 0; ks < DP / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
+        for (int ks = 0; ks < KD / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
         acc_t z[4];
 #pragma unroll
         for (int mt = 0; mt < 4; mt++)
 #pragma unroll
             for (int r = 0; r < 4; r++) z[mt][r] = M.b0[t * NH + 16 * mt + kq + 4 * r];
 #pragma unroll
-        for (int ks = 0; ks < DP / 4; ks++) {
+        for (int ks = 0; ks < KD / 4; ks++) {
 #pragma unroll
             for (int mt = 0; mt < 4; mt++)
                 z[mt] = MF<real>::mma(sW[(ks * 4 + kq) * WLD + mt * 16 + i16], qa[ks], z[mt]);
@@ -576,12 +578,13 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
         e += __shfl_xor(e, 32);
         if (kq == 0 && rv) W.Ei[arow] = M.b1[t] + e;
         // Fp^T = W0^T G^T: A = W0^T tile from LDS, B = this lane's g; the
-        // seven descriptor tiles in two passes (4 + 3) to bound the registers
+        // descriptor tiles in passes of at most four to bound the registers
         real *fp = W.Fp + (size_t)(rv ? arow : 0) * DP;
 #pragma unroll
         for (int half = 0; half < 2; half++) {
             constexpr int H0 = 4;
-            const int d0 = half ? H0 : 0, nd = half ? DPT / 16 - H0 : H0;
+            const int d0 = half ? H0 : 0, nd = half ? NT - H0 : (NT < H0 ? NT : H0);
+            if (nd <= 0) continue;
             acc_t f[H0];
 #pragma unroll
             for (int x = 0; x < H0; x++) f[x] = acc_t{0, 0, 0, 0};
@@ -598,7 +601,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
                         const int d = (d0 + x) * 16 + kq + 4 * r;
-                        if (x < nd && d < DP) fp[d] = f[x][r];
+                        if (x < nd && d < KD) fp[d] = f[x][r];
                     }
             }
         }
@@ -616,12 +619,12 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
             // input->hidden contraction in BF16 (FP32 sums): 16x16x16 blocks,
             // A[i][4kq..4kq+3] and B[4kq..4kq+3][j] packed four to a lane
             const float *Wb = M.W0bf + (size_t)t * DP * NH;
-            for (int ks = 0; ks < DPT / 16; ks++) {
+            for (int ks = 0; ks < NT; ks++) {
                 bf16x4_t a;
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                     const int d = ks * 16 + 4 * kq + u;
-                    const float v = (rv && d < DP) ? bf16_round((float)qrow[d]) : 0.f;
+                    const float v = (rv && d < KD) ? bf16_round((float)qrow[d]) : 0.f;
                     a[u] = (short)(__float_as_uint(v) >> 16);
                 }
 #pragma unroll
@@ -630,7 +633,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
                         const int d = ks * 16 + 4 * kq + u;
-                        const float v = d < DP ? Wb[d * NH + jt * 16 + i16] : 0.f;
+                        const float v = d < KD ? Wb[d * NH + jt * 16 + i16] : 0.f;
                         b[u] = (short)(__float_as_uint(v) >> 16);
                     }
                     acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[jt], 0, 0, 0);
@@ -641,11 +644,11 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
     }
     if (!done) {
         // this lane's 26 descriptor values, all loads in flight at once
-        real qa[DP / 4];
+        real qa[KD / 4];
 #pragma unroll
-        for (int ks = 0; ks < DP / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
+        for (int ks = 0; ks < KD / 4; ks++) qa[ks] = rv ? qrow[ks * 4 + kq] : real(0);
 #pragma unroll
-        for (int ks = 0; ks < DP / 4; ks++) {
+        for (int ks = 0; ks < KD / 4; ks++) {
 #pragma unroll
             for (int jt = 0; jt < 4; jt++)
                 acc[jt] = MF<real>::mma(qa[ks], sW[(ks * 4 + kq) * WLD + jt * 16 + i16], acc[jt]);
@@ -678,21 +681,21 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
     }
     __syncthreads();
     // Fp = G W0: A[i][k] = G[i][k], B[k][j] = W0[k][j] = sW[j][k]
-    acc_t f[DPT / 16];
+    acc_t f[NT];
 #pragma unroll
-    for (int jt = 0; jt < DPT / 16; jt++) f[jt] = acc_t{0, 0, 0, 0};
+    for (int jt = 0; jt < NT; jt++) f[jt] = acc_t{0, 0, 0, 0};
     for (int ks = 0; ks < NH / 4; ks++) {
         const real a = g[i16 * GLD + ks * 4 + kq];
 #pragma unroll
-        for (int jt = 0; jt < DPT / 16; jt++) f[jt] = MF<real>::mma(a, sW[(jt * 16 + i16) * WLD + ks * 4 + kq], f[jt]);
+        for (int jt = 0; jt < NT; jt++) f[jt] = MF<real>::mma(a, sW[(jt * 16 + i16) * WLD + ks * 4 + kq], f[jt]);
     }
 #pragma unroll
-    for (int jt = 0; jt < DPT / 16; jt++) {
+    for (int jt = 0; jt < NT; jt++) {
         const int col = jt * 16 + i16;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int row = a0 + MF<real>::row(kq, r);
-            if (row < end && col < DP) W.Fp[(size_t)row * DP + col] = f[jt][r];
+            if (row < end && col < KD) W.Fp[(size_t)row * DP + col] = f[jt][r];
         }
     }
 }
@@ -744,7 +747,7 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
     for (int p = 0; p < 2; p++) {
         real CR[NB], CS[NB];
         contract((C + P_CR) + (2 * t + p) * NR * NB, Fp + D_R, NR, CR);
-        if (fe) {
+        if (fe && S.mag) {
             contract((C + P_CSI) + p * NR * NB, Fp + D_SI, NR, CS);
         } else {
 #pragma unroll
@@ -756,7 +759,7 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
             o[p * 2 * NB + NB + k] = CS[k];
         }
     }
-    if (fe) mag_coef(C, Fp, W.mcoef + (size_t)i * MCOEF);
+    if (fe && S.mag) mag_coef(C, Fp, W.mcoef + (size_t)i * MCOEF);
 }
 
 // the exchange, DMI and anisotropic-exchange coefficients alone, spin carriers
@@ -807,7 +810,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
     const real *Fp = W.Fp + (size_t)i * DP;
     const int toff = (fe ? 0 : 1) * 2 * NB;   // the neighbours' blocks for this species
     real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
-    if (fe) {
+    if (fe && S.mag) {
         real si[3];
         load_spin(S.spin, i, si);
         const real os2 = real(2) * Fp[D_OS];
@@ -842,7 +845,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 const real radial = dgR + dgS * a * a;
                 const real ks = real(2) * gS * a * ir;
                 real Gj[3];
-                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, part == 0, S.spin, j, r, ir, rh, f, df, Gj);
+                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) {
                     const real G = radial * rh[x] + ks * (si[x] - a * rh[x]);
@@ -854,7 +857,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
     } else {
         for (int part = 0; part < 2; part++) {
             real CR[NB];
-            contract((C + P_CR) + (2 + part) * NR * NB, Fp + D_R, NR, CR);
+            contract((C + P_CR) + ((fe ? 0 : 2) + part) * NR * NB, Fp + D_R, NR, CR);
             const int b = part ? nfe : 0, e = part ? cnt : nfe;
             int j1_ = b < e ? S.nbrR[(size_t)(b) * ld + i] : 0;
             int j2_ = b + 1 < e ? S.nbrR[(size_t)(b + 1) * ld + i] : j1_;
@@ -875,7 +878,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 radial_basis_d(r, rc, f, df);
                 const real g = dotk(CR, df);
                 real Gj[3];
-                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, part == 0, S.spin, j, r, ir, rh, f, df, Gj);
+                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) F[x] += g * rh[x] - Gj[x];
             }
@@ -973,19 +976,22 @@ __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__
 // (dE_i/dd_ij, h_ij); the gather forms every sum in slot order.
 // -------------------------------------------------------------------------
 
-// Spin carriers and the other species run as two launches: the latter keep
-// no QS block, so that twice as many of their workgroups fit in a CU's LDS.
+// Each species runs as its own launch over atoms [first, last). Atoms without
+// spin work (the second species, or every atom of a structural-only model)
+// keep no QS block, so that twice as many of their workgroups fit in a CU's
+// LDS.
 template <bool FE>
 constexpr int qstride() { return (FE ? 2 : 1) * NA * NLM + 1; }
 
 template <typename real, bool FE>
-__global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restrict__ C, Work<real> W) {
+__global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restrict__ C, Work<real> W, int first,
+                                                    int last) {
     constexpr int QSTRIDE = qstride<FE>();
     __shared__ real sQ[ANG_ATOMS * QSTRIDE];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
-    constexpr bool fe = FE;
-    int i = (FE ? 0 : S.N_fe) + blockIdx.x * ANG_ATOMS + slot;
-    if (i >= (FE ? S.N_fe : S.N)) i = -1;
+    const bool fe = first < S.N_fe;    // species 0: the pair types tau = 0, 1
+    int i = first + blockIdx.x * ANG_ATOMS + slot;
+    if (i >= last) i = -1;
     real *Q = sQ + slot * QSTRIDE;   // QA[n][m], then QS[n][m] on spin carriers
     if (i >= 0) {
         const real *Fp = W.Fp + (size_t)i * DP;
@@ -1021,7 +1027,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
     for (int part = 0; part < 2; part++) {
         const int tau = (fe ? 0 : 2) + part;
         const real *cA = C + P_CA + tau * NA * NB, *cS = C + P_CSA + tau * NA * NB;
-        const bool spins = fe && part == 0;
+        const bool spins = FE && part == 0;
         const int b = part ? nfe : 0, e = part ? cnt : nfe;
         // this lane's neighbour index two rounds ahead, its position one round ahead
         int jc = b + lane < e ? S.nbrA[(size_t)(b + lane) * ld + i] : 0;
@@ -1151,7 +1157,7 @@ __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S.N) return;
     const size_t ld = S.N;
-    const bool fe = k < S.N_fe;
+    const bool fe = S.mag && k < S.N_fe;   // spin carrier
     real F[3], h[3];
     {
         const real *a = W.ownR + (size_t)k * 6;
@@ -1408,7 +1414,9 @@ void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int 
     if (S.N == 0) return;
     NEP_SPLIT(MLP_ATOMS)
     const int nb = mode == PASS_FULL ? nb_fe + nb_ge : nb_fe;
-    if (nb) hipLaunchKernelGGL(k_mlp<real>, dim3(nb), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
+    if (!nb) return;
+    if (S.mag) hipLaunchKernelGGL((k_mlp<real, DP>), dim3(nb), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
+    else hipLaunchKernelGGL((k_mlp<real, DS_PAD>), dim3(nb), dim3(64 * MLP_WAVES), 0, st, S, M, W, nb_fe);
 }
 
 template <typename real>
@@ -1417,15 +1425,24 @@ void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &
     NEP_SPLIT(256)
     hipLaunchKernelGGL(k_radial_coef<real>, dim3(nblk(S.N, 256)), dim3(256), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_bwd_radial<real>, dim3(nb_fe + nb_ge), dim3(256), 0, st, S, M.cR, W, nb_fe);
-    if (nb_fe) hipLaunchKernelGGL(k_bwd_mag<real>, dim3(nb_fe), dim3(256), 0, st, S, M.cR, W);
+    if (nb_fe && S.mag) hipLaunchKernelGGL(k_bwd_mag<real>, dim3(nb_fe), dim3(256), 0, st, S, M.cR, W);
 }
 
 template <typename real>
 void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(ANG_ATOMS)
-    if (nb_fe) hipLaunchKernelGGL((k_bwd_angular<real, true>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
-    if (nb_ge) hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
+    if (nb_fe) {
+        if (S.mag)
+            hipLaunchKernelGGL((k_bwd_angular<real, true>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, 0,
+                               S.N_fe);
+        else
+            hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, 0,
+                               S.N_fe);
+    }
+    if (nb_ge)
+        hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, S.N_fe,
+                           S.N);
 }
 
 template <typename real>

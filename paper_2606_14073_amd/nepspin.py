@@ -43,7 +43,11 @@ class NepError(RuntimeError):
 
 class HParams(ct.Structure):
     _fields_ = [("n_max_R", ct.c_int), ("n_max_A", ct.c_int), ("l_max", ct.c_int), ("basis_K", ct.c_int),
-                ("n_hidden", ct.c_int), ("n_species", ct.c_int), ("rc_R", ct.c_double), ("rc_A", ct.c_double)]
+                ("n_hidden", ct.c_int), ("n_species", ct.c_int), ("rc_R", ct.c_double), ("rc_A", ct.c_double),
+                ("structural", ct.c_int)]
+
+N_PARAMS = 15438
+N_PARAMS_STRUCT = 5570     # structural-only NEP: c^R, c^A, per species W0[64][37], b0, w1, b1
 
 
 class SystemView(ct.Structure):
@@ -60,7 +64,7 @@ class IntegratorParams(ct.Structure):
                 ("B1", ct.c_double * 3), ("alpha_s", ct.c_double), ("gamma_L", ct.c_double),
                 ("n_ramp", ct.c_int64), ("ensemble", ct.c_int), ("K_corr", ct.c_int), ("mid_tol", ct.c_double),
                 ("mid_cap", ct.c_int), ("seed", ct.c_uint64), ("skin", ct.c_double), ("sc_tol", ct.c_double),
-                ("sc_max", ct.c_int), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
+                ("sc_max", ct.c_int), ("mass", ct.c_double * 2), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
 
 
 class Observables(ct.Structure):
@@ -147,7 +151,8 @@ def _i32(a):
 
 def system_view(types, pos, spin, box, pbc=(1, 1, 1), mu_s=1.0, B=(0.0, 0.0, 0.0)):
     """Build an sl_system_view; returns (view, keep-alive arrays)."""
-    t, p, s = _i32(types), _f64(pos), _f64(spin)
+    t, p = _i32(types), _f64(pos)
+    s = _f64(spin) if spin is not None else None
     v = SystemView()
     v.n_atoms = t.shape[0]
     v.types = t.ctypes.data
@@ -163,7 +168,7 @@ def system_view(types, pos, spin, box, pbc=(1, 1, 1), mu_s=1.0, B=(0.0, 0.0, 0.0
 
 def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s=0.0, gamma_L=0.0, n_ramp=0,
                       ensemble=0, K_corr=1, mid_tol=1e-15, mid_cap=50, seed=0x5EED, skin=0.5, sc_tol=0.0,
-                      sc_max=30, sc_depth=0, sc_reg=1e-10):
+                      sc_max=30, sc_depth=0, sc_reg=1e-10, mass=(0.0, 0.0)):
     ip = IntegratorParams()
     ip.dt, ip.T0, ip.T1 = dt, T0, T0 if T1 is None else T1
     for a in range(3):
@@ -172,14 +177,19 @@ def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s
     ip.alpha_s, ip.gamma_L, ip.n_ramp, ip.ensemble = alpha_s, gamma_L, n_ramp, ensemble
     ip.K_corr, ip.mid_tol, ip.mid_cap, ip.seed, ip.skin = K_corr, mid_tol, mid_cap, seed, skin
     ip.sc_tol, ip.sc_max, ip.sc_depth, ip.sc_reg = sc_tol, sc_max, sc_depth, sc_reg
+    ip.mass[0], ip.mass[1] = mass
     return ip
 
 
 class Model:
+    """nep_model_create: the spin-aware NEP (15,438 parameters) or the
+    structural-only one (5,570 parameters), told apart by the length."""
+
     def __init__(self, params):
         L = load()
-        hp = HParams(8, 6, 4, 8, 64, 2, 6.0, 4.5)
         p = _f64(params)
+        self.structural = p.size == N_PARAMS_STRUCT
+        hp = HParams(8, 6, 4, 8, 64, 2, 6.0, 4.5, int(self.structural))
         h = ct.c_void_p()
         _check(L.nep_model_create(ct.byref(hp), _p(p), p.size, ct.byref(h)))
         self.h = h
@@ -223,8 +233,9 @@ class Model:
     def descriptors(self, types, pos, spin, box, pbc=(1, 1, 1), *, precision="fp64"):
         v, keep = system_view(types, pos, spin, box, pbc)
         n = v.n_atoms
-        q = np.zeros((n, 102))
-        Fp = np.zeros((n, 102))
+        nd = 37 if self.structural else 102
+        q = np.zeros((n, nd))
+        Fp = np.zeros((n, nd))
         _check(load().nep_spin_descriptors(self.h, ct.byref(v), PRECISION[precision], _p(q), _p(Fp), None))
         return q, Fp
 
