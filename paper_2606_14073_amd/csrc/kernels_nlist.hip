@@ -136,10 +136,13 @@ __device__ inline void sort_row(int *row, int n) {
     }
 }
 
+// One lane per atom: the radial-set list from the 27 surrounding cells,
+// sorted by atom index in LDS; the angular-set list is the sorted radial row
+// filtered by distance (rc_A + skin < rc_R + skin), so it comes out sorted
+// and each of its entries knows its radial slot (a2r) without a search.
 __global__ void __launch_bounds__(BLK) k_build(Sys S, double rl2R, double rl2A) {
     if (S.flags[F_REBUILD] == 0) return;
     __shared__ int rowR[MAXR * BLK];
-    __shared__ int rowA[MAXA * BLK];
     const int t = threadIdx.x;
     const int i = blockIdx.x * BLK + t;
     if (i >= S.N) return;
@@ -150,56 +153,61 @@ __global__ void __launch_bounds__(BLK) k_build(Sys S, double rl2R, double rl2A) 
     axis_offsets(R, 0, cx, ox, nx);
     axis_offsets(R, 1, cy, oy, ny);
     axis_offsets(R, 2, cz, oz, nz);
-    int nr = 0, na = 0;
+    int nr = 0;
     for (int a = 0; a < nx; a++)
         for (int b = 0; b < ny; b++)
             for (int c = 0; c < nz; c++) {
                 const int cell = R.cell_base + (ox[a] * R.nc[1] + oy[b]) * R.nc[2] + oz[c];
                 const int beg = S.cell_start[cell], cnt = S.cell_cnt[cell];
+                // the next atom's index and position are loaded one ahead
+                int jn = cnt > 0 ? S.cell_atoms[beg] : 0;
+                d4 pn = S.pos[jn];
                 for (int q = 0; q < cnt; q++) {
-                    const int j = S.cell_atoms[beg + q];
+                    const int j = jn;
+                    const d4 pj = pn;
+                    if (q + 1 < cnt) {
+                        jn = S.cell_atoms[beg + q + 1];
+                        pn = S.pos[jn];
+                    }
                     if (j == i) continue;
                     double dx, dy, dz;
-                    min_image(R, pi, S.pos[j], dx, dy, dz);
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < rl2R) {
+                    min_image(R, pi, pj, dx, dy, dz);
+                    if (dx * dx + dy * dy + dz * dz < rl2R) {
                         if (nr < MAXR) rowR[nr * BLK + t] = j;
                         nr++;
                     }
-                    if (r2 < rl2A) {
-                        if (na < MAXA) rowA[na * BLK + t] = j;
-                        na++;
-                    }
                 }
             }
-    if (nr > MAXR || na > MAXA) {
-        atomicOr(&S.flags[F_OVERFLOW], 1);
-        atomicOr(&S.rep[S.rid[i]].failed, 1);
-        nr = min(nr, MAXR);
-        na = min(na, MAXA);
-    }
+    bool over = nr > MAXR;
+    nr = min(nr, MAXR);
     sort_row(rowR + t, nr);
-    sort_row(rowA + t, na);
-    int fe = 0;
+    int fe = 0, na = 0, fea = 0;
     for (int s = 0; s < nr; s++) {
         const int j = rowR[s * BLK + t];
         S.nbrR[(size_t)s * S.N + i] = j;
         fe += j < S.N_fe;
+        double dx, dy, dz;
+        min_image(R, pi, S.pos[j], dx, dy, dz);
+        if (dx * dx + dy * dy + dz * dz < rl2A) {
+            if (na < MAXA) {
+                S.nbrA[(size_t)na * S.N + i] = j;
+                S.a2r[(size_t)na * S.N + i] = s;
+            }
+            na++;
+            fea += j < S.N_fe;
+        }
     }
+    over |= na > MAXA;
+    na = min(na, MAXA);
+    fea = min(fea, na);
     S.cntR[i] = nr;
     S.cntFeR[i] = fe;
-    if (i < S.N_fe && fe > MAXFE) {
+    S.cntA[i] = na;
+    S.cntFeA[i] = fea;
+    if (over || (S.mag && i < S.N_fe && fe > MAXFE)) {
         atomicOr(&S.flags[F_OVERFLOW], 1);
         atomicOr(&S.rep[S.rid[i]].failed, 1);
     }
-    fe = 0;
-    for (int s = 0; s < na; s++) {
-        const int j = rowA[s * BLK + t];
-        S.nbrA[(size_t)s * S.N + i] = j;
-        fe += j < S.N_fe;
-    }
-    S.cntA[i] = na;
-    S.cntFeA[i] = fe;
     S.pos_ref[i] = pi;
 }
 
@@ -224,9 +232,11 @@ __global__ void k_rev(Sys S) {
     if (S.flags[F_REBUILD] == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S.N) return;
-    const int nr = S.cntR[i], na = S.cntA[i];
+    const int na = S.cntA[i];
     int bad = 0;
-    for (int s = 0; s < nr; s++) {
+    // reverse radial slots: used by the spin couplings only (spin-carrying pairs)
+    const int nm = S.mag && i < S.N_fe ? min(S.cntFeR[i], MAXFE) : 0;
+    for (int s = 0; s < nm; s++) {
         const int j = S.nbrR[(size_t)s * S.N + i];
         const int r = find_sorted(S.nbrR, S.N, j, S.cntR[j], i);
         bad |= r < 0;
@@ -235,10 +245,8 @@ __global__ void k_rev(Sys S) {
     for (int s = 0; s < na; s++) {
         const int j = S.nbrA[(size_t)s * S.N + i];
         const int r = find_sorted(S.nbrA, S.N, j, S.cntA[j], i);
-        const int m = find_sorted(S.nbrR, S.N, i, nr, j);
-        bad |= (r < 0) | (m < 0);
+        bad |= r < 0;
         S.revA[(size_t)s * S.N + i] = r < 0 ? 0 : r;
-        S.a2r[(size_t)s * S.N + i] = m < 0 ? 0 : m;
     }
     if (bad) {
         atomicOr(&S.flags[F_OVERFLOW], 2);
