@@ -189,6 +189,32 @@ def run_self_consistent(model, nepspin, s, v, kw, n_steps, k1_ms_per_step, tol=1
     return out
 
 
+def run_structural(nepspin, n_steps, warmup=3):
+    """The structural-only NEP (no magnetic channels) on a synthetic water
+    liquid of 100^3 molecules = 3,000,000 atoms: 300 K Langevin, dt 0.5 fs,
+    skin 0.8 A, FP64 and FP32-mixed. The paper's engine runs liquid water at
+    4.38e6 atom-steps/s on one LX2 node (other hardware: context only)."""
+    s = W.config_water_bench()
+    m = nepspin.Model(W.random_params_structural())
+    v = W.maxwell_boltzmann(s.types, 300.0, masses=W.MASS_WATER)
+    ip = nepspin.integrator_params(dt=0.5, T0=300.0, gamma_L=0.02, ensemble=1, skin=0.8,
+                                   mass=tuple(W.MASS_WATER), seed=W.SEED_PHILOX)
+    out = {"workload": "synthetic water, 100^3 molecules = 3,000,000 atoms, random structural NEP, 300 K "
+                       "Langevin, dt 0.5 fs, skin 0.8 A", "steps": n_steps, "unit": "atom-steps/s",
+           "paper_lx2_node_context": 4.38e6}
+    for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
+        sim = nepspin.Sim(m, s.types, s.pos, None, s.box, s.pbc, vel=v, params=ip, precision=prec)
+        sim.integrate(warmup, observables=False)
+        t0 = time.perf_counter()
+        sim.integrate(n_steps, observables=False)
+        t1 = time.perf_counter()
+        sim.close()
+        out[key] = s.n * n_steps / (t1 - t0)
+        out[key + "_ms_per_step"] = round(1e3 * (t1 - t0) / n_steps, 3)
+    m.close()
+    return out
+
+
 def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
     """Poisson arrivals of the serving request mix (cubic FeGe cells, N
     log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed."""
@@ -284,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent midpoint leg")
+    ap.add_argument("--no-water", action="store_true", help="skip the structural-only NEP leg")
+    ap.add_argument("--water-steps", type=int, default=30)
     ap.add_argument("--sc-steps", type=int, default=20)
     ap.add_argument("--no-large", action="store_true", help="skip the 7.1M-atom precision form and the 4.2M slab")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -416,6 +444,10 @@ def main():
     if not args.no_sc:
         extra["self_consistent"] = run_self_consistent(model, nepspin, s, v0, kw, args.sc_steps, 1e3 * dt64 / K)
         print(f"self-consistent: {extra['self_consistent']}", file=sys.stderr, flush=True)
+
+    if not args.no_water:
+        extra["structural_water"] = run_structural(nepspin, args.water_steps)
+        print(f"structural-only NEP, water: {extra['structural_water']}", file=sys.stderr, flush=True)
 
     if not args.no_serving:
         extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)
