@@ -192,15 +192,15 @@ def run_self_consistent(model, nepspin, s, v, kw, n_steps, k1_ms_per_step, tol=1
 def run_structural(nepspin, n_steps, warmup=3):
     """The structural-only NEP (no magnetic channels) on a synthetic water
     liquid of 100^3 molecules = 3,000,000 atoms: 300 K Langevin, dt 0.5 fs,
-    skin 0.8 A, FP64 and FP32-mixed. The paper's engine runs liquid water at
+    skin 0.5 A, FP64 and FP32-mixed. The paper's engine runs liquid water at
     4.38e6 atom-steps/s on one LX2 node (other hardware: context only)."""
     s = W.config_water_bench()
     m = nepspin.Model(W.random_params_structural())
     v = W.maxwell_boltzmann(s.types, 300.0, masses=W.MASS_WATER)
-    ip = nepspin.integrator_params(dt=0.5, T0=300.0, gamma_L=0.02, ensemble=1, skin=0.8,
+    ip = nepspin.integrator_params(dt=0.5, T0=300.0, gamma_L=0.02, ensemble=1, skin=0.5,
                                    mass=tuple(W.MASS_WATER), seed=W.SEED_PHILOX)
     out = {"workload": "synthetic water, 100^3 molecules = 3,000,000 atoms, random structural NEP, 300 K "
-                       "Langevin, dt 0.5 fs, skin 0.8 A", "steps": n_steps, "unit": "atom-steps/s",
+                       "Langevin, dt 0.5 fs, skin 0.5 A", "steps": n_steps, "unit": "atom-steps/s",
            "paper_lx2_node_context": 4.38e6}
     for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
         sim = nepspin.Sim(m, s.types, s.pos, None, s.box, s.pbc, vel=v, params=ip, precision=prec)
