@@ -138,7 +138,9 @@ def _check(rc):
 
 
 def _p(a):
-    return None if a is None else ct.c_void_p(a.ctypes.data)
+    # data_as keeps the array alive for as long as the pointer object lives
+    # (through the call), also when the array is a temporary conversion
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
 
 
 def _f64(a):

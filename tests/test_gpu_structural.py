@@ -106,3 +106,33 @@ def test_structural_full_size_sampled(smodel, oracle):
     e, f2 = abs(got["E"] - ref["E"]) / s.n, rel_l2(got["F"], ref["F"])
     print(f"structural fp32 vs fp64, 3,000,000 atoms: |dE|/N {e:.2e} eV, F rel-l2 {f2:.2e}", flush=True)
     assert e <= 1e-6 and f2 <= 1e-5
+
+
+def test_structural_server_equals_direct(smodel):
+    """Water replicas of different sizes in the replica server: each ends
+    bitwise equal to its direct simulation."""
+    from paper_2606_14073_amd import nepspin
+    reqs = []
+    for n, T, seed in ((5, 250.0, 3), (6, 320.0, 4), (7, 280.0, 5)):
+        s = W.water_box(n, seed=seed, noise=0.05)
+        v = W.maxwell_boltzmann(s.types, T, seed=seed + 7, masses=W.MASS_WATER)
+        ip = nepspin.integrator_params(dt=0.5, T0=T, gamma_L=0.02, ensemble=1, skin=SKIN,
+                                       mass=tuple(W.MASS_WATER), seed=100 + seed)
+        reqs.append((s, v, ip))
+    steps = 10
+    direct = []
+    for s, v, ip in reqs:
+        sim = nepspin.Sim(smodel, s.types, s.pos, None, s.box, s.pbc, vel=v, params=ip)
+        sim.integrate(steps)
+        direct.append(sim.state())
+        sim.close()
+    sv = nepspin.Server(smodel, precision="fp64", steps_per_batch=4, max_slots=8)
+    ids = [sv.submit(s.types, s.pos, None, s.box, s.pbc, vel=v, params=ip, n_steps=steps) for s, v, ip in reqs]
+    sv.drain()
+    for rid, d in zip(ids, direct):
+        st = sv.poll(rid)
+        assert st["state"] == nepspin.SL_DONE and st["steps_done"] == steps
+        got = sv.fetch(rid)
+        for x, y in zip(d[:3], got[:3]):
+            assert np.array_equal(x, y)
+    sv.close()
