@@ -312,6 +312,8 @@ def main():
     ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent midpoint leg")
     ap.add_argument("--no-water", action="store_true", help="skip the structural-only NEP leg")
     ap.add_argument("--water-steps", type=int, default=30)
+    ap.add_argument("--water-only", action="store_true",
+                    help="run only the structural-only NEP leg and print its result as one JSON line")
     ap.add_argument("--sc-steps", type=int, default=20)
     ap.add_argument("--no-large", action="store_true", help="skip the 7.1M-atom precision form and the 4.2M slab")
     ap.add_argument("--large-steps", type=int, default=20)
@@ -329,6 +331,9 @@ def main():
         return
 
     from paper_2606_14073_amd import nepspin
+    if args.water_only:
+        print(json.dumps(run_structural(nepspin, args.water_steps)), flush=True)
+        return
 
     s = W.config_fp64_bench()
     params = W.random_params()
