@@ -47,7 +47,7 @@ struct ModelDev {
 template <typename real>
 struct Work {
     real *q, *Fp, *Ei, *AB;     // [N][DP], [N][DP], [N], [N][NA][NAB]
-    real *rcoef;                // [N][2][2 NB]: radial and single-ion coefficients contracted with the atom's Fp, per neighbour species
+    real *rcoef;                // [4][N][NB]: radial (blocks 0, 1) and single-ion (2, 3) coefficients contracted with the atom's Fp, per neighbour species
     real *mcoef;                // [N_fe][3 NB]: exchange, DMI, anisotropic-exchange coefficients contracted with the atom's Fp
     real *ownM;                 // [N_fe][6]: magnetic-pair sum_j dE_i/dd_ij, dE_i/ds_i
     real *pbA;                  // angular pair records [MAXA][N][4]: dE_i/dd_ij, h_ij, stored likewise

@@ -718,8 +718,9 @@ __device__ inline void put_pair(real *pb, size_t idx, const real G[3], const rea
 // Per atom i of species t, its radial-set coefficients contracted with its
 // own Fp, for each neighbour species p: CR_p[k] = sum_n c^R_{2t+p}[n][k] Fp^R_n
 // and, on spin carriers, CS_p[k] = sum_n c^si_{2t+p}[n][k] Fp^si_n (zero on
-// the others). Block [N][p][CR, CS]: a neighbour reads the NB or 2 NB values
-// of its own species. Spin carriers also get the exchange, DMI and
+// the others). Stored as [CR_0 | CR_1 | CS_0 | CS_1][N][NB]: a neighbour reads
+// the NB values of its own species (and NB more if it carries a spin), and
+// atoms adjacent in memory share cache lines. Spin carriers also get the exchange, DMI and
 // anisotropic-exchange coefficients (Fe-Fe pairs), [N_fe][CE, CD, CA].
 template <typename real>
 __device__ inline void mag_coef(const real *__restrict__ C, const real *Fp, real *m) {
@@ -742,21 +743,20 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
     const bool fe = i < S.N_fe;
     const int t = fe ? 0 : 1;
     const real *Fp = W.Fp + (size_t)i * DP;
-    real *o = W.rcoef + (size_t)i * RCOEF;
+    const size_t ld = S.N;
 #pragma unroll 1
     for (int p = 0; p < 2; p++) {
-        real CR[NB], CS[NB];
+        real CR[NB];
         contract((C + P_CR) + (2 * t + p) * NR * NB, Fp + D_R, NR, CR);
-        if (fe && S.mag) {
+        real *oR = W.rcoef + ((size_t)p * ld + i) * NB;
+#pragma unroll
+        for (int k = 0; k < NB; k++) oR[k] = CR[k];
+        if (fe && S.mag) {   // single-ion block, read only for spin-carrying partners
+            real CS[NB];
             contract((C + P_CSI) + p * NR * NB, Fp + D_SI, NR, CS);
-        } else {
+            real *oS = W.rcoef + ((size_t)(2 + p) * ld + i) * NB;
 #pragma unroll
-            for (int k = 0; k < NB; k++) CS[k] = 0;
-        }
-#pragma unroll
-        for (int k = 0; k < NB; k++) {
-            o[p * 2 * NB + k] = CR[k];
-            o[p * 2 * NB + NB + k] = CS[k];
+            for (int k = 0; k < NB; k++) oS[k] = CS[k];
         }
     }
     if (fe && S.mag) mag_coef(C, Fp, W.mcoef + (size_t)i * MCOEF);
@@ -778,13 +778,13 @@ __global__ void __launch_bounds__(256) k_mag_coef(Sys S, const real *__restrict_
 // contracted block (and its spin), so F_i = sum_j (G_ij - G_ji) needs no
 // pair records. Own sums: F_i and dE_i/ds_i (single-ion and onsite).
 template <typename real>
-__device__ inline void partner_radial(const real *cj, bool fe_j, const d4 *spin, int j, real r, real ir,
-                                      const real rh[3], const real f[NB], const real df[NB], real Gj[3]) {
-    const real dgR = dotc(cj, df);
+__device__ inline void partner_radial(const real *cR, const real *cS, bool fe_j, const d4 *spin, int j, real r,
+                                      real ir, const real rh[3], const real f[NB], const real df[NB], real Gj[3]) {
+    const real dgR = dotc(cR + (size_t)j * NB, df);
     if (fe_j) {
         real sj[3];
         load_spin(spin, j, sj);
-        const real gS = dotc(cj + NB, f), dgS = dotc(cj + NB, df);
+        const real gS = dotc(cS + (size_t)j * NB, f), dgS = dotc(cS + (size_t)j * NB, df);
         // rhat_ji = -rhat_ij
         const real a = -(sj[0] * rh[0] + sj[1] * rh[1] + sj[2] * rh[2]);
         const real radial = dgR + dgS * a * a;
@@ -808,7 +808,8 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
     const int cnt = S.cntR[i], nfe = S.cntFeR[i];
     const size_t ld = S.N;
     const real *Fp = W.Fp + (size_t)i * DP;
-    const int toff = (fe ? 0 : 1) * 2 * NB;   // the neighbours' blocks for this species
+    // the neighbours' contracted blocks for this atom's species
+    const real *nR = W.rcoef + (size_t)(fe ? 0 : 1) * ld * NB, *nS = W.rcoef + (size_t)(fe ? 2 : 3) * ld * NB;
     real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
     if (fe && S.mag) {
         real si[3];
@@ -845,7 +846,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 const real radial = dgR + dgS * a * a;
                 const real ks = real(2) * gS * a * ir;
                 real Gj[3];
-                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
+                partner_radial(nR, nS, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) {
                     const real G = radial * rh[x] + ks * (si[x] - a * rh[x]);
@@ -878,7 +879,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 radial_basis_d(r, rc, f, df);
                 const real g = dotk(CR, df);
                 real Gj[3];
-                partner_radial(W.rcoef + (size_t)j * RCOEF + toff, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
+                partner_radial(nR, nS, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) F[x] += g * rh[x] - Gj[x];
             }
