@@ -39,7 +39,8 @@ from paper_2606_14073_amd import workload as W  # noqa: E402
 PEAK = {"fp64": 78.6, "fp32": 157.3, "hbm_gbs": 8000.0}
 KERNEL_NAME = {"desc_radial": "k_desc_radial", "desc_angular": "k_desc_angular", "readout": "k_mlp",
                "bwd_radial": "k_bwd_radial", "bwd_angular": "k_bwd_angular", "gather": "k_gather",
-               "couplings": "k_assemble_*", "sweep": "k_sweep", "nlist": "k_build/k_rev", "integrate": "k_kick/..."}
+               "couplings": "k_mag_coef/k_assemble_angular", "pairs": "k_assemble_pairs", "sweep": "k_sweep",
+               "nlist": "k_build/k_rev", "integrate": "k_kick/..."}
 
 
 def pair_counts(s):
@@ -95,15 +96,15 @@ def flops_per_step(group, pc, k_corr=1):
         # channel values 144 + force/field terms 90; Fe-Ge: 36 + 30; per atom contractions
         return pc["R"] * 153 + fe_centre_fe * 234 + fe_centre_ge * 66 + Nfe * 5 * 162 + N * 2 * 162
     if group == "couplings":
-        # per spin-step pass. Radial-set assembly: per spin carrier the four channel
-        # contractions 810; per Fe-Fe pair geometry/basis 80, three coupling values and
-        # the single-ion weight 72, its tensor 21; per Fe-Ge pair 80 + 18 + 21.
-        # Spin-angular part: per spin carrier P = Fp^sa A 168; per Fe-Fe pair inside
-        # rc_A geometry/basis 75, g^sa 126, harmonics 50, contraction 336 + 48.
-        # Symmetrisation: per Fe-Fe pair geometry and rhat 33
-        per_pass = (Nfe * (810 + 168) + fe_centre_fe * (173 + 33) + fe_centre_ge * 119
-                    + pc["A_fefe"] * 635)
-        return (1 + k_corr) * per_pass
+        # per spin-step pass: per spin carrier the exchange, DMI and anisotropic
+        # contractions 486 and P = Fp^sa A 168; spin-angular part per Fe-Fe pair
+        # inside rc_A: geometry/basis 75, g^sa 126, harmonics 50, contraction 336 + 48
+        return (1 + k_corr) * (Nfe * (486 + 168) + pc["A_fefe"] * 635)
+    if group == "pairs":
+        # per spin-step pass: per spin carrier the two single-ion contractions 324;
+        # per Fe-Fe pair geometry/basis 80, three coupling values and the single-ion
+        # weight 72, its tensor 21, rhat 33; per Fe-Ge pair 80 + 18 + 21
+        return (1 + k_corr) * (Nfe * 324 + fe_centre_fe * (173 + 33) + fe_centre_ge * 119)
     if group == "readout":
         # 2 x (104 x 64) FMA per atom + tanh, energy and gradient
         per = 2 * 2 * 104 * 64 + 64 * 30

@@ -690,7 +690,8 @@ struct Engine {
         for (int p = 0; p <= last; p++) {
             // every pass sits at the same mid positions: the structural terms of the first are reused
             forward(m, w, spin_hat, p == 0 ? PASS_SPIN : PASS_SPIN_REUSE);
-            { ProfScope q(this, 6); launch_assemble(S, m, w, st); }
+            { ProfScope q(this, 6); launch_assemble_coef(S, m, w, st); }
+            { ProfScope q(this, 10); launch_assemble_pairs(S, m, w, st); }
             if (p > 0) {
                 ProfScope q(this, 9);
                 launch_spin_restore(S, st);

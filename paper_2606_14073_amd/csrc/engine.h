@@ -84,7 +84,9 @@ void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> 
 template <typename real>
 void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st);
 template <typename real>
-void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+void launch_assemble_coef(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+template <typename real>
+void launch_assemble_pairs(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
 template <typename real>
 void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, int n_colours, hipStream_t st);
 

@@ -1453,10 +1453,15 @@ void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st) {
 }
 
 template <typename real>
-void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+void launch_assemble_coef(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
     if (S.N_fe == 0) return;
     hipLaunchKernelGGL(k_mag_coef<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
     hipLaunchKernelGGL(k_assemble_angular<real>, dim3(nblk(S.N_fe, ANG_ATOMS)), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W);
+}
+
+template <typename real>
+void launch_assemble_pairs(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+    if (S.N_fe == 0) return;
     hipLaunchKernelGGL(k_assemble_pairs<real>, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, M.cR, W);
 }
 
@@ -1469,7 +1474,8 @@ void launch_assemble(const Sys &S, const ModelDev<real> &M, const Work<real> &W,
     template void launch_bwd_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t); \
     template void launch_bwd_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
     template void launch_gather<real>(const Sys &, const Work<real> &, hipStream_t);                             \
-    template void launch_assemble<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);
+    template void launch_assemble_coef<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
+    template void launch_assemble_pairs<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);
 
 NEP_INST(double)
 NEP_INST(float)
