@@ -1139,11 +1139,19 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
             rc = greedy_colour(sys, skin, col);
             if (rc) return rc;
         }
+        for (int64_t q = 0; q < r.n_fe; q++) {
+            const int c = col[r.fe_idx[q]];
+            if (c < 0 || c > 4096) return fail(SL_E_INVALID, "colour of a spin carrier must be in [0, 4096]");
+        }
+        // spin carriers stored colour by colour (caller order inside a colour):
+        // a colour class is then a contiguous run of atoms, so the coupling
+        // assembly, which writes each spin's couplings at its colour-list
+        // position, stores contiguously, and the sweep reads contiguously
+        std::stable_sort(r.fe_idx.begin(), r.fe_idx.end(), [&](int a, int b) { return col[a] < col[b]; });
         r.colour_fe.resize(r.n_fe);
         r.ncol = 0;
         for (int64_t q = 0; q < r.n_fe; q++) {
             const int c = col[r.fe_idx[q]];
-            if (c < 0 || c > 4096) return fail(SL_E_INVALID, "colour of a spin carrier must be in [0, 4096]");
             r.colour_fe[q] = c;
             r.ncol = std::max(r.ncol, c + 1);
         }
