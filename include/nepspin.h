@@ -154,7 +154,7 @@ typedef struct {
  *   force[n][3]    : F_i = -dE/dr_i, or NULL
  *   field[n][3]    : H_i = -dE/ds_i (+ mu_s mu_B B), species-0 rows; or NULL
  * The model keeps the device work arrays of its last evaluation (about
- * 11 KB per atom in FP64, 7 KB in FP32) for the next call of the same
+ * 13 KB per atom in FP64, 8 KB in FP32) for the next call of the same
  * precision; another precision, a system more than eight times smaller or
  * nep_model_destroy releases them. Calls on one model are serialised.
  * Errors: SL_E_INVALID (bad sizes/types), SL_E_BOX, SL_E_OVERFLOW (more than
