@@ -252,9 +252,17 @@ __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restri
     for (int n = 0; n < NR; n++) {
         q[D_R + n] = qR[n];
         q[D_EX + n] = qE[n];
-        q[D_DM + n] = qD[n];
-        q[D_AN + n] = qA[n];
-        q[D_SI + n] = qS[n];
+    }
+    // The structural-only read-out contracts over the first 40 entries (the
+    // zero onsite and exchange entries 37-39 included): it never reads the
+    // later magnetic channels, which stay unwritten there.
+    if (S.mag) {
+#pragma unroll
+        for (int n = 0; n < NR; n++) {
+            q[D_DM + n] = qD[n];
+            q[D_AN + n] = qA[n];
+            q[D_SI + n] = qS[n];
+        }
     }
 }
 
@@ -456,13 +464,13 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
 #pragma unroll
     for (int l = 0; l < 4; l++) {
         if (!reuse) q[D_A + 4 * n + l] = qa[l];
-        q[D_SA + 4 * n + l] = qs[l];
+        if (S.mag) q[D_SA + 4 * n + l] = qs[l];   // beyond the structural-only read-out's entries
     }
     if (!reuse) {
 #pragma unroll
         for (int m = 0; m < NLM; m++) ab[m] = An[m];
     }
-    if (fe && mode == PASS_FULL) {
+    if (fe && S.mag && mode == PASS_FULL) {   // B only for the spin-carrying backward
 #pragma unroll
         for (int m = 0; m < NLM; m++) ab[NLM + m] = Bn[m];
     }
