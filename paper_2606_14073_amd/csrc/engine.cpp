@@ -1063,6 +1063,9 @@ static int settle_layout(Engine &e, std::vector<int> &bad, bool global_flags = t
     return fail(SL_E_INVALID, "recolouring did not settle");
 }
 
+// largest replica whose spin carriers are stored colour by colour
+constexpr int64_t COLOUR_MAJOR_MAX_ATOMS = 1 << 19;
+
 static const char *colour_msg = "two spins of the same colour lie within rc_R of each other (invalid colouring)";
 
 static int make_replica(const sl_system_view *sys, const double *vel, const int32_t *colour,
@@ -1143,11 +1146,16 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
             const int c = col[r.fe_idx[q]];
             if (c < 0 || c > 4096) return fail(SL_E_INVALID, "colour of a spin carrier must be in [0, 4096]");
         }
-        // spin carriers stored colour by colour (caller order inside a colour):
-        // a colour class is then a contiguous run of atoms, so the coupling
-        // assembly, which writes each spin's couplings at its colour-list
-        // position, stores contiguously, and the sweep reads contiguously
-        std::stable_sort(r.fe_idx.begin(), r.fe_idx.end(), [&](int a, int b) { return col[a] < col[b]; });
+        // Replicas whose gathered per-atom data (about 0.4 KB per atom) fits
+        // in the 256 MB last-level cache store their spin carriers colour by
+        // colour (caller order inside a colour): a colour class is then a
+        // contiguous run of atoms, so the coupling assembly, which writes each
+        // spin's couplings at its colour-list position, stores contiguously,
+        // and the sweep reads contiguously. Larger ones keep the caller
+        // order, whose spatial locality the neighbour gathers need once the
+        // system no longer fits in that cache.
+        if (n <= COLOUR_MAJOR_MAX_ATOMS)
+            std::stable_sort(r.fe_idx.begin(), r.fe_idx.end(), [&](int a, int b) { return col[a] < col[b]; });
         r.colour_fe.resize(r.n_fe);
         r.ncol = 0;
         for (int64_t q = 0; q < r.n_fe; q++) {
