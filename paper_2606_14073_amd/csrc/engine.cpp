@@ -489,19 +489,44 @@ struct Engine {
         for (Replica *r : reps) {
             if (std::find(new_reps.begin(), new_reps.end(), r) != new_reps.end() && r->fe_off >= 0) moved.push_back(r);
         }
-        // snapshot resident state (host) when reallocating or when ranges may overlap
-        std::vector<std::vector<d4>> snap(moved.size() * 5);
+        // Snapshot the resident state (the arrays may be reallocated and the
+        // new ranges may overlap the old ones): into a device staging buffer,
+        // five state arrays of every moved replica, or into host memory when
+        // that buffer cannot be allocated.
+        size_t stage_n = 0;
+        std::vector<size_t> stage_off(moved.size());
+        for (size_t k = 0; k < moved.size(); k++) {
+            stage_off[k] = stage_n;
+            stage_n += moved[k]->n;
+        }
+        struct Staging {   // released on every way out of this function
+            d4 *p = nullptr;
+            ~Staging() {
+                if (p) (void)hipFree(p);
+            }
+        } staging;
+        if (stage_n && hipMalloc((void **)&staging.p, 5 * stage_n * sizeof(d4)) != hipSuccess) {
+            (void)hipGetLastError();
+            staging.p = nullptr;
+        }
+        d4 *const stage = staging.p;
+        std::vector<std::vector<d4>> snap(stage ? 0 : moved.size() * 5);
         for (size_t k = 0; k < moved.size(); k++) {
             Replica *r = moved[k];
             d4 *src[5] = {pos, vel, spin, force, field};
             for (int a = 0; a < 5; a++) {
-                snap[5 * k + a].resize(r->n);
-                if (r->n_fe)
-                    HIPCHK(hipMemcpyAsync(snap[5 * k + a].data(), src[a] + r->fe_off, r->n_fe * sizeof(d4),
-                                          hipMemcpyDeviceToHost, st));
+                d4 *to = nullptr;
+                hipMemcpyKind kind = hipMemcpyDeviceToDevice;
+                if (stage) {
+                    to = stage + a * stage_n + stage_off[k];
+                } else {
+                    snap[5 * k + a].resize(r->n);
+                    to = snap[5 * k + a].data();
+                    kind = hipMemcpyDeviceToHost;
+                }
+                if (r->n_fe) HIPCHK(hipMemcpyAsync(to, src[a] + r->fe_off, r->n_fe * sizeof(d4), kind, st));
                 if (r->n - r->n_fe)
-                    HIPCHK(hipMemcpyAsync(snap[5 * k + a].data() + r->n_fe, src[a] + r->ge_off,
-                                          (r->n - r->n_fe) * sizeof(d4), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipMemcpyAsync(to + r->n_fe, src[a] + r->ge_off, (r->n - r->n_fe) * sizeof(d4), kind, st));
             }
             HIPCHK(hipMemcpyAsync(&r->dev, rep + r->slot, sizeof(RepDev), hipMemcpyDeviceToHost, st));
         }
@@ -556,16 +581,18 @@ struct Engine {
         n_cells = cb;
         n_chunks = (int)h_chunks.size();
         // colour classes
+        // (counting sort: inside a colour, replica order, then atom order)
         col_ptr.assign(cmax + 1, 0);
-        std::vector<int> h_colidx;
-        h_colidx.reserve(nfe);
-        for (int c = 0; c < cmax; c++) {
-            col_ptr[c] = (int)h_colidx.size();
+        for (Replica *r : reps)
+            for (int c : r->colour_fe) col_ptr[c + 1]++;
+        for (int c = 0; c < cmax; c++) col_ptr[c + 1] += col_ptr[c];
+        std::vector<int> h_colidx(col_ptr[cmax]);
+        {
+            std::vector<int> fill(col_ptr.begin(), col_ptr.end() - 1);
             for (Replica *r : reps)
-                for (int64_t a = 0; a < r->n_fe; a++)
-                    if (!r->colour_fe.empty() && r->colour_fe[a] == c) h_colidx.push_back(r->fe_off + (int)a);
+                for (int64_t a = 0; a < (int64_t)r->colour_fe.size(); a++)
+                    h_colidx[fill[r->colour_fe[a]]++] = r->fe_off + (int)a;
         }
-        col_ptr[cmax] = (int)h_colidx.size();
         // spin carriers without a colour (evaluation only) keep their own index
         std::vector<int> h_colpos(nfe);
         for (size_t q = 0; q < nfe; q++) h_colpos[q] = (int)q;
@@ -595,12 +622,12 @@ struct Engine {
             if (mk != moved.end()) {
                 size_t m = mk - moved.begin();
                 for (int a = 0; a < 5; a++) {
-                    if (r->n_fe)
-                        HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, snap[5 * m + a].data(), r->n_fe * sizeof(d4),
-                                              hipMemcpyHostToDevice, st));
+                    const d4 *from = stage ? stage + a * stage_n + stage_off[m] : snap[5 * m + a].data();
+                    const hipMemcpyKind kind = stage ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+                    if (r->n_fe) HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, from, r->n_fe * sizeof(d4), kind, st));
                     if (r->n - r->n_fe)
-                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, snap[5 * m + a].data() + r->n_fe,
-                                              (r->n - r->n_fe) * sizeof(d4), hipMemcpyHostToDevice, st));
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, from + r->n_fe, (r->n - r->n_fe) * sizeof(d4), kind,
+                                              st));
                 }
             } else {
                 const double *src[3] = {r->pos.data(), r->vel.data(), r->spin.data()};
@@ -623,6 +650,11 @@ struct Engine {
                     HIPCHK(hipStreamSynchronize(st));
                 }
             }
+        }
+        if (stage) {
+            HIPCHK(hipStreamSynchronize(st));
+            (void)hipFree(staging.p);
+            staging.p = nullptr;
         }
         // clear the error flags, force a neighbour rebuild, then F and H
         int hflags[NFLAGS] = {0};
