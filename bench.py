@@ -65,7 +65,7 @@ def pair_counts(s):
 def flops_per_step(group, pc, k_corr=1):
     """Algorithmic FLOPs of one step's launches of a kernel group (FMA = 2),
     counted once per (centre, neighbour) pair inside the channel's cutoff and
-    once per atom; the figures per pair are listed in the design doc. The
+    once per atom; the figures per pair are in the comments below. The
     descriptor and read-out groups run one full pass, one spin-step pass over
     the spin carriers and k_corr spin-step passes that reuse the structural
     angular terms."""
