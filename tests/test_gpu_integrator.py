@@ -122,6 +122,26 @@ def test_step_parity_full_size(model, oracle):
     assert max(e) <= TOL64
 
 
+def test_step_parity_above_colour_major_bound(model, oracle):
+    """42x42x42 cells = 592,704 atoms: above the size up to which the spin
+    carriers are stored colour by colour, so this replica keeps the caller's
+    order; one full oracle step after three"""
+    from paper_2606_14073_amd import nepspin
+    kw = SCHEDULES["langevin"]
+    s = W.fege_lattice(42, 42, 42)
+    assert s.n > 1 << 19
+    p = W.random_params()
+    v = W.maxwell_boltzmann(s.types, 300.0)
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=_params(nepspin, **kw))
+    sim.integrate(3)
+    a = sim.state()
+    sim.integrate(1)
+    b = sim.state()
+    e = _compare_step(oracle, s, p, s.colour, a, b, kw)
+    print(f"592,704 atoms, step 3: {e}", flush=True)
+    assert max(e) <= TOL64
+
+
 def test_determinism_and_checkpoint(model):
     from paper_2606_14073_amd import nepspin
     kw = SCHEDULES["langevin"]
