@@ -185,7 +185,9 @@ int nep_spin_descriptors(const nep_model *m, const sl_system_view *sys, sl_preci
  *        omega = (h + alpha_s xbar x h)/(1+alpha_s^2),
  *        h = H_lin(xbar) + mu_s mu_B B_n + eta_i,
  *        eta_i = sqrt(2 alpha_s kB T_n hbar/dt) xi_i (fixed for the step),
- *      iterated until max|y'-y| <= mid_tol or mid_cap iterations;
+ *      the midpoint equation y = G(y) solved until max|G(y)-y| <= mid_tol
+ *      or mid_cap iterations, the result being G(y) (Newton steps with a
+ *      finite-difference Jacobian; mid_cap = 1 is the explicit rotation);
  *   A; then E, F, H at (R^{n+1}, S^{n+1}); B.
  * T_n = T0 + (T1-T0) min(n, n_ramp)/n_ramp and B_n likewise (constant T0, B0
  * when n_ramp = 0). xi are Philox4x32-10 normals keyed by seed, counted by
@@ -198,7 +200,7 @@ typedef struct {
     int ensemble;        /* 0 NVE (no O step, alpha_s must be 0 for NVE spins), 1 Langevin */
     int K_corr;          /* number of corrector passes (0 = predictor only)  */
     double mid_tol;      /* per-spin midpoint tolerance, e.g. 1e-15           */
-    int mid_cap;         /* per-spin midpoint iteration cap, e.g. 50          */
+    int mid_cap;         /* per-spin midpoint iteration cap, e.g. 50 (Newton) */
     uint64_t seed;       /* Philox key                                        */
     double skin;         /* Verlet skin (A); lists rebuilt when an atom moved
                             more than skin/2 since the last build             */

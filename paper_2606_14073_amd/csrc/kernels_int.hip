@@ -137,12 +137,22 @@ __device__ inline double rsqrt_nr(double x) {
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// Value of lane K of this lane's quad (lanes 4q..4q+3), by DPP.
+template <int K>
+__device__ inline double quad_bcast(double v) {
+    constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);   // quad_perm [K, K, K, K]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
 // SWEEP_L lanes share a spin: they split the neighbour gather (couplings stored
 // in colour-list order, so a wavefront reads contiguous records), reduce, and
-// then run the midpoint iteration in lockstep; lane 0 stores the result.
+// then solve the midpoint equation together (each quad of lanes evaluates the
+// rotation at four points per Newton step); lane 0 stores the result.
 // Latency is what bounds a colour class, so the loads are issued in two
 // waves: everything indexed by the colour-list position (atom, replica,
 // coupling count, self terms, the first SWEEP_R0 coupling slots of each lane,
@@ -221,15 +231,11 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     const int cap = R.mid_cap;
     const double Dxx = Axx + os, Dyy = Ayy + os, Dzz = Azz + os;   // A_i + o_i I
     double sx = s4.x, sy = s4.y, sz = s4.z;
-    double yx = sx, yy = sy, yz = sz;
-    for (int turn = 0; turn < turns; turn++) {
-    if (turn) {
-        sx = yx;
-        sy = yy;
-        sz = yz;
-    }
-    for (int it = 0; it < cap; it++) {
-        double mx = sx + yx, my = sy + yy, mz = sz + yz;
+    // G(y): the spin rotated about the precession vector taken at the
+    // midpoint m = (s + y)/|s + y| (field, damping, anisotropy and onsite
+    // terms evaluated at m), by the angle |w| tau (Rodrigues)
+    auto rotate = [&](double px, double py, double pz, double &nx, double &ny, double &nz) {
+        double mx = sx + px, my = sy + py, mz = sz + pz;
         const double mn = rsqrt_nr(mx * mx + my * my + mz * mz);
         mx *= mn;
         my *= mn;
@@ -241,34 +247,81 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
         const double wy = (h1 + al * (mz * h0 - mx * h2)) * inv;
         const double wz = (h2 + al * (mx * h1 - my * h0)) * inv;
         const double w2 = wx * wx + wy * wy + wz * wz;
-        double nx, ny, nz;
         if (w2 == 0.0) {
             nx = sx;
             ny = sy;
             nz = sz;
-        } else {
-            const double iw = rsqrt_nr(w2);
-            const double th = w2 * iw * tau, ath = fabs(th);   // negative for a backward step
-            double sn, cs, omc;
-            if (ath <= 1.0) {
-                sin_omc_taylor(th, sn, omc);
-                cs = 1.0 - omc;
-            } else {
-                sincos(th, &sn, &cs);
-                omc = 1.0 - cs;
-            }
-            const double ux = wx * iw, uy = wy * iw, uz = wz * iw;
-            const double us = ux * sx + uy * sy + uz * sz;
-            nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
-            ny = sy * cs + (uz * sx - ux * sz) * sn + uy * us * omc;
-            nz = sz * cs + (ux * sy - uy * sx) * sn + uz * us * omc;
+            return;
         }
-        const double diff = fmax(fabs(nx - yx), fmax(fabs(ny - yy), fabs(nz - yz)));
-        yx = nx;
-        yy = ny;
-        yz = nz;
-        if (diff <= tol) break;
-    }
+        const double iw = rsqrt_nr(w2);
+        const double th = w2 * iw * tau, ath = fabs(th);   // negative for a backward step
+        double sn, cs, omc;
+        if (ath <= 1.0) {
+            sin_omc_taylor(th, sn, omc);
+            cs = 1.0 - omc;
+        } else {
+            sincos(th, &sn, &cs);
+            omc = 1.0 - cs;
+        }
+        const double ux = wx * iw, uy = wy * iw, uz = wz * iw;
+        const double us = ux * sx + uy * sy + uz * sz;
+        nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
+        ny = sy * cs + (uz * sx - ux * sz) * sn + uy * us * omc;
+        nz = sz * cs + (ux * sy - uy * sx) * sn + uz * us * omc;
+    };
+    // The midpoint equation y = G(y) is solved by Newton's method on
+    // G(y) - y with a forward-difference Jacobian: the four lanes of each
+    // quad evaluate G at y and at y + h e_x, y + h e_y, y + h e_z at once
+    // (the spin's 16 lanes are otherwise idle here), exchange the results by
+    // quad broadcasts and take the same step. The iteration stops, as the
+    // plain fixed-point one, when |G(y) - y| <= tol, and returns G(y): a
+    // rotation of the spin, so its length is kept. The Jacobian's relative
+    // error (about 1e-8 from the step h = 2^-26) only slows the final
+    // convergence to linear with that ratio.
+    const int sub = lane & 3;
+    constexpr double FD_H = 0x1p-26, FD_IH = 0x1p26;
+    double yx = sx, yy = sy, yz = sz;
+    for (int turn = 0; turn < turns; turn++) {
+        if (turn) {
+            sx = yx;
+            sy = yy;
+            sz = yz;
+        }
+        for (int it = 0; it < cap; it++) {
+            double nx, ny, nz;
+            rotate(yx + (sub == 1 ? FD_H : 0.0), yy + (sub == 2 ? FD_H : 0.0), yz + (sub == 3 ? FD_H : 0.0), nx, ny,
+                   nz);
+            const double g0x = quad_bcast<0>(nx), g0y = quad_bcast<0>(ny), g0z = quad_bcast<0>(nz);
+            const double rx = g0x - yx, ry = g0y - yy, rz = g0z - yz;
+            const double diff = fmax(fabs(rx), fmax(fabs(ry), fabs(rz)));
+            if (diff <= tol || it + 1 == cap) {
+                yx = g0x;
+                yy = g0y;
+                yz = g0z;
+                break;
+            }
+            // A = I - J, J columns (G(y + h e_c) - G(y)) / h
+            const double a00 = 1.0 - (quad_bcast<1>(nx) - g0x) * FD_IH, a10 = -(quad_bcast<1>(ny) - g0y) * FD_IH,
+                         a20 = -(quad_bcast<1>(nz) - g0z) * FD_IH;
+            const double a01 = -(quad_bcast<2>(nx) - g0x) * FD_IH, a11 = 1.0 - (quad_bcast<2>(ny) - g0y) * FD_IH,
+                         a21 = -(quad_bcast<2>(nz) - g0z) * FD_IH;
+            const double a02 = -(quad_bcast<3>(nx) - g0x) * FD_IH, a12 = -(quad_bcast<3>(ny) - g0y) * FD_IH,
+                         a22 = 1.0 - (quad_bcast<3>(nz) - g0z) * FD_IH;
+            // y += A^-1 r (Cramer's rule); a plain fixed-point step if A is not
+            // safely invertible (never for a contracting map)
+            const double c00 = a11 * a22 - a12 * a21, c01 = a12 * a20 - a10 * a22, c02 = a10 * a21 - a11 * a20;
+            const double det = a00 * c00 + a01 * c01 + a02 * c02;
+            if (fabs(det) > 0.25) {
+                const double id = 1.0 / det;
+                yx += (c00 * rx + (a02 * a21 - a01 * a22) * ry + (a01 * a12 - a02 * a11) * rz) * id;
+                yy += (c01 * rx + (a00 * a22 - a02 * a20) * ry + (a02 * a10 - a00 * a12) * rz) * id;
+                yz += (c02 * rx + (a01 * a20 - a00 * a21) * ry + (a00 * a11 - a01 * a10) * rz) * id;
+            } else {
+                yx = g0x;
+                yy = g0y;
+                yz = g0z;
+            }
+        }
     }
     if (lane == 0) {
         d4 out = {yx, yy, yz, 0.0};
