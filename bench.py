@@ -37,10 +37,16 @@ from paper_2606_14073_amd import workload as W  # noqa: E402
 
 # MI355X published peaks
 PEAK = {"fp64": 78.6, "fp32": 157.3, "hbm_gbs": 8000.0}
-KERNEL_NAME = {"desc_radial": "k_desc_radial", "desc_angular": "k_desc_angular", "readout": "k_mlp",
-               "bwd_radial": "k_bwd_radial", "bwd_angular": "k_bwd_angular", "gather": "k_gather",
-               "couplings": "k_mag_coef/k_assemble_angular", "pairs": "k_assemble_pairs", "sweep": "k_sweep",
-               "nlist": "k_build/k_rev", "integrate": "k_kick/..."}
+KERNEL_NAME = {"desc_radial": "k_desc_radial<{r}>", "desc_angular": "k_desc_angular<{r}>",
+               "readout": "k_mlp<{r},104>", "bwd_radial": "k_bwd_radial<{r}>",
+               "bwd_angular": "k_bwd_angular<{r},true>", "bwd_angular_1": "k_bwd_angular<{r},false>",
+               "gather": "k_gather<{r}>", "couplings": "k_assemble_angular<{r}>", "pairs": "k_assemble_pairs<{r}>",
+               "sweep": "k_sweep<{r}>", "nlist": "k_build_cells", "integrate": "k_kick"}
+
+
+def kernel_name(group, real="double"):
+    """the largest kernel of a profile group, named as in the kernel trace"""
+    return KERNEL_NAME.get(group, group).replace("{r}", real)
 
 
 def pair_counts(s):
@@ -86,11 +92,13 @@ def flops_per_step(group, pc, k_corr=1):
         spin = pc["A_fe"] * 587 + pc["A_fefe"] * 469 + Nfe * 672
         reuse = pc["A_fefe"] * (75 + 50 + 133 + 336) + Nfe * 336
         return full + spin + k_corr * reuse
-    if group == "bwd_angular":
+    if group in ("bwd_angular", "bwd_angular_1"):
         # per pair: geometry/basis+derivative 110, g^A and dg^A 252, harmonics and
         # gradients 150, per lm contraction 44 x 24; spin pairs: g^sa, dg^sa 252 and
-        # 28 x 24; per atom QA, QS 1008
-        return pc["A"] * 1568 + pc["A_fefe"] * 924 + N * 1008
+        # 28 x 24; per atom QA, QS 1008. Species 0 (spin carriers), then species 1.
+        if group == "bwd_angular":
+            return pc["A_fe"] * 1568 + pc["A_fefe"] * 924 + Nfe * 1008
+        return (pc["A"] - pc["A_fe"]) * 1568 + (N - Nfe) * 1008
     if group == "bwd_radial":
         # per pair: geometry/basis+derivative 115, radial dg 18, record 20; Fe-Fe: 8 more
         # channel values 144 + force/field terms 90; Fe-Ge: 36 + 30; per atom contractions
@@ -387,7 +395,7 @@ def main():
         groups[g] = {"avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_step": int(fs),
                      "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4),
                      "launches_per_step": per_step}
-    kname = f"{KERNEL_NAME.get(dom, dom)}<double>"
+    kname = kernel_name(dom)
     fs_dom = flops_per_step(dom, pc, kw["K_corr"])
     ms_dom, nl_dom = prof.get(dom, (0.0, 0))
     fl = None if fs_dom is None or not nl_dom else fs_dom * K / nl_dom     # mean FLOPs per launch
@@ -432,12 +440,12 @@ def main():
             nk = nl32 * (2 * ncol - 1)
             by = sweep_bytes_per_launch(pc, ncol, real_bytes=4)
             ach = by / (ms32 / nk * 1e-3) / 1e9
-            f32["roofline"] = {"kernel": f"{KERNEL_NAME['sweep']}<float>", "bound": "hbm", "achieved": round(ach, 1),
+            f32["roofline"] = {"kernel": kernel_name("sweep", "float"), "bound": "hbm", "achieved": round(ach, 1),
                                "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4),
                                "avg_launch_ms": round(ms32 / nk, 5), "launches": nk}
         elif fs32 is not None and nl32:
             ach = fs32 * n_prof / (ms32 * 1e-3) / 1e12
-            f32["roofline"] = {"kernel": f"{KERNEL_NAME.get(dom32, dom32)}<float>",
+            f32["roofline"] = {"kernel": kernel_name(dom32, "float"),
                                "bound": "mfma" if dom32 == "readout" else "alu", "achieved": round(ach, 3),
                                "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": round(ach / PEAK["fp32"], 4),
                                "avg_launch_ms": round(ms32 / nl32, 4), "launches": nl32,

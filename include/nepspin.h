@@ -275,12 +275,14 @@ int sl_destroy(sl_sim *s);
  * launch of that group inside sl_integrate_steps is bracketed by HIP events
  * on the simulation's stream; totals accumulate until read. Groups:
  *   0 descriptor (radial set)   1 descriptor (angular set)   2 read-out
- *   3 backward (radial set)     4 backward (angular set)     5 gather
- *   6 spin-coupling coefficients and spin-angular parts      7 colour sweep
- *   8 neighbour lists           9 lattice half-steps, baths and reductions
+ *   3 backward (radial set)     4 backward (angular set), species 0
+ *   5 gather                    6 spin-coupling coefficients and spin-angular parts
+ *   7 colour sweep              8 neighbour lists
+ *   9 lattice half-steps, baths and reductions
  *  10 spin-pair coupling assembly
+ *  11 backward (angular set), species 1
  * mask: bit g enables group g (0 disables timing). */
-#define SL_NPROF 11
+#define SL_NPROF 12
 int sl_profile_enable(sl_sim *s, unsigned mask);
 
 /* ms_total[SL_NPROF]: summed event time per group (ms); launches[SL_NPROF]:

@@ -690,7 +690,8 @@ struct Engine {
     void backward(const ModelDev<real> &m, const Work<real> &w) {
         const Sys S = sys();
         { ProfScope p(this, 3); launch_bwd_radial(S, m, w, st); }
-        { ProfScope p(this, 4); launch_bwd_angular(S, m, w, st); }
+        { ProfScope p(this, 4); launch_bwd_angular(S, m, w, 0, st); }
+        { ProfScope p(this, 11); launch_bwd_angular(S, m, w, 1, st); }
         { ProfScope p(this, 5); launch_gather(S, w, st); }
     }
 

@@ -80,7 +80,8 @@ void launch_mlp(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int 
 template <typename real>
 void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
 template <typename real>
-void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st);
+void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int species,
+                        hipStream_t st);   // one launch: species 0 (spin carriers) or 1
 template <typename real>
 void launch_gather(const Sys &S, const Work<real> &W, hipStream_t st);
 template <typename real>

@@ -1438,10 +1438,10 @@ void launch_bwd_radial(const Sys &S, const ModelDev<real> &M, const Work<real> &
 }
 
 template <typename real>
-void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, hipStream_t st) {
+void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> &W, int species, hipStream_t st) {
     if (S.N == 0) return;
     NEP_SPLIT(ANG_ATOMS)
-    if (nb_fe) {
+    if (species == 0 && nb_fe) {
         if (S.mag)
             hipLaunchKernelGGL((k_bwd_angular<real, true>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, 0,
                                S.N_fe);
@@ -1449,7 +1449,7 @@ void launch_bwd_angular(const Sys &S, const ModelDev<real> &M, const Work<real> 
             hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_fe), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, 0,
                                S.N_fe);
     }
-    if (nb_ge)
+    if (species == 1 && nb_ge)
         hipLaunchKernelGGL((k_bwd_angular<real, false>), dim3(nb_ge), dim3(8 * ANG_ATOMS), 0, st, S, M.cR, W, S.N_fe,
                            S.N);
 }
@@ -1480,7 +1480,7 @@ void launch_assemble_pairs(const Sys &S, const ModelDev<real> &M, const Work<rea
                                             int, hipStream_t);                                                   \
     template void launch_mlp<real>(const Sys &, const ModelDev<real> &, const Work<real> &, int, hipStream_t);   \
     template void launch_bwd_radial<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t); \
-    template void launch_bwd_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
+    template void launch_bwd_angular<real>(const Sys &, const ModelDev<real> &, const Work<real> &, int, hipStream_t);\
     template void launch_gather<real>(const Sys &, const Work<real> &, hipStream_t);                             \
     template void launch_assemble_coef<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);\
     template void launch_assemble_pairs<real>(const Sys &, const ModelDev<real> &, const Work<real> &, hipStream_t);

@@ -27,7 +27,7 @@ EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_e
            "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour", "sl_replica_bytes"]
 
 PROFILE_GROUPS = ["desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "gather", "couplings",
-                  "sweep", "nlist", "integrate", "pairs"]
+                  "sweep", "nlist", "integrate", "pairs", "bwd_angular_1"]
 
 
 def replica_bytes(n_atoms, precision="fp64"):
