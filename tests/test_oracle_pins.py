@@ -401,6 +401,23 @@ def test_larmor_precession(oracle):
     np.testing.assert_allclose(s_out[0], [math.cos(ang), math.sin(ang), 0.0], atol=1e-13)
 
 
+def test_larmor_precession_large_angles(oracle):
+    """zero model in a 30,000 T field: each half-step turns the spin by
+    mu_B B (dt/2)/hbar = 1.32 rad, beyond the small-angle series of the
+    rotation; after n steps the angle is n mu_B B dt/hbar exactly"""
+    p = np.zeros(15438)
+    pos = np.array([[10.0, 10, 10]])
+    spin = np.array([[1.0, 0, 0]])
+    box = np.array([100.0] * 3)
+    n, B = 7, 3.0e4
+    sp = oracle.step_params(dt=1.0, B0=(0, 0, B), mu_s=1.0)
+    _, _, s_out, _, _ = oracle.run([0], pos, np.zeros((1, 3)), spin, box, np.zeros(3, np.int32), p,
+                                   [0], sp, n)
+    ang = MUB * B * n * 1.0 / HBAR
+    assert MUB * B * 0.5 / HBAR > 1.3
+    np.testing.assert_allclose(s_out[0], [math.cos(ang), math.sin(ang), 0.0], atol=1e-13)
+
+
 def test_spin_norm_preserved(oracle):
     s = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
     p = W.random_params()
