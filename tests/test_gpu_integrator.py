@@ -58,6 +58,11 @@ SCHEDULES = {
     "selfconsistent": dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, sc_tol=1e-13, sc_max=40),
     "accelerated": dict(dt=2.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, sc_tol=1e-13, sc_max=40,
                         sc_depth=3),
+    # one midpoint iteration: both sides take the explicit rotation G(s)
+    "explicit_rotation": dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, 1.0), mid_cap=1),
+    # a 30,000 T field: rotation angles near 2.6 rad per half step, past the
+    # Taylor range of the rotation
+    "large_angles": dict(dt=2.0, T0=100.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, 3.0e4)),
 }
 
 
