@@ -36,6 +36,10 @@ __device__ inline int atom_of_block(const Sys &S, int per_block, int nbFe, int l
     return i < S.N ? i : -1;
 }
 
+// i, or -1 when its replica is not advancing (paused for a new colouring,
+// finished, or its step void): the force-field kernels leave such atoms alone
+__device__ inline int live(const Sys &S, int i) { return i >= 0 && S.rep[S.rid[i]].active ? i : -1; }
+
 template <typename real>
 __device__ inline void load_spin(const d4 *sp, int j, real s[3]) {
     const d4 v = sp[j];
@@ -104,7 +108,7 @@ template <typename real>
 __global__ void __launch_bounds__(256) k_desc_radial(Sys S, const real *__restrict__ C, Work<real> W,
                                                      const d4 *spin, int nbFe) {
     bool fe;
-    const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
+    const int i = live(S, atom_of_block(S, 256, nbFe, threadIdx.x, fe));
     if (i < 0) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
@@ -301,7 +305,7 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
     __shared__ int smax[2];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     bool fe;
-    const int i = atom_of_block(S, ANG_ATOMS, nbFe, slot, fe);
+    const int i = live(S, atom_of_block(S, ANG_ATOMS, nbFe, slot, fe));
     const bool reuse = mode == PASS_SPIN_REUSE;
     if (threadIdx.x == 0) smax[0] = smax[1] = 0;
     __syncthreads();
@@ -549,7 +553,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
     __syncthreads();
     const int i16 = lane & 15, kq = lane >> 4;
     const int arow = a0 + i16;
-    const bool rv = arow < end;
+    const bool rv = arow < end && live(S, arow) >= 0;
     const real *qrow = W.q + (size_t)(rv ? arow : 0) * DP;
     if constexpr (f64) {
         // Transposed form: Z^T = W0 Q^T + b0 (hidden x atoms). With the FP64
@@ -684,7 +688,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int row = a0 + MF<real>::row(kq, r);
-            if (row < end) W.Ei[row] = M.b1[t] + e[r];
+            if (row < end && live(S, row) >= 0) W.Ei[row] = M.b1[t] + e[r];
         }
     }
     __syncthreads();
@@ -703,7 +707,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int row = a0 + MF<real>::row(kq, r);
-            if (row < end && col < KD) W.Fp[(size_t)row * DP + col] = f[jt][r];
+            if (row < end && col < KD && live(S, row) >= 0) W.Fp[(size_t)row * DP + col] = f[jt][r];
         }
     }
 }
@@ -747,7 +751,7 @@ __device__ inline void mag_coef(const real *__restrict__ C, const real *Fp, real
 template <typename real>
 __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N) return;
+    if (i >= S.N || live(S, i) < 0) return;
     const bool fe = i < S.N_fe;
     const int t = fe ? 0 : 1;
     const real *Fp = W.Fp + (size_t)i * DP;
@@ -775,7 +779,7 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
 template <typename real>
 __global__ void __launch_bounds__(256) k_mag_coef(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N_fe) return;
+    if (i >= S.N_fe || live(S, i) < 0) return;
     mag_coef(C, W.Fp + (size_t)i * DP, W.mcoef + (size_t)i * MCOEF);
 }
 
@@ -808,7 +812,7 @@ __device__ inline void partner_radial(const real *cR, const real *cS, bool fe_j,
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
     bool fe;
-    const int i = atom_of_block(S, 256, nbFe, threadIdx.x, fe);
+    const int i = live(S, atom_of_block(S, 256, nbFe, threadIdx.x, fe));
     if (i < 0) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
@@ -906,7 +910,7 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_mag(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N_fe) return;
+    if (i >= S.N_fe || live(S, i) < 0) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc;
@@ -1000,7 +1004,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
     const bool fe = first < S.N_fe;    // species 0: the pair types tau = 0, 1
     int i = first + blockIdx.x * ANG_ATOMS + slot;
-    if (i >= last) i = -1;
+    i = live(S, i < last ? i : -1);
     real *Q = sQ + slot * QSTRIDE;   // QA[n][m], then QS[n][m] on spin carriers
     if (i >= 0) {
         const real *Fp = W.Fp + (size_t)i * DP;
@@ -1164,7 +1168,7 @@ __global__ void __launch_bounds__(64) k_bwd_angular(Sys S, const real *__restric
 template <typename real>
 __global__ void __launch_bounds__(256) k_gather(Sys S, Work<real> W) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= S.N) return;
+    if (k >= S.N || live(S, k) < 0) return;   // a paused replica keeps its last forces and fields
     const size_t ld = S.N;
     const bool fe = S.mag && k < S.N_fe;   // spin carrier
     real F[3], h[3];
@@ -1241,10 +1245,11 @@ template <typename real>
 __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__restrict__ C, Work<real> W) {
     __shared__ real sP[ANG_ATOMS * PSTRIDE];
     const int lane = threadIdx.x & 7, slot = threadIdx.x >> 3;
-    const int i = blockIdx.x * ANG_ATOMS + slot;
+    const int i0 = blockIdx.x * ANG_ATOMS + slot;
+    const int i = live(S, i0 < S.N_fe ? i0 : -1);
     const real *cS = C + P_CSA;   // tau = (Fe, Fe)
     real *P = sP + slot * PSTRIDE;
-    if (i < S.N_fe) {
+    if (i >= 0) {
         const real *Fp = W.Fp + (size_t)i * DP;
         for (int x = lane; x < NA * NLM; x += 8) {
             const int n = x / NLM, m = x - n * NLM;
@@ -1252,7 +1257,7 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
         }
     }
     __syncthreads();
-    if (i >= S.N_fe) return;
+    if (i < 0) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_A, rc2 = rc * rc;
@@ -1296,7 +1301,7 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
 template <typename real>
 __global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__restrict__ C, Work<real> W) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S.N_fe) return;
+    if (i >= S.N_fe || live(S, i) < 0) return;
     const Img R = img_of(S.rep[S.rid[i]]);
     const d4 pi = S.pos[i];
     const real rc = (real)RC_R, rc2 = rc * rc, rca = (real)RC_A, rca2 = rca * rca;   // as the angular pass
