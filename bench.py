@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the spin-lattice NEP step on one MI355X.
 
-Headline workload: B20 FeGe-like crystal, 32x32x32 cells = 262,144 atoms
-(131,072 spins), periodic, seeded random model, 300 K Langevin lattice bath
-and stochastic-LLG spin bath (damping 0.1), dt = 1 fs, FP64 end to end. One
-step = the whole B A O S A B step (three descriptor passes and read-outs,
-two spin-coupling assemblies, four colour sweeps, one backward pass,
+Headline workload: B20 FeGe-like crystal, 96x96x96 cells = 7,077,888 atoms
+(3,538,944 spins), periodic, seeded random model plus the short-range
+repulsion, 300 K Langevin lattice bath and stochastic-LLG spin bath (damping
+0.1), dt = 1 fs, FP64 end to end, with the FP32-mixed path on the same
+workload beside it (rate, and E/F/H errors against FP64). One step = the
+whole B A O S A B step (three descriptor passes and read-outs, two
+spin-coupling assemblies, four colour sweeps, one backward pass,
 neighbour-list upkeep, half-steps and baths) for every atom. Inputs are
 resident on the device before the timed region; the clock brackets
 sl_integrate_steps, which returns after the device has finished.
 
-Also reported: the FP32-mixed variant of the same workload, a bounded sample
-of the replica-serving workload (p50/p99 step latency), the roofline of the
-dominant kernel (HIP-event time over the timed region against an algorithmic
-FLOP count) and the CPU oracle on the host cores.
+Also reported: the 262,144-atom workload (FP64 and FP32-mixed), the
+self-consistent midpoint, the 4,194,304-atom slab, the structural-only NEP on
+synthetic water, a bounded sample of the replica-serving workload (p50/p99
+step latency), the roofline of the dominant kernel (HIP-event time over the
+timed region against an algorithmic FLOP or byte count) and the CPU oracle on
+the host cores.
 
 Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
 """
@@ -142,26 +146,6 @@ def sim_rate(model, nepspin, s, v, ip, precision, n_steps, warmup=2):
     t1 = time.perf_counter()
     sim.close()
     return s.n * n_steps / (t1 - t0)
-
-
-def run_precision_form(model, nepspin, n_steps):
-    """96^3 cells = 7,077,888 atoms at 300 K: FP64, FP32-mixed and the BF16
-    variant side by side, with the errors of E, F, H against FP64."""
-    s = W.config_precision()
-    v = W.maxwell_boltzmann(s.types, 300.0)
-    ip = nepspin.integrator_params(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, seed=W.SEED_PHILOX)
-    out = {"workload": "FeGe B20 96x96x96 cells, 7,077,888 atoms, periodic, 300 K, K_corr 1", "steps": n_steps}
-    for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed"), ("bf16h", "bf16_hidden")):
-        out[key] = sim_rate(model, nepspin, s, v, ip, prec, n_steps)
-    ref = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, want=("E", "F", "H"))
-    errs = {}
-    for prec, key in (("fp32", "fp32_mixed"), ("bf16h", "bf16_hidden")):
-        got = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, precision=prec, want=("E", "F", "H"))
-        errs[key] = {"dE_per_atom_eV": abs(got["E"] - ref["E"]) / s.n,
-                     "F_rel_l2": float(np.linalg.norm(got["F"] - ref["F"]) / np.linalg.norm(ref["F"])),
-                     "H_rel_l2": float(np.linalg.norm(got["H"] - ref["H"]) / np.linalg.norm(ref["H"]))}
-    out["errors_vs_fp64"] = errs
-    return out
 
 
 def run_slab(model, nepspin, n_steps):
@@ -310,25 +294,124 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pair_counts_scaled(s, cells=16):
+    """pair counts of a crystal too large for a k-d tree pass: those of a
+    cells^3 crystal from the same generator, scaled by the atom count (the
+    counts per atom of the periodic lattice do not depend on its size)"""
+    small = pair_counts(W.fege_lattice(cells, cells, cells))
+    f = s.n / small["N"]
+    out = {k: int(round(v * f)) for k, v in small.items()}
+    out["N"], out["N_fe"] = s.n, int((s.types == 0).sum())
+    return out
+
+
+def roofline_of(group, prof, pc, n_steps, k_corr, s, real="double"):
+    """roofline of one kernel group from its HIP-event time over n_steps: the
+    colour sweep against HBM (algorithmic bytes), the others against the FP64
+    vector (or MFMA) peak with the work model of flops_per_step"""
+    ms, nl = prof.get(group, (0.0, 0))
+    rb = 8 if real == "double" else 4
+    kname = kernel_name(group, real)
+    if not nl:
+        return {"kernel": kname, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "note": "no timed launches"}
+    if group == "sweep":
+        # one timed sweep = 2 x n_colours - 1 launches of k_sweep (ascending, then
+        # descending; the turning colour's two visits share one launch)
+        ncol = int(s.colour.max()) + 1
+        nk = nl * (2 * ncol - 1)
+        avg = ms / nk
+        by = sweep_bytes_per_launch(pc, ncol, real_bytes=rb)
+        ach = by / (avg * 1e-3) / 1e9
+        return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
+                "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": traffic_from_profile(kname),
+                "avg_launch_ms": round(avg, 5), "launches": nk, "bytes_per_launch": int(by)}
+    fs = flops_per_step(group, pc, k_corr)
+    if fs is None:
+        return {"kernel": kname, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "note": "group has no work model"}
+    fl = fs * n_steps / nl            # mean FLOPs per launch
+    avg = ms / nl
+    ach = fl / (avg * 1e-3) / 1e12
+    peak = PEAK["fp64"] if real == "double" else PEAK["fp32"]
+    out = {"kernel": kname, "bound": "mfma" if group == "readout" else "alu", "achieved": round(ach, 3),
+           "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic_from_profile(kname),
+           "avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_launch": int(fl)}
+    if real != "double":
+        out["note"] = ("peak is the packed-FP32 vector rate; the kernels are built without packed FP32, whose "
+                       "plain vector rate is 78.6 TFLOP/s")
+    return out
+
+
+def cpu_baseline(params, s1, s2, v2):
+    """The oracle on the host cores: the 512-atom workload's 100 NVE steps in
+    full on every thread OpenMP gets, 10 of them on one thread, and one step of
+    the 262,144-atom workload (atom-steps/s of each)"""
+    import subprocess
+    from oracle import oracle as O
+    O.build(force=False)
+    zbl = W.SHORT_RANGE_FEGE
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    sp1 = O.step_params(dt=1.0, B0=(0, 0, 1.0), K_corr=1, zbl=zbl)
+    t0 = time.perf_counter()
+    O.run(s1.types, s1.pos, np.zeros((s1.n, 3)), s1.spin, s1.box, s1.pbc, params, s1.colour, sp1, 100)
+    dt1 = time.perf_counter() - t0
+    full = s1.n * 100 / dt1
+    # one thread: a child process, since OpenMP fixes its team size at start-up
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "from paper_2606_14073_amd import workload as W; s = W.config_small(); p = W.random_params(); "
+            "sp = O.step_params(dt=1.0, B0=(0, 0, 1.0), K_corr=1, zbl=W.SHORT_RANGE_FEGE); t0 = time.perf_counter(); "
+            "O.run(s.types, s.pos, np.zeros((s.n, 3)), s.spin, s.box, s.pbc, p, s.colour, sp, 10); "
+            "print(s.n * 10 / (time.perf_counter() - t0))" % ROOT)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        one = float(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                   timeout=300, check=True).stdout.split()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        one = None
+    sp2 = O.step_params(dt=1.0, T0=300.0, alpha=0.1, gammaL=0.01, ensemble=1, K_corr=1, seed=W.SEED_PHILOX,
+                        zbl=zbl)
+    t0 = time.perf_counter()
+    O.run(s2.types, s2.pos, v2, s2.spin, s2.box, s2.pbc, params, s2.colour, sp2, 1)
+    t2 = time.perf_counter() - t0
+    return {"value": full, "unit": "atom-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"the 512-atom workload (4x4x4 cells), its 100 NVE steps in full, {dt1:.1f} s on "
+                      f"{cores} OpenMP threads; host CPU: {host_cpu_model()}",
+            "one_thread": one, "one_thread_sample": "10 steps of the same 512-atom workload on 1 thread",
+            "config_262144_one_step": s2.n / t2,
+            "config_262144_sample": f"1 step of the 262,144-atom workload at 300 K, {t2:.1f} s on {cores} threads "
+                                    "(a 10-step sample does not fit the benchmark's time)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sc", action="store_true", help="skip the self-consistent midpoint leg")
     ap.add_argument("--no-water", action="store_true", help="skip the structural-only NEP leg")
+    ap.add_argument("--no-262k", action="store_true", help="skip the 262,144-atom legs")
+    ap.add_argument("--no-slab", action="store_true", help="skip the 4.2M-atom slab leg")
     ap.add_argument("--water-steps", type=int, default=30)
     ap.add_argument("--water-only", action="store_true",
                     help="run only the structural-only NEP leg and print its result as one JSON line")
     ap.add_argument("--sc-steps", type=int, default=20)
-    ap.add_argument("--no-large", action="store_true", help="skip the 7.1M-atom precision form and the 4.2M slab")
-    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--side-steps", type=int, default=50, help="timed steps of the 262,144-atom and slab legs")
     ap.add_argument("--serving-requests", type=int, default=24)
     ap.add_argument("--serving-steps", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -344,18 +427,16 @@ def main():
         print(json.dumps(run_structural(nepspin, args.water_steps)), flush=True)
         return
 
-    s = W.config_fp64_bench()
     params = W.random_params()
-    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    model = nepspin.Model(params, short_range=W.SHORT_RANGE_FEGE)
     kw = dict(dt=1.0, T0=300.0, alpha_s=0.1, gamma_L=0.01, ensemble=1, K_corr=1, seed=W.SEED_PHILOX)
-    model = nepspin.Model(params)
     K, Wm = args.steps, args.warmup
 
-    def run(precision, n_steps, prof_groups=()):
-        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v0, colour=s.colour,
+    def run(s, v, precision, n_steps, prof_groups=(), warm=Wm):
+        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour,
                           params=nepspin.integrator_params(**kw), precision=precision)
-        if Wm:
-            sim.integrate(Wm, observables=False)
+        if warm:
+            sim.integrate(warm, observables=False)
         sim.profile(prof_groups)
         sim.profile_read()
         t0 = time.perf_counter()
@@ -366,98 +447,92 @@ def main():
         sim.close()
         return t1 - t0, prof
 
-    # Untimed profiling pass: every kernel group bracketed by HIP events on the
-    # library's stream, for the per-step breakdown and the dominant kernel.
-    n_prof = max(10, min(K, 50))
-    _, prof_all = run("fp64", n_prof, tuple(nepspin.PROFILE_GROUPS))
-    tot = sum(v[0] for v in prof_all.values())
-    print(f"fp64 profiling pass, {n_prof} steps:", file=sys.stderr)
-    for g, (m_, n_) in prof_all.items():
-        print(f"  {g:13s} {m_ / n_prof:8.3f} ms/step  {100 * m_ / tot:5.1f}%  launches/step {n_ / n_prof:.1f}",
-              file=sys.stderr)
-    dom = max(prof_all, key=lambda g: prof_all[g][0])
+    def breakdown(prof, n):
+        tot = sum(v[0] for v in prof.values()) or 1.0
+        return {g: {"ms_per_step": round(m_ / n, 4), "share": round(m_ / tot, 4), "launches_per_step": n_ / n}
+                for g, (m_, n_) in prof.items()}
 
-    # Timed FP64 headline; HIP events bracket only the dominant group's launches.
-    dt64, prof = run("fp64", K, (dom,))
-    rate64 = s.n * K / dt64
+    # Headline: the largest single-GPU workload, 96^3 cells = 7,077,888 atoms,
+    # FP64, 300 K Langevin + stochastic LLG, K_corr 1. An untimed profiling
+    # pass with HIP events around every kernel group gives the breakdown and
+    # the dominant group; the timed run brackets only that group's launches.
+    s3 = W.config_precision()
+    v3 = W.maxwell_boltzmann(s3.types, 300.0)
+    pc3 = pair_counts_scaled(s3)
+    n_prof = max(5, min(K, 10))
+    _, prof_all = run(s3, v3, "fp64", n_prof, tuple(nepspin.PROFILE_GROUPS), warm=2)
+    dom = max(prof_all, key=lambda g: prof_all[g][0])
+    print(f"fp64 profiling pass, 7,077,888 atoms, {n_prof} steps:", file=sys.stderr)
+    for g, b in breakdown(prof_all, n_prof).items():
+        print(f"  {g:13s} {b['ms_per_step']:8.3f} ms/step  {100 * b['share']:5.1f}%  launches/step "
+              f"{b['launches_per_step']:.1f}", file=sys.stderr)
+    dt64, prof = run(s3, v3, "fp64", K, (dom,))
+    rate64 = s3.n * K / dt64
     print(f"fp64: {K} steps in {dt64:.3f} s -> {rate64:.4e} atom-steps/s (dominant: {dom})",
           file=sys.stderr, flush=True)
-
-    pc = pair_counts(s)
+    roofline = roofline_of(dom, prof, pc3, K, kw["K_corr"], s3)
     groups = {}
     for g, (ms, nl) in prof_all.items():
-        fs = flops_per_step(g, pc, kw["K_corr"])
+        fs = flops_per_step(g, pc3, kw["K_corr"])
         if fs is None or nl == 0:
             continue
-        per_step = nl / n_prof
-        avg = ms / nl
         ach = fs * n_prof / (ms * 1e-3) / 1e12
-        groups[g] = {"avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_step": int(fs),
-                     "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4),
-                     "launches_per_step": per_step}
-    kname = kernel_name(dom)
-    fs_dom = flops_per_step(dom, pc, kw["K_corr"])
-    ms_dom, nl_dom = prof.get(dom, (0.0, 0))
-    fl = None if fs_dom is None or not nl_dom else fs_dom * K / nl_dom     # mean FLOPs per launch
-    if dom == "sweep" and nl_dom:
-        # one profiled sweep = 2 x n_colours - 1 launches of k_sweep (ascending, then
-        # descending; the last colour's two visits share one launch)
-        ncol = int(s.colour.max()) + 1
-        nk = nl_dom * (2 * ncol - 1)
-        avg = ms_dom / nk
-        by = sweep_bytes_per_launch(pc, ncol)
-        ach = by / (avg * 1e-3) / 1e9
-        roofline = {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
-                    "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": traffic_from_profile(kname),
-                    "avg_launch_ms": round(avg, 5), "launches": nk, "bytes_per_launch": int(by)}
-    elif fl is not None and nl_dom:
-        avg = ms_dom / nl_dom
-        ach = fl / (avg * 1e-3) / 1e12
-        roofline = {"kernel": kname, "bound": "mfma" if dom == "readout" else "alu",
-                    "achieved": round(ach, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
-                    "frac": round(ach / PEAK["fp64"], 4), "traffic": traffic_from_profile(kname),
-                    "avg_launch_ms": round(avg, 4), "launches": nl_dom, "flop_per_launch": int(fl)}
-    else:
-        roofline = {"kernel": kname, "bound": None, "achieved": None, "peak": None, "unit": None,
-                    "frac": None, "traffic": None, "note": "dominant group has no work model"}
-
-    extra = {"breakdown_ms_per_step": {g: round(m_ / n_prof, 4) for g, (m_, n_) in prof_all.items()},
+        groups[g] = {"avg_launch_ms": round(ms / nl, 4), "launches": nl, "flop_per_step": int(fs),
+                     "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4)}
+    extra = {"breakdown_ms_per_step": {g: b["ms_per_step"] for g, b in breakdown(prof_all, n_prof).items()},
              "kernel_rooflines": groups}
 
     if not args.no_fp32:
-        # same workload in FP32-mixed: an untimed profiling pass for its breakdown
-        # and roofline, then the timed run
-        _, p32 = run("fp32", n_prof, tuple(nepspin.PROFILE_GROUPS))
+        _, p32 = run(s3, v3, "fp32", n_prof, tuple(nepspin.PROFILE_GROUPS), warm=2)
         dom32 = max(p32, key=lambda g: p32[g][0])
-        dt32, _ = run("fp32", K)
-        f32 = {"value": s.n * K / dt32, "ms_per_step": 1e3 * dt32 / K, "speedup_vs_fp64": dt64 / dt32,
-               "breakdown_ms_per_step": {g: round(m_ / n_prof, 4) for g, (m_, n_) in p32.items()},
-               "dominant": dom32}
-        fs32 = flops_per_step(dom32, pc, kw["K_corr"])
-        ms32, nl32 = p32[dom32]
-        if dom32 == "sweep" and nl32:
-            ncol = int(s.colour.max()) + 1
-            nk = nl32 * (2 * ncol - 1)
-            by = sweep_bytes_per_launch(pc, ncol, real_bytes=4)
-            ach = by / (ms32 / nk * 1e-3) / 1e9
-            f32["roofline"] = {"kernel": kernel_name("sweep", "float"), "bound": "hbm", "achieved": round(ach, 1),
-                               "peak": PEAK["hbm_gbs"], "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4),
-                               "avg_launch_ms": round(ms32 / nk, 5), "launches": nk}
-        elif fs32 is not None and nl32:
-            ach = fs32 * n_prof / (ms32 * 1e-3) / 1e12
-            f32["roofline"] = {"kernel": kernel_name(dom32, "float"),
-                               "bound": "mfma" if dom32 == "readout" else "alu", "achieved": round(ach, 3),
-                               "peak": PEAK["fp32"], "unit": "TFLOP/s", "frac": round(ach / PEAK["fp32"], 4),
-                               "avg_launch_ms": round(ms32 / nl32, 4), "launches": nl32,
-                               "note": "peak is the packed-FP32 vector rate; the kernels are built without "
-                                       "packed FP32, whose plain vector rate is 78.6 TFLOP/s"}
+        dt32, pr32 = run(s3, v3, "fp32", K, (dom32,))
+        f32 = {"value": s3.n * K / dt32, "unit": "atom-steps/s", "ms_per_step": 1e3 * dt32 / K,
+               "speedup_vs_fp64": dt64 / dt32,
+               "breakdown_ms_per_step": {g: b["ms_per_step"] for g, b in breakdown(p32, n_prof).items()},
+               "dominant": dom32, "roofline": roofline_of(dom32, pr32, pc3, K, kw["K_corr"], s3, "float")}
+        # errors of the FP32-mixed potential against FP64 on the same state
+        ref = model.eval(s3.types, s3.pos, s3.spin, s3.box, s3.pbc, B=(0, 0, 0.5), want=("E", "Ei", "F", "H"))
+        got = model.eval(s3.types, s3.pos, s3.spin, s3.box, s3.pbc, B=(0, 0, 0.5), precision="fp32",
+                         want=("E", "Ei", "F", "H"))
+        f32["errors_vs_fp64"] = {
+            "dE_per_atom_eV": abs(got["E"] - ref["E"]) / s3.n,
+            "max_dEi_eV": float(np.abs(got["Ei"] - ref["Ei"]).max()),
+            "F_rel_l2": float(np.linalg.norm(got["F"] - ref["F"]) / np.linalg.norm(ref["F"])),
+            "H_rel_l2": float(np.linalg.norm(got["H"] - ref["H"]) / np.linalg.norm(ref["H"])),
+            "bounds": "|dE|/N <= 1e-6 eV, F and H rel-l2 <= 1e-5"}
+        del ref, got
+        model.close()
+        model = nepspin.Model(params, short_range=W.SHORT_RANGE_FEGE)   # releases the 7M-atom eval arrays
         extra["fp32_mixed"] = f32
-        print(f"fp32-mixed: {K} steps in {dt32:.3f} s -> {s.n * K / dt32:.4e} atom-steps/s (dominant: {dom32})",
-              file=sys.stderr, flush=True)
+        print(f"fp32-mixed: {K} steps in {dt32:.3f} s -> {f32['value']:.4e} atom-steps/s (dominant: {dom32}); "
+              f"errors {f32['errors_vs_fp64']}", file=sys.stderr, flush=True)
 
-    if not args.no_sc:
-        extra["self_consistent"] = run_self_consistent(model, nepspin, s, v0, kw, args.sc_steps, 1e3 * dt64 / K)
-        print(f"self-consistent: {extra['self_consistent']}", file=sys.stderr, flush=True)
+    s2 = W.config_fp64_bench()
+    v2 = W.maxwell_boltzmann(s2.types, 300.0)
+    if not args.no_262k:
+        pc2 = pair_counts(s2)
+        n2 = args.side_steps
+        leg = {"workload": "FeGe B20 32x32x32 cells, 262,144 atoms (131,072 spins), periodic, 300 K Langevin + "
+                           "stochastic LLG (alpha 0.1), dt 1 fs, K_corr 1, short-range term", "steps": n2}
+        _, p2 = run(s2, v2, "fp64", n2, tuple(nepspin.PROFILE_GROUPS))
+        leg["breakdown_ms_per_step"] = {g: b["ms_per_step"] for g, b in breakdown(p2, n2).items()}
+        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
+            dtx, _ = run(s2, v2, prec, n2)
+            leg[key] = s2.n * n2 / dtx
+            leg[key + "_ms_per_step"] = round(1e3 * dtx / n2, 3)
+        dom2 = max(p2, key=lambda g: p2[g][0])
+        leg["dominant"] = dom2
+        leg["roofline"] = roofline_of(dom2, p2, pc2, n2, kw["K_corr"], s2)
+        extra["fege_262k"] = leg
+        print(f"262,144 atoms: {leg}", file=sys.stderr, flush=True)
+        if not args.no_sc:
+            extra["self_consistent"] = run_self_consistent(model, nepspin, s2, v2, kw, args.sc_steps,
+                                                           leg["fp64_ms_per_step"])
+            print(f"self-consistent: {extra['self_consistent']}", file=sys.stderr, flush=True)
+
+    if not args.no_slab:
+        extra["slab"] = run_slab(model, nepspin, args.side_steps)
+        print(f"slab: {extra['slab']}", file=sys.stderr, flush=True)
 
     if not args.no_water:
         extra["structural_water"] = run_structural(nepspin, args.water_steps)
@@ -466,33 +541,15 @@ def main():
     if not args.no_serving:
         extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)
         print(f"serving: {extra['serving']}", file=sys.stderr, flush=True)
-
-    if not args.no_large:
-        # a model of their own: its evaluation engine (up to 120 GB) is released afterwards
-        big = nepspin.Model(params)
-        extra["precision_form"] = run_precision_form(big, nepspin, args.large_steps)
-        print(f"precision form: {extra['precision_form']}", file=sys.stderr, flush=True)
-        extra["slab"] = run_slab(big, nepspin, args.large_steps)
-        print(f"slab: {extra['slab']}", file=sys.stderr, flush=True)
-        big.close()
+    model.close()
 
     cpu = None
     if not args.no_cpu:
-        from oracle import oracle as O
-        O.build(force=False)
-        sp = O.step_params(dt=1.0, T0=300.0, alpha=0.1, gammaL=0.01, ensemble=1, K_corr=1, seed=W.SEED_PHILOX)
-        t0 = time.perf_counter()
-        O.run(s.types, s.pos, v0, s.spin, s.box, s.pbc, params, s.colour, sp, args.cpu_steps)
-        t1 = time.perf_counter()
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": s.n * args.cpu_steps / (t1 - t0), "unit": "atom-steps/s", "cores": cores,
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} full step(s) of the same 262,144-atom workload from its initial state, "
-                         f"{t1 - t0:.1f} s with OpenMP over atoms"}
+        cpu = cpu_baseline(params, W.config_small(), s2, v2)
         print(f"cpu oracle: {cpu}", file=sys.stderr, flush=True)
 
     line = {
-        "metric": "atom-steps/s per MI355X (FP64 spin-lattice NEP step)",
+        "metric": "atom\u00b7steps/s per MI355X, FP64 vs FP32-mixed; p50/p99 replica step latency",
         "value": rate64,
         "unit": "atom-steps/s",
         "n_gpus": 1,
@@ -503,10 +560,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded B20 FeGe-like lattice and random NEP weights)",
-        "config": {"workload": "FeGe B20 32x32x32 cells, 262,144 atoms (131,072 spins), periodic, "
-                               "300 K Langevin + stochastic LLG (alpha 0.1), dt 1 fs, K_corr 1",
-                   "atoms": s.n, "precision": "fp64"},
+        "data": "synthetic (seeded B20 FeGe-like lattice, random NEP weights plus the short-range term)",
+        "config": {"workload": "FeGe B20 96x96x96 cells, 7,077,888 atoms (3,538,944 spins), periodic, 300 K "
+                               "Langevin + stochastic LLG (alpha 0.1), dt 1 fs, K_corr 1, FP64; FP32-mixed "
+                               "beside it",
+                   "atoms": s3.n, "precision": "fp64"},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -65,10 +65,11 @@ typedef enum {
  * and energy sums are FP64 in every mode. */
 typedef enum {
     SL_FP64 = 0,          /* everything FP64                                */
-    SL_FP32_MIXED = 1,    /* potential in FP32, accumulated in FP32          */
-    SL_FP32_BF16H = 2     /* as SL_FP32_MIXED, with the input->hidden
-                             contraction of the read-out in BF16 (FP32 sums) */
+    SL_FP32_MIXED = 1     /* potential in FP32, accumulated in FP32          */
 } sl_precision;
+/* Any other value is SL_E_INVALID. (A BF16 input->hidden contraction of the
+ * read-out was measured at 3.7e-4 eV/atom and 1e-3 relative force error,
+ * outside the FP32 bounds, and is not offered.) */
 
 const char *sl_last_error(void);
 
@@ -96,6 +97,21 @@ typedef struct {
                             w1[64], b1[1]. No spins: spin inputs are ignored,
                             fields are zero, a step is B A O A B, and
                             nep_spin_descriptors returns [n][37] arrays.       */
+    /* Optional short-range repulsion (Sec. 6 includes an optional short-range
+     * pair term in the modeled work of a step without giving its form; the
+     * form here is the universal screened-Coulomb potential of Ziegler,
+     * Biersack and Littmark):
+     *   E_i += 1/2 sum_j V(r_ij),  V(r) = K Z_i Z_j / r * phi(r/a) * S(r),
+     *   K = 14.399645 eV A, a = 0.8854 * 0.529177210903 A / (Z_i^0.23 + Z_j^0.23),
+     *   phi(x) = 0.18175 e^{-3.19980x} + 0.50986 e^{-0.94229x}
+     *          + 0.28022 e^{-0.40290x} + 0.02817 e^{-0.20162x},
+     *   S(r) = 1 below sr_r_inner, (1 + cos(pi (r - sr_r_inner)/(sr_r_outer - sr_r_inner)))/2
+     *          between, 0 from sr_r_outer on.
+     * sr_Z[t] is the nuclear charge of species t. sr_r_outer = 0 turns the
+     * term off; otherwise 0 < sr_r_inner < sr_r_outer <= rc_R and Z > 0 are
+     * required (SL_E_INVALID). It adds to E, E_i and F only.              */
+    double sr_Z[2];
+    double sr_r_inner, sr_r_outer;
 } nep_spin_hparams;
 
 /* params: 15,438 doubles in this order (tau = 2 t_i + t_j is the ordered

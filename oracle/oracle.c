@@ -72,6 +72,10 @@
 
 static const double MASS[2] = {55.845, 72.630};
 
+/* Coulomb constant e^2/(4 pi eps0) in eV A and the Bohr radius in A (CODATA) */
+#define KCOUL 14.399645
+#define ABOHR 0.529177210903
+
 /* ------------------------------------------------------------------------- */
 /* neighbour sets                                                            */
 /* ------------------------------------------------------------------------- */
@@ -278,6 +282,45 @@ static void cross3(const double *a, const double *b, double *c) {
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+
+/* ------------------------------------------------------------------------- */
+/* optional short-range repulsion                                            */
+/* ------------------------------------------------------------------------- */
+
+/* The universal screened-Coulomb (ZBL) repulsion of Ziegler, Biersack and
+ * Littmark (The Stopping and Range of Ions in Solids, 1985):
+ *   V(r) = KCOUL Z_i Z_j / r * phi(r/a),  a = 0.8854 a_Bohr / (Z_i^0.23 + Z_j^0.23),
+ *   phi(x) = 0.18175 e^{-3.19980x} + 0.50986 e^{-0.94229x}
+ *          + 0.28022 e^{-0.40290x} + 0.02817 e^{-0.20162x},
+ * switched off between r_inner and r_outer by
+ *   S(r) = 1 (r <= r_inner), (1 + cos(pi (r - r_inner)/(r_outer - r_inner)))/2, 0 (r >= r_outer).
+ * Returns V S and its derivative in r. Sec. 6 includes an optional
+ * short-range pair term in the modeled work of a step without giving its
+ * form; this is the one NEP models add for close approach. */
+static void zbl_pair(double r, double zi, double zj, double r1, double r2, double *V, double *dV) {
+    static const double c[4] = {0.18175, 0.50986, 0.28022, 0.02817};
+    static const double e[4] = {3.19980, 0.94229, 0.40290, 0.20162};
+    if (r >= r2) { *V = 0.0; *dV = 0.0; return; }
+    double a = 0.8854 * ABOHR / (pow(zi, 0.23) + pow(zj, 0.23));
+    double phi = 0.0, dphi = 0.0;
+    for (int k = 0; k < 4; k++) {
+        double t = c[k] * exp(-e[k] * r / a);
+        phi += t;
+        dphi -= e[k] / a * t;
+    }
+    double pre = KCOUL * zi * zj;
+    double v = pre * phi / r;
+    double dv = pre * (dphi / r - phi / (r * r));
+    double s = 1.0, ds = 0.0;
+    if (r > r1) {
+        double w = M_PI / (r2 - r1);
+        s = 0.5 * (1.0 + cos(w * (r - r1)));
+        ds = -0.5 * w * sin(w * (r - r1));
+    }
+    *V = v * s;
+    *dV = dv * s + v * ds;
+}
+
 /* ------------------------------------------------------------------------- */
 /* model context                                                             */
 /* ------------------------------------------------------------------------- */
@@ -292,6 +335,7 @@ typedef struct {
     const double *p;       /* parameters */
     double rcR, rcA;
     int act;               /* 0 tanh, 1 identity (linear read-out, tests only) */
+    const double *zbl;     /* short-range term {Z_0, Z_1, r_inner, r_outer}, or NULL */
     nlist_t nl;            /* neighbours within rcR */
     struct nb_s **env;     /* optional per-atom environments (spin step only) */
     int *env_m;
@@ -451,6 +495,15 @@ static void backward_atom(const ctx_t *C, int i, const double *Fp, double *G,
     memset(G, 0, sizeof(double) * 3 * nslot);
     memset(hnb, 0, sizeof(double) * 3 * nslot);
     for (int a = 0; a < 3; a++) hown[a] = 2.0 * Fp[D_OS] * si[a];
+    /* short-range repulsion: E_i holds V(r_ij)/2, dr_ij/dd_ij = rhat_ij */
+    if (C->zbl) {
+        for (int q = 0; q < nslot; q++) {
+            int s = nl->off[i] + q, j = nl->j[s];
+            double V, dV, r = nl->r[s];
+            zbl_pair(r, C->zbl[C->type[i]], C->zbl[C->type[j]], C->zbl[2], C->zbl[3], &V, &dV);
+            for (int a = 0; a < 3; a++) G[3 * q + a] += 0.5 * dV * nl->d[3 * s + a] / r;
+        }
+    }
     nb_t *e;
     int m = environment(C, i, &e);
     for (int t = 0; t < m; t++) {
@@ -611,6 +664,7 @@ static void ctx_init(ctx_t *C, int n, const int *type, const double *pos, const 
                      int act, int use_cells) {
     C->n = n; C->type = type; C->pos = pos; C->box = box; C->pbc = pbc; C->p = p;
     C->rcR = rcR; C->rcA = rcA; C->act = act;
+    C->zbl = NULL;
     C->spin = malloc(sizeof(double) * 3 * (n + 1));
     for (int i = 0; i < n; i++)
         for (int a = 0; a < 3; a++) C->spin[3 * i + a] = type[i] == 0 ? spin[3 * i + a] : 0.0;
@@ -637,6 +691,16 @@ static double forward_all(const ctx_t *C, double *q, double *Fp, double *Ei) {
     for (int i = 0; i < n; i++) {
         descriptor_atom(C, i, q + (size_t)ND * i);
         Ei[i] = mlp_atom(C, C->type[i], q + (size_t)ND * i, Fp + (size_t)ND * i);
+        /* short-range repulsion: half of each pair's energy to each atom */
+        if (C->zbl) {
+            const nlist_t *nl = &C->nl;
+            for (int s = nl->off[i]; s < nl->off[i + 1]; s++) {
+                int j = nl->j[s];
+                double V, dV;
+                zbl_pair(nl->r[s], C->zbl[C->type[i]], C->zbl[C->type[j]], C->zbl[2], C->zbl[3], &V, &dV);
+                Ei[i] += 0.5 * V;
+            }
+        }
     }
     double E = 0;
     for (int i = 0; i < n; i++) E += Ei[i];
@@ -746,13 +810,16 @@ int or_neighbors(int n, const double *pos, const double *box, const int *pbc, do
     return over ? -1 : 0;
 }
 
-/* E = E_NEP (+ E_Zeeman reported separately); all outputs optional */
+/* E = E_NEP (+ E_Zeeman reported separately); all outputs optional. zbl:
+ * {Z_0, Z_1, r_inner, r_outer} of the short-range term, or NULL (off, also
+ * when r_outer <= 0); E_NEP and E_i then include it. */
 int or_eval(int n, const int *type, const double *pos, const double *spin, const double *box,
             const int *pbc, const double *params, double rcR, double rcA, int act,
             double mu_s, const double *B, double *E_nep, double *E_z, double *Ei, double *F,
-            double *H, double *q_out, double *Fp_out) {
+            double *H, double *q_out, double *Fp_out, const double *zbl) {
     ctx_t C;
     ctx_init(&C, n, type, pos, spin, box, pbc, params, rcR, rcA, act, n > 4096);
+    if (zbl && zbl[3] > 0) C.zbl = zbl;
     double *q = malloc(sizeof(double) * ND * (size_t)(n + 1));
     double *Fp = malloc(sizeof(double) * ND * (size_t)(n + 1));
     double *Ea = malloc(sizeof(double) * (n + 1));
@@ -807,6 +874,8 @@ typedef struct {
      * spins, the step is B A O A B; masses per species (u), 0 = Fe/Ge */
     int structural;
     double mass[2];
+    /* short-range repulsion {Z_0, Z_1, r_inner, r_outer}; off when r_outer <= 0 */
+    double zbl[4];
 } or_step_params;
 
 typedef struct {
@@ -1004,6 +1073,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         double frac = sp->n_ramp > 0 ? (double)(*step < sp->n_ramp ? *step : sp->n_ramp) / sp->n_ramp : 0.0;
         for (int a = 0; a < 3; a++) B[a] = sp->B0[a] + (sp->B1[a] - sp->B0[a]) * frac;
         ctx_init(&C, n, type, pos, spin, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
+        if (sp->zbl[3] > 0) C.zbl = sp->zbl;
         forward_all(&C, q, Fp, Ei);
         forces_fields(&C, Fp, sp->mu_s, Bz, F, H);
         ctx_free(&C);
@@ -1133,6 +1203,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         wrap(n, pos, box, pbc);
         /* full evaluation at (R^{n+1}, S^{n+1}) */
         ctx_init(&C, n, type, pos, spin, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
+        if (sp->zbl[3] > 0) C.zbl = sp->zbl;
         double E = forward_all(&C, q, Fp, Ei);
         forces_fields(&C, Fp, sp->mu_s, B, F, H);
         double Ez = zeeman(&C, sp->mu_s, B);

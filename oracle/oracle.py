@@ -75,7 +75,7 @@ class StepParams(ct.Structure):
                 ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
                 ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int), ("sc_max", ct.c_int),
                 ("sc_tol", ct.c_double), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double),
-                ("structural", ct.c_int), ("mass", ct.c_double * 2)]
+                ("structural", ct.c_int), ("mass", ct.c_double * 2), ("zbl", ct.c_double * 4)]
 
 
 class Obs(ct.Structure):
@@ -95,7 +95,7 @@ def lib():
         L = ct.CDLL(LIB_PATH)
         P = ct.c_void_p
         L.or_eval.argtypes = [ct.c_int, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
-                              ct.c_double, P, P, P, P, P, P, P, P]
+                              ct.c_double, P, P, P, P, P, P, P, P, P]
         L.or_neighbors.argtypes = [ct.c_int, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
         L.or_philox.argtypes = [P, P, P]
         L.or_field_lin.argtypes = [ct.c_int, P, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
@@ -136,11 +136,21 @@ def neighbors(pos, box, pbc, rc, use_cells=False, maxnb=256):
     return [nbr[i, :cnt[i]].copy() for i in range(n)]
 
 
+def _zbl(zbl):
+    """short-range term (Z_0, Z_1, r_inner, r_outer) as a C array, or None"""
+    if zbl is None:
+        return None
+    z = np.ascontiguousarray(zbl, dtype=np.float64)
+    assert z.shape == (4,)
+    return z
+
+
 def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0), act=0,
-             rcR=RC_R, rcA=RC_A, want=("E", "F", "H")):
+             rcR=RC_R, rcA=RC_A, want=("E", "F", "H"), zbl=None):
     """Energy, forces, fields (and optionally q, Fp, per-atom E) of one system;
     params of the spin-aware model, or of the structural-only one (spins are
-    then ignored, and q / Fp keep the first 37 columns)."""
+    then ignored, and q / Fp keep the first 37 columns). zbl = (Z_0, Z_1,
+    r_inner, r_outer) adds the short-range repulsion to E and E_i."""
     types = _i32(types)
     pos = _f64(pos)
     n = types.shape[0]
@@ -155,7 +165,8 @@ def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0),
     q = np.zeros((n, N_DESC)) if "q" in want else None
     Fp = np.zeros((n, N_DESC)) if "Fp" in want else None
     lib().or_eval(n, _p(types), _p(pos), _p(spin), _p(_f64(box)), _p(_i32(pbc)), _p(_f64(params)),
-                  rcR, rcA, act, mu_s, _p(_f64(B)), _p(E), _p(Ez), _p(Ei), _p(F), _p(H), _p(q), _p(Fp))
+                  rcR, rcA, act, mu_s, _p(_f64(B)), _p(E), _p(Ez), _p(Ei), _p(F), _p(H), _p(q), _p(Fp),
+                  _p(_zbl(zbl)))
     out["E"] = float(E[0])
     out["Ez"] = float(Ez[0])
     for k, v in (("Ei", Ei), ("F", F), ("H", H), ("q", q), ("Fp", Fp)):
@@ -203,8 +214,11 @@ def normals(seed, atom, step, stream):
 def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
                 mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
                 K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30, sc_depth=0,
-                sc_reg=1e-10, structural=0, mass=(0.0, 0.0)) -> StepParams:
+                sc_reg=1e-10, structural=0, mass=(0.0, 0.0), zbl=None) -> StepParams:
     sp = StepParams()
+    if zbl is not None:
+        for a in range(4):
+            sp.zbl[a] = zbl[a]
     sp.dt = dt
     sp.T0 = T0
     sp.T1 = T0 if T1 is None else T1

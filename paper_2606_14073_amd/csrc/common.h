@@ -127,6 +127,13 @@ __device__ inline double dsqrt<double>(double x) { return sqrt(x); }
 template <>
 __device__ inline float dsqrt<float>(float x) { return sqrtf(x); }
 template <typename real>
+__device__ inline real dexp(real x);
+template <>
+__device__ inline double dexp<double>(double x) { return exp(x); }
+template <>
+__device__ inline float dexp<float>(float x) { return expf(x); }
+
+template <typename real>
 __device__ inline real dtanh(real x);
 template <>
 __device__ inline double dtanh<double>(double x) { return tanh(x); }

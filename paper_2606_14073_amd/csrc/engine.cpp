@@ -69,22 +69,26 @@ static double now_s() {
 // model
 // ---------------------------------------------------------------------------
 
-constexpr size_t MODEL_DEV = 324 + 252 + 4 * 324 + 252 + 2 * DP * NH + 2 * NH + 2 * NH + 2;
-
 struct nep_model {
     std::vector<double> p;          // spin-aware layout (a structural-only model is expanded)
     bool structural = false;
+    double zbl[4] = {0, 0, 0, 0};   // short-range term: Z_0, Z_1, r_inner, r_outer (r_outer 0: off)
     double *d64 = nullptr;
     float *d32 = nullptr;
-    float *dbf = nullptr;
     ModelDev<double> m64{};
     ModelDev<float> m32{};
     std::mutex eval_mu;
-    struct Engine *eval_eng[3] = {nullptr, nullptr, nullptr};
+    struct Engine *eval_eng[2] = {nullptr, nullptr};
 };
 
+// e^2/(4 pi eps0) in eV A, the Bohr radius in A (CODATA), and the universal
+// screening length a = 0.8854 a_Bohr / (Z_i^0.23 + Z_j^0.23) of Ziegler,
+// Biersack and Littmark
+constexpr double K_COULOMB = 14.399645;
+constexpr double A_BOHR = 0.529177210903;
+
 template <typename real>
-static void model_layout(const std::vector<double> &p, std::vector<real> &h) {
+static void model_layout(const std::vector<double> &p, const double *zbl, std::vector<real> &h) {
     h.assign(MODEL_DEV, real(0));
     size_t o = 0;
     auto copy = [&](int off, int n) {
@@ -109,10 +113,21 @@ static void model_layout(const std::vector<double> &p, std::vector<real> &h) {
     for (int t = 0; t < 2; t++)
         for (int hh = 0; hh < NH; hh++) h[o++] = (real)p[P_MLP + t * P_MLP_STRIDE + NH * ND + NH + hh];
     for (int t = 0; t < 2; t++) h[o++] = (real)p[P_MLP + t * P_MLP_STRIDE + NH * ND + 2 * NH];
+    if (zbl[3] > 0) {
+        for (int tau = 0; tau < 4; tau++) {
+            const double zi = zbl[tau >> 1], zj = zbl[tau & 1];
+            h[M_ZBL + tau] = (real)(K_COULOMB * zi * zj);
+            h[M_ZBL + 4 + tau] = (real)((std::pow(zi, 0.23) + std::pow(zj, 0.23)) / (0.8854 * A_BOHR));
+        }
+        h[M_ZBL + 8] = (real)zbl[2];
+        h[M_ZBL + 9] = (real)zbl[3];
+        h[M_ZBL + 10] = (real)(M_PI / (zbl[3] - zbl[2]));
+        h[M_ZBL + 11] = real(1);
+    }
 }
 
 template <typename real>
-static ModelDev<real> model_ptrs(real *base, const float *bf) {
+static ModelDev<real> model_ptrs(real *base) {
     ModelDev<real> m;
     size_t o = 0;
     m.cR = base + o; o += 324;
@@ -126,18 +141,7 @@ static ModelDev<real> model_ptrs(real *base, const float *bf) {
     m.b0 = base + o; o += 2 * NH;
     m.w1 = base + o; o += 2 * NH;
     m.b1 = base + o; o += 2;
-    m.W0bf = bf;
     return m;
-}
-
-static float to_bf16(float x) {
-    uint32_t u;
-    std::memcpy(&u, &x, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    u &= 0xFFFF0000u;
-    float r;
-    std::memcpy(&r, &u, 4);
-    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -345,7 +349,6 @@ struct Engine {
         w.selfc = take(cf * 8);
         w.cpl_j = cpl_j;
         w.cpl_n = cpl_n;
-        w.bf16 = prec == SL_FP32_BF16H;
     }
 
     static size_t work_count(size_t c, size_t cf) {
@@ -1234,6 +1237,14 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
         return fail(SL_E_INVALID, "unsupported hyper-parameters (this build: n_max_R 8, n_max_A 6, l_max 4, "
                                   "basis_K 8, n_hidden 64, 2 species, rc 6.0/4.5)");
     if (hp->structural != 0 && hp->structural != 1) return fail(SL_E_INVALID, "structural must be 0 or 1");
+    if (hp->sr_r_outer != 0.0) {
+        const bool ok = std::isfinite(hp->sr_Z[0]) && std::isfinite(hp->sr_Z[1]) && hp->sr_Z[0] > 0 &&
+                        hp->sr_Z[1] > 0 && std::isfinite(hp->sr_r_inner) && hp->sr_r_inner > 0 &&
+                        hp->sr_r_inner < hp->sr_r_outer && hp->sr_r_outer <= RC_R;
+        if (!ok)
+            return fail(SL_E_INVALID, "short-range term: need Z_0, Z_1 > 0 and 0 < r_inner < r_outer <= rc_R "
+                                      "(r_outer = 0 turns it off)");
+    }
     const size_t want = hp->structural ? (size_t)N_PARAMS_STRUCT : (size_t)N_PARAMS;
     if (n_params != want)
         return fail(SL_E_INVALID, hp->structural ? "expected 5570 parameters (structural-only model)"
@@ -1247,23 +1258,24 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
     }
     auto m = std::make_unique<nep_model>();
     m->structural = hp->structural == 1;
+    if (hp->sr_r_outer != 0.0) {
+        m->zbl[0] = hp->sr_Z[0];
+        m->zbl[1] = hp->sr_Z[1];
+        m->zbl[2] = hp->sr_r_inner;
+        m->zbl[3] = hp->sr_r_outer;
+    }
     if (m->structural) m->p = expand_structural(params);
     else m->p.assign(params, params + n_params);
     std::vector<double> h64;
     std::vector<float> h32;
-    model_layout(m->p, h64);
-    model_layout(m->p, h32);
-    std::vector<float> hbf(2 * (size_t)DP * NH);
-    const size_t w0off = 324 + 252 + 4 * 324 + 252;
-    for (size_t k = 0; k < hbf.size(); k++) hbf[k] = to_bf16((float)h64[w0off + k]);
+    model_layout(m->p, m->zbl, h64);
+    model_layout(m->p, m->zbl, h32);
     int rc;
-    if ((rc = dalloc(&m->d64, MODEL_DEV)) || (rc = dalloc(&m->d32, MODEL_DEV)) || (rc = dalloc(&m->dbf, hbf.size())))
-        return rc;
+    if ((rc = dalloc(&m->d64, MODEL_DEV)) || (rc = dalloc(&m->d32, MODEL_DEV))) return rc;
     HIPCHK(hipMemcpy(m->d64, h64.data(), MODEL_DEV * 8, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(m->d32, h32.data(), MODEL_DEV * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(m->dbf, hbf.data(), hbf.size() * 4, hipMemcpyHostToDevice));
-    m->m64 = model_ptrs(m->d64, m->dbf);
-    m->m32 = model_ptrs(m->d32, m->dbf);
+    m->m64 = model_ptrs(m->d64);
+    m->m32 = model_ptrs(m->d32);
     *out = m.release();
     return SL_OK;
 }
@@ -1273,13 +1285,13 @@ extern "C" int nep_model_destroy(nep_model *m) {
     for (auto &e : m->eval_eng) delete e;
     dfree(m->d64);
     dfree(m->d32);
-    dfree(m->dbf);
     delete m;
     return SL_OK;
 }
 
 static int check_prec(sl_precision p) {
-    if (p != SL_FP64 && p != SL_FP32_MIXED && p != SL_FP32_BF16H) return fail(SL_E_INVALID, "unknown precision");
+    if (p != SL_FP64 && p != SL_FP32_MIXED)
+        return fail(SL_E_INVALID, "unknown precision (SL_FP64 or SL_FP32_MIXED)");
     return SL_OK;
 }
 
@@ -1292,7 +1304,7 @@ static int eval_common(const nep_model *mc, const sl_system_view *sys, sl_precis
     if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r, m->structural))) return rc;
     // one evaluation engine per model: the work arrays of another precision,
     // or of a system more than eight times larger, are released first
-    for (int q = 0; q < 3; q++)
+    for (int q = 0; q < 2; q++)
         if (m->eval_eng[q] && (q != (int)prec || (size_t)r.n * 8 < m->eval_eng[q]->cap)) {
             delete m->eval_eng[q];
             m->eval_eng[q] = nullptr;

@@ -36,12 +36,19 @@ struct Sys {
     int *flags;
 };
 
+// Device copy of a model, one array per arithmetic type: c^R, c^A, c^ex,
+// c^dm, c^an, c^si, c^sa, W0 [2][DP][NH] (transposed, zero padded), b0, w1,
+// b1, then the optional short-range term at M_ZBL: K Z_i Z_j and the inverse
+// screening length 1/a for each pair type tau = 2 t_i + t_j, r_inner,
+// r_outer, pi / (r_outer - r_inner), and 1 when the term is on (else 0).
+constexpr int M_ZBL = 324 + 252 + 4 * 324 + 252 + 2 * DP * NH + 2 * NH + 2 * NH + 2;
+constexpr int MODEL_DEV = M_ZBL + 12;
+
 template <typename real>
 struct ModelDev {
     const real *cR, *cA, *cEX, *cDM, *cAN, *cSI, *cSA;   // [4][n][9]
     const real *W0;        // [2][64][DP], zero padded
     const real *b0, *w1, *b1;
-    const float *W0bf;     // [2][64][DP], W0 rounded to bf16 (for the BF16 variant)
 };
 
 template <typename real>
@@ -58,7 +65,6 @@ struct Work {
     real *selfc;                // [N_fe][8]: A_i (xx yy zz xy xz yz), o_i (colour-list order)
     int *cpl_j;                 // [MAXFE][N_fe]: neighbour of each coupling (colour-list order)
     int *cpl_n;                 // [N_fe]: couplings inside rc_R per spin (colour-list order)
-    int bf16;                   // read-out input->hidden contraction in BF16
 };
 
 // ---- launchers (kernels_*.hip) ----

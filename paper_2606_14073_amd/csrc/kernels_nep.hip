@@ -487,15 +487,9 @@ __global__ void __launch_bounds__(64) k_desc_angular(Sys S, const real *__restri
 // One wavefront takes a tile of 16 atoms of one species; W0^T of that species
 // is staged in LDS once per workgroup. Operand layout of v_mfma_*_16x16x4:
 // A[i][k] in lane i + 16k, B[k][j] in lane j + 16k. Accumulator element r of
-// lane l holds column l % 16 and row 4 (l / 16) + r for the FP32 and BF16
-// instructions, row (l / 16) + 4 r for the FP64 one (checked on gfx950).
+// lane l holds column l % 16 and row 4 (l / 16) + r for the FP32
+// instruction, row (l / 16) + 4 r for the FP64 one (checked on gfx950).
 // -------------------------------------------------------------------------
-
-__device__ inline float bf16_round(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __uint_as_float(u & 0xFFFF0000u);
-}
 
 template <typename real>
 struct MF;
@@ -511,7 +505,6 @@ struct MF<float> {
     __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int kq, int r) { return 4 * kq + r; }
 };
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int MLP_WAVES = 8;           // 8 wavefronts x 16 atoms per workgroup
 constexpr int MLP_ATOMS = 16 * MLP_WAVES;
@@ -625,36 +618,7 @@ __global__ void __launch_bounds__(512) k_mlp(Sys S, ModelDev<real> M, Work<real>
         const real b0 = M.b0[t * NH + jt * 16 + i16];
         acc[jt] = acc_t{b0, b0, b0, b0};
     }
-    bool done = false;
-    if constexpr (sizeof(real) == 4) {
-        if (W.bf16) {
-            // input->hidden contraction in BF16 (FP32 sums): 16x16x16 blocks,
-            // A[i][4kq..4kq+3] and B[4kq..4kq+3][j] packed four to a lane
-            const float *Wb = M.W0bf + (size_t)t * DP * NH;
-            for (int ks = 0; ks < NT; ks++) {
-                bf16x4_t a;
-#pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int d = ks * 16 + 4 * kq + u;
-                    const float v = (rv && d < KD) ? bf16_round((float)qrow[d]) : 0.f;
-                    a[u] = (short)(__float_as_uint(v) >> 16);
-                }
-#pragma unroll
-                for (int jt = 0; jt < 4; jt++) {
-                    bf16x4_t b;
-#pragma unroll
-                    for (int u = 0; u < 4; u++) {
-                        const int d = ks * 16 + 4 * kq + u;
-                        const float v = d < KD ? Wb[d * NH + jt * 16 + i16] : 0.f;
-                        b[u] = (short)(__float_as_uint(v) >> 16);
-                    }
-                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[jt], 0, 0, 0);
-                }
-            }
-            done = true;
-        }
-    }
-    if (!done) {
+    {
         // this lane's 26 descriptor values, all loads in flight at once
         real qa[KD / 4];
 #pragma unroll
@@ -809,6 +773,33 @@ __device__ inline void partner_radial(const real *cR, const real *cS, bool fe_j,
     }
 }
 
+// Optional short-range repulsion of one pair of type tau at distance r: the
+// universal screened-Coulomb (ZBL) potential K Z_i Z_j / r phi(r/a), phi a
+// sum of four exponentials of r/a, times the switch
+// (1 + cos(pi (r - r_inner)/(r_outer - r_inner)))/2 above r_inner. Z is the
+// model's short-range block (products K Z_i Z_j, inverse screening lengths,
+// r_inner, r_outer, pi/(r_outer - r_inner)). V and dV/dr of the pair.
+template <typename real>
+__device__ inline void short_range(const real *Z, int tau, real r, real ir, real &V, real &dV) {
+    const real ia = Z[4 + tau];
+    const real c0 = real(0.18175) * dexp<real>(real(-3.19980) * ia * r);
+    const real c1 = real(0.50986) * dexp<real>(real(-0.94229) * ia * r);
+    const real c2 = real(0.28022) * dexp<real>(real(-0.40290) * ia * r);
+    const real c3 = real(0.02817) * dexp<real>(real(-0.20162) * ia * r);
+    const real phi = c0 + c1 + c2 + c3;
+    const real dphi = -ia * (real(3.19980) * c0 + real(0.94229) * c1 + real(0.40290) * c2 + real(0.20162) * c3);
+    const real v = Z[tau] * phi * ir;
+    const real dv = Z[tau] * (dphi - phi * ir) * ir;
+    real s = 1, ds = 0;
+    if (r > Z[8]) {
+        const real w = Z[10], x = w * (r - Z[8]);
+        s = real(0.5) * (real(1) + dcos<real>(x));
+        ds = real(-0.5) * w * dsin<real>(x);
+    }
+    V = v * s;
+    dV = dv * s + v * ds;
+}
+
 template <typename real>
 __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restrict__ C, Work<real> W, int nbFe) {
     bool fe;
@@ -823,6 +814,12 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
     // the neighbours' contracted blocks for this atom's species
     const real *nR = W.rcoef + (size_t)(fe ? 0 : 1) * ld * NB, *nS = W.rcoef + (size_t)(fe ? 2 : 3) * ld * NB;
     real F[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    // short-range term: half of every pair's energy goes to E_i; the force of
+    // the pair on i is V'(r) rhat_ij (both halves)
+    const real *Z = C + M_ZBL;
+    const bool zon = Z[11] != real(0);
+    const real zr2 = zon ? Z[9] : real(0);
+    real esr = 0;
     if (fe && S.mag) {
         real si[3];
         load_spin(S.spin, i, si);
@@ -865,6 +862,13 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                     h[x] += real(2) * gS * a * rh[x];
                     F[x] += G - Gj[x];
                 }
+                if (r < zr2) {
+                    real V, dV;
+                    short_range(Z, part, r, ir, V, dV);
+                    esr += real(0.5) * V;
+#pragma unroll
+                    for (int x = 0; x < 3; x++) F[x] += dV * rh[x];
+                }
             }
         }
     } else {
@@ -894,10 +898,18 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
                 partner_radial(nR, nS, S.mag && part == 0, S.spin, j, r, ir, rh, f, df, Gj);
 #pragma unroll
                 for (int x = 0; x < 3; x++) F[x] += g * rh[x] - Gj[x];
+                if (r < zr2) {
+                    real V, dV;
+                    short_range(Z, (fe ? 0 : 2) + part, r, ir, V, dV);
+                    esr += real(0.5) * V;
+#pragma unroll
+                    for (int x = 0; x < 3; x++) F[x] += dV * rh[x];
+                }
             }
         }
     }
     put_pair(W.ownR, (size_t)i, F, h);
+    if (esr != real(0)) W.Ei[i] += esr;
 }
 
 // Magnetic pair part of the radial-set backward pass: exchange, DMI and

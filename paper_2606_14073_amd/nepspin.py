@@ -16,10 +16,10 @@ LIB_PATH = os.path.join(HERE, "libnepspin.so")
 
 SL_OK, SL_E_INVALID, SL_E_OOM, SL_E_BOX, SL_E_DEVICE, SL_E_NONFINITE, SL_E_NOTFOUND, SL_E_BUSY, \
     SL_E_OVERFLOW, SL_E_NOLIB = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-SL_FP64, SL_FP32_MIXED, SL_FP32_BF16H = 0, 1, 2
+SL_FP64, SL_FP32_MIXED = 0, 1
 SL_QUEUED, SL_RUNNING, SL_DONE, SL_FAILED = 0, 1, 2, 3
 
-PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED, "bf16h": SL_FP32_BF16H}
+PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED}
 
 EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
@@ -44,7 +44,8 @@ class NepError(RuntimeError):
 class HParams(ct.Structure):
     _fields_ = [("n_max_R", ct.c_int), ("n_max_A", ct.c_int), ("l_max", ct.c_int), ("basis_K", ct.c_int),
                 ("n_hidden", ct.c_int), ("n_species", ct.c_int), ("rc_R", ct.c_double), ("rc_A", ct.c_double),
-                ("structural", ct.c_int)]
+                ("structural", ct.c_int), ("sr_Z", ct.c_double * 2), ("sr_r_inner", ct.c_double),
+                ("sr_r_outer", ct.c_double)]
 
 N_PARAMS = 15438
 N_PARAMS_STRUCT = 5570     # structural-only NEP: c^R, c^A, per species W0[64][37], b0, w1, b1
@@ -185,13 +186,18 @@ def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s
 
 class Model:
     """nep_model_create: the spin-aware NEP (15,438 parameters) or the
-    structural-only one (5,570 parameters), told apart by the length."""
+    structural-only one (5,570 parameters), told apart by the length.
+    short_range = (Z_0, Z_1, r_inner, r_outer) adds the screened-Coulomb
+    repulsion; None leaves it off."""
 
-    def __init__(self, params):
+    def __init__(self, params, short_range=None):
         L = load()
         p = _f64(params)
         self.structural = p.size == N_PARAMS_STRUCT
         hp = HParams(8, 6, 4, 8, 64, 2, 6.0, 4.5, int(self.structural))
+        if short_range is not None:
+            hp.sr_Z[0], hp.sr_Z[1], hp.sr_r_inner, hp.sr_r_outer = (float(x) for x in short_range)
+        self.short_range = short_range
         h = ct.c_void_p()
         _check(L.nep_model_create(ct.byref(hp), _p(p), p.size, ct.byref(h)))
         self.h = h

@@ -43,6 +43,13 @@ SEED_WEIGHTS = 0
 SEED_STATE = 1
 SEED_PHILOX = 0x5EED
 
+# The optional short-range repulsion of the FeGe workloads: nuclear charges of
+# Fe and Ge, and the interval over which the repulsion is switched off (A).
+# The seeded random weights alone let neighbours approach to under 1.5 A
+# within 100-200 steps at 300 K (weight seeds 0-12 all do); below 2 A the
+# screened-Coulomb term keeps them apart.
+SHORT_RANGE_FEGE = (26.0, 32.0, 1.0, 2.0)
+
 
 def b20_fractional(u: float) -> np.ndarray:
     """The four 4a sites of space group P2_1 3 for parameter u (mod 1)."""

@@ -25,6 +25,18 @@ def min_image_delta(a, b, box, pbc):
     return d
 
 
+def pos_error(pos1, rp, pos0, box, pbc):
+    """Position error of one step, relative to the step's own displacement:
+    ||dr||_inf / ||r^{n+1} - r^n||_inf (minimum image), with r^{n+1} the
+    reference. Stored coordinates round at ulp(|r|), about 3e-14 A on a 150 A
+    box, i.e. ~1e-11 of a 1 fs displacement; that floor (4 ulp of the largest
+    coordinate) is subtracted before the ratio is taken."""
+    dpos = np.abs(min_image_delta(pos1, rp, box, pbc)).max()
+    disp = np.abs(min_image_delta(rp, pos0, box, pbc)).max()
+    floor = 4 * np.spacing(np.abs(rp).max())
+    return max(dpos - floor, 0.0) / disp if disp > 0 else dpos
+
+
 def cluster_around(types, pos, spin, box, pbc, k, radius):
     """Atoms within `radius` of atom k, unwrapped by minimum image into a free
     cluster; returns (types, pos, spin, index of k in the cluster)."""
@@ -34,14 +46,14 @@ def cluster_around(types, pos, spin, box, pbc, k, radius):
     return types[sel], cpos, spin[sel], int(np.nonzero(sel == k)[0][0])
 
 
-def oracle_local(oracle, types, pos, spin, box, pbc, params, atoms, *, B=(0, 0, 0), mu_s=1.0):
+def oracle_local(oracle, types, pos, spin, box, pbc, params, atoms, *, B=(0, 0, 0), mu_s=1.0, zbl=None):
     """Per-atom E_i, F_i, H_i of selected atoms of a large system, each from a
     free cluster of radius 2 rc + 1 A around it (everything that reaches it)."""
     Ei, F, H = [], [], []
     for k in atoms:
         ct, cp, cs, kk = cluster_around(types, pos, spin, box, pbc, k, 13.0)
         o = oracle.evaluate(ct, cp, cs, np.array([1e5] * 3), np.zeros(3, np.int32), params, B=B, mu_s=mu_s,
-                            want=("E", "F", "H", "Ei"))
+                            want=("E", "F", "H", "Ei"), zbl=zbl)
         Ei.append(o["Ei"][kk])
         F.append(o["F"][kk])
         H.append(o["H"][kk])

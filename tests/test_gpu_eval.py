@@ -66,21 +66,116 @@ def test_eval_deterministic(model):
     assert a["E"] == b["E"]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16h"])
-def test_eval_mixed_precision_error(model, oracle, prec):
+def test_eval_mixed_precision_error(model, oracle):
     s = W.fege_lattice(7, 7, 7)
     p = W.random_params()
     ref = oracle.evaluate(s.types, s.pos, s.spin, s.box, s.pbc, p, B=(0, 0, 1.0))
-    got = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, B=(0, 0, 1.0), precision=prec)
+    got = model.eval(s.types, s.pos, s.spin, s.box, s.pbc, B=(0, 0, 1.0), precision="fp32")
     dE = abs(got["E"] - (ref["E"] + ref["Ez"])) / s.n
     dF = rel_l2(got["F"], ref["F"])
     dH = rel_l2(got["H"], ref["H"])
-    print(f"{prec}: dE/atom={dE:.3e} eV  dF={dF:.3e}  dH={dH:.3e}", flush=True)
-    if prec == "fp32":
-        assert dE <= 1e-6 and dF <= 1e-5 and dH <= 1e-5
+    print(f"fp32: dE/atom={dE:.3e} eV  dF={dF:.3e}  dH={dH:.3e}", flush=True)
+    assert dE <= 1e-6 and dF <= 1e-5 and dH <= 1e-5
+
+
+def test_precision_modes(model):
+    """only FP64 and FP32-mixed exist; any other value is an error"""
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    v, keep = nepspin.system_view(s.types, s.pos, s.spin, s.box, s.pbc)
+    import ctypes as ct
+    E = np.zeros(1)
+    for bad in (2, -1, 7):
+        rc = nepspin.load().nep_spin_eval(model.h, ct.byref(v), bad, E.ctypes.data_as(ct.c_void_p), None, None,
+                                          None, None)
+        assert rc == nepspin.SL_E_INVALID
+
+
+# ---------------------------------------------------------------------------
+# optional short-range repulsion
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def model_sr():
+    from paper_2606_14073_amd import nepspin
+    return nepspin.Model(W.random_params(), short_range=W.SHORT_RANGE_FEGE)
+
+
+def close_pairs(s, targets, seed):
+    """positions of crystal s with one atom of each of len(targets) random
+    atoms' nearest-neighbour pairs moved along the pair axis so that the pair
+    distance becomes the target (below, inside and above the switch of the
+    short-range term); neighbour counts stay those of the crystal"""
+    from tests.helpers import min_image_delta
+    rng = np.random.default_rng(seed)
+    pos = s.pos.copy()
+    moved = set()
+    for t in targets:
+        while True:
+            i = int(rng.integers(0, s.n))
+            d = min_image_delta(pos, pos[i], s.box, s.pbc)
+            r = np.linalg.norm(d, axis=1)
+            r[i] = 1e9
+            j = int(np.argmin(r))
+            if i not in moved and j not in moved:
+                break
+        u = d[j] / r[j]
+        pos[i] = pos[i] + (r[j] - t) * u
+        moved.update((i, j))
+    return pos
+
+
+@pytest.mark.parametrize("case", ["crystal", "close_pairs", "close_pairs_cluster"])
+def test_eval_short_range_fp64_matches_oracle(model_sr, oracle, case):
+    p = W.random_params()
+    zbl = W.SHORT_RANGE_FEGE
+    B = (0.1, 0.3, -0.2)
+    targets = (0.7, 0.95, 1.05, 1.3, 1.5, 1.75, 1.95, 2.05)
+    if case == "crystal":
+        s = W.fege_lattice(4, 4, 4, noise=0.3, seed=5)
+        pos, box = s.pos, s.box
+    elif case == "close_pairs":
+        s = W.fege_lattice(4, 4, 4, seed=3)
+        pos, box = close_pairs(s, targets, 3), s.box
     else:
-        # the BF16 read-out variant is reported, not required to pass
-        assert np.isfinite(dE) and dF < 1.0
+        s = W.fege_lattice(2, 3, 2, pbc=(0, 0, 0), seed=4)
+        pos, box = close_pairs(s, targets[:5], 4), np.zeros(3)
+    obox = box if np.all(s.pbc) else np.array([1e4] * 3)
+    ref = oracle.evaluate(s.types, pos, s.spin, obox, s.pbc, p, B=B, want=("E", "F", "H", "Ei"), zbl=zbl)
+    print(f"case {case}: n={s.n}", flush=True)
+    got = model_sr.eval(s.types, pos, s.spin, box, s.pbc, B=B, want=("E", "Ei", "F", "H"))
+    assert rel_inf(got["Ei"], ref["Ei"]) <= TOL64
+    assert abs(got["E"] - (ref["E"] + ref["Ez"])) <= TOL64 * abs(ref["E"] + ref["Ez"])
+    assert rel_inf(got["F"], ref["F"]) <= TOL64
+    assert rel_inf(got["H"], ref["H"]) <= TOL64
+    # the term really acts where pairs were moved close and is absent in the crystal
+    plain = oracle.evaluate(s.types, pos, s.spin, obox, s.pbc, p, B=B, want=("E",))
+    if case == "crystal":
+        assert ref["E"] == plain["E"]
+    else:
+        assert ref["E"] - plain["E"] > 1.0
+
+
+def test_eval_short_range_fp32_error(model_sr, oracle):
+    s = W.fege_lattice(7, 7, 7, seed=6)
+    pos = close_pairs(s, (1.2, 1.4, 1.6, 1.8, 1.9) * 4, 6)
+    p = W.random_params()
+    ref = oracle.evaluate(s.types, pos, s.spin, s.box, s.pbc, p, zbl=W.SHORT_RANGE_FEGE)
+    got = model_sr.eval(s.types, pos, s.spin, s.box, s.pbc, precision="fp32")
+    dE = abs(got["E"] - (ref["E"] + ref["Ez"])) / s.n
+    dF = rel_l2(got["F"], ref["F"])
+    dH = rel_l2(got["H"], ref["H"])
+    print(f"fp32 with short-range: dE/atom={dE:.3e} eV  dF={dF:.3e}  dH={dH:.3e}", flush=True)
+    assert dE <= 1e-6 and dF <= 1e-5 and dH <= 1e-5
+
+
+def test_short_range_arguments():
+    from paper_2606_14073_amd import nepspin
+    p = W.random_params()
+    for bad in ((26.0, 32.0, 2.0, 1.0), (0.0, 32.0, 1.0, 2.0), (26.0, 32.0, 1.0, 6.5), (26.0, 32.0, -1.0, 2.0)):
+        with pytest.raises(nepspin.NepError) as e:
+            nepspin.Model(p, short_range=bad)
+        assert e.value.code == nepspin.SL_E_INVALID
 
 
 def test_eval_full_size_sampled(model, oracle):

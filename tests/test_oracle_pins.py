@@ -245,6 +245,102 @@ def test_forces_fields_finite_difference(oracle):
 
 
 # --------------------------------------------------------------------------
+# Optional short-range repulsion (universal ZBL screened Coulomb, switched
+# off between r_inner and r_outer)
+# --------------------------------------------------------------------------
+
+KCOUL = 14.399645   # e^2/(4 pi eps0), eV A
+
+
+def _dimer(oracle, r, zbl, types=(0, 1), want=("E", "F", "Ei")):
+    pos = np.array([[50.0, 50, 50], [50.0 + r, 50, 50]])
+    return oracle.evaluate(np.array(types, np.int32), pos, np.zeros((2, 3)), np.array([200.0] * 3),
+                           np.zeros(3, np.int32), np.zeros(15438), zbl=zbl, want=want)
+
+
+def test_short_range_coulomb_limit(oracle):
+    """The screening function is 1 at contact and smooth, so r V(r) tends to
+    the bare Coulomb value e^2/(4 pi eps0) Z_i Z_j: 2 f(r) - f(2r) removes the
+    linear term of f(r) = r V(r) and leaves it within O(r^2)."""
+    for Z0, Z1, types in ((26.0, 32.0, (0, 1)), (26.0, 32.0, (0, 0)), (8.0, 1.0, (1, 1))):
+        zbl = (Z0, Z1, 1.0, 2.0)
+        r = 1e-5
+        f1 = r * _dimer(oracle, r, zbl, types)["E"]
+        f2 = 2 * r * _dimer(oracle, 2 * r, zbl, types)["E"]
+        Z = (Z0, Z1)
+        want = KCOUL * Z[types[0]] * Z[types[1]]
+        assert (2 * f1 - f2) / want == pytest.approx(1.0, abs=1e-7)
+        assert f1 / want < 1.0
+
+
+def test_short_range_switch_and_split(oracle):
+    """Switching: unchanged below r_inner, exactly one half at the middle of
+    [r_inner, r_outer] (1/2 (1 + cos(pi/2))), zero from r_outer on. Each atom
+    of a dimer holds half the pair energy, the forces are opposite and point
+    apart, and a trimer's energy is the sum of its three pairs' energies."""
+    full = _dimer(oracle, 1.5, (26.0, 32.0, 1.6, 2.0))
+    half = _dimer(oracle, 1.5, (26.0, 32.0, 1.0, 2.0))
+    assert half["E"] / full["E"] == pytest.approx(0.5, rel=1e-14)
+    assert full["Ei"][0] == full["Ei"][1] == pytest.approx(0.5 * full["E"], rel=1e-15)
+    assert full["E"] > 0 and full["F"][0, 0] < 0 and full["F"][1, 0] == -full["F"][0, 0]
+    assert _dimer(oracle, 2.0, (26.0, 32.0, 1.0, 2.0))["E"] == 0.0
+    assert _dimer(oracle, 2.3, (26.0, 32.0, 1.0, 2.0))["E"] == 0.0
+    zbl = (26.0, 32.0, 1.0, 2.2)
+    pos = np.array([[50.0, 50, 50], [51.3, 50.2, 50], [50.4, 51.5, 50.3]])
+    types = np.array([0, 1, 0], np.int32)
+    e3 = oracle.evaluate(types, pos, np.zeros((3, 3)), np.array([200.0] * 3), np.zeros(3, np.int32),
+                         np.zeros(15438), zbl=zbl, want=("E",))["E"]
+    pairs = 0.0
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        r = float(np.linalg.norm(pos[a] - pos[b]))
+        pairs += _dimer(oracle, r, zbl, (types[a], types[b]))["E"]
+    assert e3 == pytest.approx(pairs, rel=1e-13)
+
+
+def test_short_range_screening_length(oracle):
+    """The screening length depends on the pair only through Z_i^0.23 +
+    Z_j^0.23: pairs with equal sums have the same screening function, so their
+    energies at one distance stand in the ratio of the charge products."""
+    za = (8.0, 8.0)
+    zb = (1.0, (2 * 8.0 ** 0.23 - 1.0) ** (1 / 0.23))
+    for r in (0.3, 0.8, 1.4):
+        ea = _dimer(oracle, r, (za[0], za[1], 3.0, 4.0))["E"]
+        eb = _dimer(oracle, r, (zb[0], zb[1], 3.0, 4.0))["E"]
+        assert eb / ea == pytest.approx(zb[0] * zb[1] / 64.0, rel=1e-12)
+
+
+def test_short_range_forces_finite_difference(oracle):
+    """Full model plus the short-range term on a compressed cluster whose
+    closest pairs lie below, inside and above the switching interval: central
+    differences of the energy equal the forces and fields; the forces sum to
+    zero."""
+    rng = np.random.default_rng(21)
+    s = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
+    pos = (s.pos - s.pos.mean(axis=0)) * 0.62 + 100.0 + rng.normal(0, 0.05, s.pos.shape)
+    box, pbc = np.array([500.0] * 3), np.zeros(3, np.int32)
+    d = np.linalg.norm(pos[:, None] - pos[None], axis=2) + 1e9 * np.eye(s.n)
+    assert d.min() < 1.45 and np.sum((d > 1.45) & (d < 2.1)) >= 8
+    p = W.random_params()
+    zbl = (26.0, 32.0, 1.45, 2.1)
+    B = (0.2, 0.1, -0.4)
+    ref = oracle.evaluate(s.types, pos, s.spin, box, pbc, p, B=B, zbl=zbl)
+    Fmax = np.abs(ref["F"]).max()
+    assert np.abs(ref["F"].sum(axis=0)).max() <= 1e-12 * np.abs(ref["F"]).sum()
+
+    def etot(pp):
+        o = oracle.evaluate(s.types, pp, s.spin, box, pbc, p, B=B, zbl=zbl, want=())
+        return o["E"] + o["Ez"]
+    for i in range(0, s.n, 5):
+        for a in range(3):
+            h = 1e-5
+            pp = pos.copy(); pp[i, a] += h
+            ep = etot(pp)
+            pp[i, a] -= 2 * h
+            em = etot(pp)
+            assert abs(-(ep - em) / (2 * h) - ref["F"][i, a]) <= 1e-6 * Fmax
+
+
+# --------------------------------------------------------------------------
 # P5-P8: invariances
 # --------------------------------------------------------------------------
 
@@ -416,6 +512,76 @@ def test_larmor_precession_large_angles(oracle):
     ang = MUB * B * n * 1.0 / HBAR
     assert MUB * B * 0.5 / HBAR > 1.3
     np.testing.assert_allclose(s_out[0], [math.cos(ang), math.sin(ang), 0.0], atol=1e-13)
+
+
+def test_field_ramp_larmor(oracle):
+    """Ramp of the applied field: B_n = B0 + (B1 - B0) min(n, n_ramp)/n_ramp,
+    taken at the start of step n for both half rotations of that step. With
+    the zero model an isolated spin only precesses about z, by
+    mu_s mu_B |B_n| dt/hbar in step n, so the angle after steps n0..n1-1 is
+    mu_B dt/hbar sum_n |B_n|: a ramp shifted by one step (n+1, or n/(n_ramp-1))
+    changes the sum."""
+    p = np.zeros(15438)
+    pos = np.array([[10.0, 10, 10]])
+    spin0 = np.array([[1.0, 0, 0]])
+    box = np.array([100.0] * 3)
+    B1, n_ramp = 800.0, 4
+    sp = oracle.step_params(dt=1.0, B0=(0, 0, 0), B1=(0, 0, B1), n_ramp=n_ramp, mu_s=1.0)
+    for step0, n in ((0, 6), (2, 3), (5, 2)):
+        _, _, s_out, st, _ = oracle.run([0], pos, np.zeros((1, 3)), spin0, box, np.zeros(3, np.int32), p,
+                                        [0], sp, n, step0=step0)
+        assert st == step0 + n
+        fracs = [min(k, n_ramp) / n_ramp for k in range(step0, step0 + n)]
+        ang = MUB * B1 * sum(fracs) * 1.0 / HBAR
+        np.testing.assert_allclose(s_out[0], [math.cos(ang), math.sin(ang), 0.0], atol=1e-13)
+    # the angle of the unshifted ramp differs from a one-step shift by far more than the tolerance
+    assert MUB * B1 / n_ramp / HBAR > 1e-3
+
+
+def test_temperature_ramp_one_o_step(oracle):
+    """Ramp of the bath temperature: T_n = T0 + (T1 - T0) min(n, n_ramp)/n_ramp
+    at the start of step n. With the zero model and atoms at rest, step n
+    leaves exactly v_i = sqrt((1 - c1^2) kappa kB T_n / m_i) xi_i, c1 =
+    exp(-gamma_L dt), xi_i the lattice-stream normals of (atom i, step n)."""
+    n_at = 6
+    pos = np.stack([np.arange(n_at) * 20.0 + 10, np.full(n_at, 10.0), np.full(n_at, 10.0)], axis=1)
+    types = np.array([0, 1, 0, 1, 0, 1], np.int32)
+    spin = np.zeros((n_at, 3))
+    spin[types == 0] = [0, 0, 1.0]
+    T0, T1, n_ramp, g, dt, seed = 100.0, 500.0, 4, 0.01, 1.0, 1234
+    sp = oracle.step_params(dt=dt, T0=T0, T1=T1, n_ramp=n_ramp, gammaL=g, ensemble=1, seed=seed)
+    c1 = math.exp(-g * dt)
+    for n in range(6):
+        _, vel, _, _, _ = oracle.run(types, pos, np.zeros((n_at, 3)), spin, np.array([1e3] * 3),
+                                     np.zeros(3, np.int32), np.zeros(15438), np.where(types == 0, 0, -1), sp, 1,
+                                     step0=n)
+        Tn = T0 + (T1 - T0) * min(n, n_ramp) / n_ramp
+        for i in range(n_at):
+            sig = math.sqrt((1 - c1 * c1) * KAPPA * KB * Tn / W.MASS[types[i]])
+            np.testing.assert_allclose(vel[i], sig * oracle.normals(seed, i, n, 0), rtol=1e-14, atol=0)
+
+
+def test_spin_temperature_estimator(oracle):
+    """T_spin = sum |s x H|^2 / (2 kB sum s.H) over the spins, with H the full
+    field at the end of the step. Zero model: H_i = mu_s mu_B B, and spins at
+    polar angles theta_i to B keep them while they precess, so
+    T_spin = mu_s mu_B |B| sum sin^2 theta_i / (2 kB sum cos theta_i) and
+    E_Z = -mu_s mu_B |B| sum cos theta_i."""
+    th = np.array([0.3, 1.1, 0.7, 2.0, 0.05])
+    ph = np.array([0.0, 1.0, 2.5, 4.0, 5.5])
+    n_at = th.size
+    spin = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], axis=1)
+    pos = np.stack([np.arange(n_at) * 20.0 + 10, np.full(n_at, 10.0), np.full(n_at, 10.0)], axis=1)
+    types = np.zeros(n_at, np.int32)
+    Bz, mu_s = 50.0, 2.2
+    sp = oracle.step_params(dt=1.0, B0=(0, 0, Bz), mu_s=mu_s)
+    _, _, s_out, _, ob = oracle.run(types, pos, np.zeros((n_at, 3)), spin, np.array([1e3] * 3),
+                                    np.zeros(3, np.int32), np.zeros(15438), np.arange(n_at), sp, 1)
+    np.testing.assert_allclose(s_out[:, 2], np.cos(th), atol=1e-14)
+    h = mu_s * MUB * Bz
+    want = h * np.sum(np.sin(th) ** 2) / (2 * KB * np.sum(np.cos(th)))
+    assert ob[0, 5] == pytest.approx(want, rel=1e-13)
+    assert ob[0, 3] == pytest.approx(-h * np.sum(np.cos(th)), rel=1e-13)
 
 
 def test_spin_norm_preserved(oracle):
