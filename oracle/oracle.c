@@ -336,6 +336,7 @@ typedef struct {
     double rcR, rcA;
     int act;               /* 0 tanh, 1 identity (linear read-out, tests only) */
     const double *zbl;     /* short-range term {Z_0, Z_1, r_inner, r_outer}, or NULL */
+    const double *landau;  /* onsite moment-length term {a, b} of spin carriers, or NULL */
     nlist_t nl;            /* neighbours within rcR */
     struct nb_s **env;     /* optional per-atom environments (spin step only) */
     int *env_m;
@@ -495,6 +496,10 @@ static void backward_atom(const ctx_t *C, int i, const double *Fp, double *G,
     memset(G, 0, sizeof(double) * 3 * nslot);
     memset(hnb, 0, sizeof(double) * 3 * nslot);
     for (int a = 0; a < 3; a++) hown[a] = 2.0 * Fp[D_OS] * si[a];
+    if (C->landau && C->type[i] == 0) {
+        double r2 = dot3(si, si), k = 2.0 * C->landau[0] + 4.0 * C->landau[1] * r2;
+        for (int a = 0; a < 3; a++) hown[a] += k * si[a];
+    }
     /* short-range repulsion: E_i holds V(r_ij)/2, dr_ij/dd_ij = rhat_ij */
     if (C->zbl) {
         for (int q = 0; q < nslot; q++) {
@@ -665,6 +670,7 @@ static void ctx_init(ctx_t *C, int n, const int *type, const double *pos, const 
     C->n = n; C->type = type; C->pos = pos; C->box = box; C->pbc = pbc; C->p = p;
     C->rcR = rcR; C->rcA = rcA; C->act = act;
     C->zbl = NULL;
+    C->landau = NULL;
     C->spin = malloc(sizeof(double) * 3 * (n + 1));
     for (int i = 0; i < n; i++)
         for (int a = 0; a < 3; a++) C->spin[3 * i + a] = type[i] == 0 ? spin[3 * i + a] : 0.0;
@@ -691,6 +697,11 @@ static double forward_all(const ctx_t *C, double *q, double *Fp, double *Ei) {
     for (int i = 0; i < n; i++) {
         descriptor_atom(C, i, q + (size_t)ND * i);
         Ei[i] = mlp_atom(C, C->type[i], q + (size_t)ND * i, Fp + (size_t)ND * i);
+        /* onsite moment-length term a |s|^2 + b |s|^4 of a spin carrier */
+        if (C->landau && C->type[i] == 0) {
+            double r2 = dot3(C->spin + 3 * i, C->spin + 3 * i);
+            Ei[i] += C->landau[0] * r2 + C->landau[1] * r2 * r2;
+        }
         /* short-range repulsion: half of each pair's energy to each atom */
         if (C->zbl) {
             const nlist_t *nl = &C->nl;
@@ -812,14 +823,16 @@ int or_neighbors(int n, const double *pos, const double *box, const int *pbc, do
 
 /* E = E_NEP (+ E_Zeeman reported separately); all outputs optional. zbl:
  * {Z_0, Z_1, r_inner, r_outer} of the short-range term, or NULL (off, also
- * when r_outer <= 0); E_NEP and E_i then include it. */
+ * when r_outer <= 0); landau: {a, b} of the onsite moment-length term, or
+ * NULL. E_NEP and E_i include both; H includes the latter. */
 int or_eval(int n, const int *type, const double *pos, const double *spin, const double *box,
             const int *pbc, const double *params, double rcR, double rcA, int act,
             double mu_s, const double *B, double *E_nep, double *E_z, double *Ei, double *F,
-            double *H, double *q_out, double *Fp_out, const double *zbl) {
+            double *H, double *q_out, double *Fp_out, const double *zbl, const double *landau) {
     ctx_t C;
     ctx_init(&C, n, type, pos, spin, box, pbc, params, rcR, rcA, act, n > 4096);
     if (zbl && zbl[3] > 0) C.zbl = zbl;
+    if (landau && (landau[0] != 0 || landau[1] != 0)) C.landau = landau;
     double *q = malloc(sizeof(double) * ND * (size_t)(n + 1));
     double *Fp = malloc(sizeof(double) * ND * (size_t)(n + 1));
     double *Ea = malloc(sizeof(double) * (n + 1));
@@ -876,12 +889,23 @@ typedef struct {
     double mass[2];
     /* short-range repulsion {Z_0, Z_1, r_inner, r_outer}; off when r_outer <= 0 */
     double zbl[4];
+    /* onsite moment-length term a |s|^2 + b |s|^4 on spin carriers (off when
+     * both are 0), and the moment-length (longitudinal) fluctuations: lsf = 1
+     * replaces the transverse bath (alpha unused) by the Langevin dynamics
+     * ds/dt = (h x s)/hbar + (lsf_gamma/hbar) h + noise, whose damping and
+     * noise also change |s| */
+    double landau[2];
+    int lsf;
+    double lsf_gamma;
 } or_step_params;
 
 typedef struct {
     double step, E_nep, E_kin, E_z, T_lat, T_spin, M[3];
     double passes;   /* sweeps of the spin step (predictor + correctors)      */
     double change;   /* max |g - x| of its last pass                         */
+    double capped;   /* spin rotations of the step's last pass that stopped at
+                        mid_cap without meeting mid_tol                      */
+    double s_len;    /* mean |s| over the spin carriers                       */
 } or_obs;
 
 /* Anderson mixing (type II) for a fixed point x = g(x) of dimension n.
@@ -970,9 +994,15 @@ static void hlin_fixed(const ctx_t *C, const double *Fps, int i, double h[3]) {
     for (int a = 0; a < 3; a++) h[a] = -h[a];
 }
 
-/* -d/ds_i of the terms linear in s_i, evaluated at x */
+/* -d/ds_i of the terms in s_i alone (onsite and single-ion channels, which
+ * the frozen Fp makes quadratic, and the exact onsite moment-length term),
+ * evaluated at x */
 static void hlin_self(const ctx_t *C, const double *Fps, int i, const double *x, double h[3]) {
     for (int a = 0; a < 3; a++) h[a] = -2.0 * Fps[(size_t)ND * i + D_OS] * x[a];
+    if (C->landau) {
+        double k = 2.0 * C->landau[0] + 4.0 * C->landau[1] * dot3(x, x);
+        for (int a = 0; a < 3; a++) h[a] -= k * x[a];
+    }
     nb_t *e;
     int m = env_get(C, i, &e);
     for (int t = 0; t < m; t++) {
@@ -983,18 +1013,25 @@ static void hlin_self(const ctx_t *C, const double *Fps, int i, const double *x,
     env_put(C, i, e);
 }
 
-/* one implicit-midpoint Rodrigues rotation of spin i over time tau */
-static void rotate_spin(const ctx_t *C, const double *Fps, int i, double tau, const double *Bext,
-                        const double *eta, const or_step_params *sp, double *snew) {
-    const double *s = C->spin + 3 * i;
-    double hfix[3];
-    hlin_fixed(C, Fps, i, hfix);
+/* one implicit-midpoint Rodrigues rotation of spin s over time tau: the
+ * midpoint equation y = G(y), G(y) the rotation of s about the precession
+ * vector taken at the midpoint m of s and y (direction of s + y, length
+ * |s|), solved by plain iteration until max|G(y) - y| <= mid_tol or mid_cap
+ * evaluations; returns the last G(y) and sets *capped when the tolerance was
+ * not met */
+static void midpoint_rotation(const ctx_t *C, const double *Fps, int i, const double *s, const double *hfix,
+                              double tau, const double *Bext, const double *eta, const or_step_params *sp,
+                              double *out, int *capped) {
     double y[3] = {s[0], s[1], s[2]}, yn[3];
-    double al = sp->alpha;
+    double al = sp->lsf ? 0.0 : sp->alpha;
+    double len = sp->lsf ? sqrt(dot3(s, s)) : 1.0;
+    int conv = 0;
     for (int it = 0; it < sp->mid_cap; it++) {
         double xb[3] = {s[0] + y[0], s[1] + y[1], s[2] + y[2]};
         double nx = sqrt(dot3(xb, xb));
         for (int a = 0; a < 3; a++) xb[a] /= nx;
+        if (sp->lsf)
+            for (int a = 0; a < 3; a++) xb[a] *= len;
         double hs[3], h[3], xh[3], w[3];
         hlin_self(C, Fps, i, xb, hs);
         for (int a = 0; a < 3; a++) h[a] = hfix[a] + hs[a] + sp->mu_s * MUB * Bext[a] + eta[a];
@@ -1025,9 +1062,43 @@ static void rotate_spin(const ctx_t *C, const double *Fps, int i, double tau, co
             if (dd > diff) diff = dd;
             y[a] = yn[a];
         }
-        if (diff <= sp->mid_tol) break;
+        if (diff <= sp->mid_tol) { conv = 1; break; }
     }
-    for (int a = 0; a < 3; a++) snew[a] = y[a];
+    for (int a = 0; a < 3; a++) out[a] = y[a];
+    if (!conv) *capped += 1;
+}
+
+/* Longitudinal half step of the Langevin dynamics with moment-length
+ * fluctuations over time t: s += (gamma t / hbar) h(s) + sqrt(2 gamma kB T t / hbar) xi,
+ * h the full frozen-Fp field at s (neighbours, own channels, onsite
+ * moment-length term, Zeeman), xi three normals (Euler-Maruyama step of
+ * ds = (gamma/hbar) h dt + sqrt(2 gamma kB T / hbar) dW) */
+static void lsf_half(const ctx_t *C, const double *Fps, int i, double *s, const double *hfix, double t,
+                     const double *Bext, double T, const or_step_params *sp, uint64_t step, uint32_t stream) {
+    double hs[3], xi[3] = {0, 0, 0};
+    hlin_self(C, Fps, i, s, hs);
+    if (T > 0) normals3(sp->seed, (uint32_t)i, step, stream, xi);
+    double k = sp->lsf_gamma * t / HBAR, sig = sqrt(2.0 * sp->lsf_gamma * KB * T * t / HBAR);
+    for (int a = 0; a < 3; a++) s[a] += k * (hfix[a] + hs[a] + sp->mu_s * MUB * Bext[a]) + sig * xi[a];
+}
+
+/* The update of spin i for one visit of its colour (time tau): the implicit-
+ * midpoint rotation; with moment-length fluctuations, between two
+ * longitudinal half steps (noise streams 2 + 2 visit and 3 + 2 visit, visit 0
+ * on the ascending and 1 on the descending pass). */
+static void rotate_spin(const ctx_t *C, const double *Fps, int i, double tau, const double *Bext,
+                        const double *eta, const or_step_params *sp, double T, int visit, uint64_t step,
+                        double *snew, int *capped) {
+    double s[3] = {C->spin[3 * i], C->spin[3 * i + 1], C->spin[3 * i + 2]};
+    double hfix[3];
+    hlin_fixed(C, Fps, i, hfix);
+    if (sp->lsf && sp->lsf_gamma > 0) {
+        lsf_half(C, Fps, i, s, hfix, 0.5 * tau, Bext, T, sp, step, 2u + 2u * (uint32_t)visit);
+        midpoint_rotation(C, Fps, i, s, hfix, tau, Bext, eta, sp, snew, capped);
+        lsf_half(C, Fps, i, snew, hfix, 0.5 * tau, Bext, T, sp, step, 3u + 2u * (uint32_t)visit);
+    } else {
+        midpoint_rotation(C, Fps, i, s, hfix, tau, Bext, eta, sp, snew, capped);
+    }
 }
 
 static void wrap(int n, double *pos, const double *box, const int *pbc) {
@@ -1052,6 +1123,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
     double *Sh = malloc(sizeof(double) * 3 * (size_t)(n + 1));
     double *eta = calloc(3 * (size_t)(n + 1), sizeof(double));
     double *snew = malloc(sizeof(double) * 3 * (size_t)(n + 1));
+    int *cap_of = calloc((size_t)(n + 1), sizeof(int));
     /* self-consistent iteration: the iterate x (end-of-step spins whose
      * midpoint the pass uses) and, for the accelerated variant, the history */
     const int depth = sp->sc_tol > 0 && sp->sc_depth > 0 ? (sp->sc_depth < 8 ? sp->sc_depth : 8) : 0;
@@ -1074,6 +1146,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         for (int a = 0; a < 3; a++) B[a] = sp->B0[a] + (sp->B1[a] - sp->B0[a]) * frac;
         ctx_init(&C, n, type, pos, spin, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
         if (sp->zbl[3] > 0) C.zbl = sp->zbl;
+        if (sp->landau[0] != 0 || sp->landau[1] != 0) C.landau = sp->landau;
         forward_all(&C, q, Fp, Ei);
         forces_fields(&C, Fp, sp->mu_s, Bz, F, H);
         ctx_free(&C);
@@ -1100,11 +1173,11 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
                 for (int a = 0; a < 3; a++) vel[3 * i + a] = c1 * vel[3 * i + a] + sig * xi[a];
             }
         }
-        int passes = 0;
+        int passes = 0, capped = 0;
         double change = 0;
         /* S: spin step at R_mid (none for a structural-only model) */
         if (!sp->structural) {
-            double esig = (sp->alpha > 0 && T > 0) ? sqrt(2.0 * sp->alpha * KB * T * HBAR / dt) : 0.0;
+            double esig = (!sp->lsf && sp->alpha > 0 && T > 0) ? sqrt(2.0 * sp->alpha * KB * T * HBAR / dt) : 0.0;
             for (int i = 0; i < n; i++) {
                 double xi[3] = {0, 0, 0};
                 if (esig > 0 && type[i] == 0) normals3(sp->seed, (uint32_t)i, (uint64_t)st, 1, xi);
@@ -1119,29 +1192,35 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
             for (int pc = 0; pc <= last; pc++) {
                 /* Fp* at (R_mid, S_hat) */
                 ctx_init(&C, n, type, pos, Sh, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
+                if (sp->landau[0] != 0 || sp->landau[1] != 0) C.landau = sp->landau;
                 forward_all(&C, q, Fp, Ei);
                 /* restart from S^n; C.spin now holds the spins being swept */
                 memcpy(C.spin, Sn, sizeof(double) * 3 * n);
                 env_cache(&C);
+                capped = 0;
+                memset(cap_of, 0, sizeof(int) * (size_t)(n + 1));
                 for (int pass = 0; pass < 2; pass++) {
                     for (int cc = 0; cc < ncol; cc++) {
                         int c = pass == 0 ? cc : ncol - 1 - cc;
                         if (sp->sequential) {
                             for (int i = 0; i < n; i++)
                                 if (colour[i] == c) {
-                                    rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
+                                    rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, T, pass, (uint64_t)st,
+                                                snew + 3 * i, &capped);
                                     for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
                                 }
                         } else {
     #pragma omp parallel for schedule(dynamic, 8)
                             for (int i = 0; i < n; i++)
-                                if (colour[i] == c) rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, snew + 3 * i);
+                                if (colour[i] == c) rotate_spin(&C, Fp, i, 0.5 * dt, B, eta + 3 * i, sp, T, pass,
+                                                                (uint64_t)st, snew + 3 * i, &cap_of[i]);
                             for (int i = 0; i < n; i++)
                                 if (colour[i] == c)
                                     for (int a = 0; a < 3; a++) C.spin[3 * i + a] = snew[3 * i + a];
                         }
                     }
                 }
+                for (int i = 0; i < n; i++) capped += cap_of[i];
                 passes = pc + 1;
                 /* residual of the pass: g - x, with g the swept spins (for the
                  * plain iteration x is the previous pass's g, S^n for the first) */
@@ -1193,7 +1272,8 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
                     double m[3], nn;
                     for (int a = 0; a < 3; a++) m[a] = 0.5 * (Sn[3 * i + a] + X[3 * i + a]);
                     nn = sqrt(dot3(m, m));
-                    for (int a = 0; a < 3; a++) Sh[3 * i + a] = m[a] / nn;
+                    /* with moment-length fluctuations the plain average */
+                    for (int a = 0; a < 3; a++) Sh[3 * i + a] = sp->lsf ? m[a] : m[a] / nn;
                 }
             }
         }
@@ -1204,6 +1284,7 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
         /* full evaluation at (R^{n+1}, S^{n+1}) */
         ctx_init(&C, n, type, pos, spin, box, pbc, params, sp->rcR, sp->rcA, sp->act, use_cells);
         if (sp->zbl[3] > 0) C.zbl = sp->zbl;
+        if (sp->landau[0] != 0 || sp->landau[1] != 0) C.landau = sp->landau;
         double E = forward_all(&C, q, Fp, Ei);
         forces_fields(&C, Fp, sp->mu_s, B, F, H);
         double Ez = zeeman(&C, sp->mu_s, B);
@@ -1236,10 +1317,15 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
             for (int a = 0; a < 3; a++) o->M[a] = nfe ? M[a] / nfe : 0.0;
             o->passes = passes;
             o->change = change;
+            o->capped = capped;
+            double sl = 0;
+            for (int i = 0; i < n; i++)
+                if (type[i] == 0) sl += sqrt(dot3(spin + 3 * i, spin + 3 * i));
+            o->s_len = nfe ? sl / nfe : 0.0;
         }
     }
     free(q); free(Fp); free(Ei); free(F); free(H); free(Sn); free(Sh); free(eta); free(snew);
-    free(X); free(fk); free(gk); free(fprev); free(gprev); free(xnew); free(dF); free(dG);
+    free(X); free(fk); free(gk); free(fprev); free(gprev); free(xnew); free(dF); free(dG); free(cap_of);
     return 0;
 }
 

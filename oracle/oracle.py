@@ -75,13 +75,15 @@ class StepParams(ct.Structure):
                 ("seed", ct.c_uint64), ("ensemble", ct.c_int), ("K_corr", ct.c_int),
                 ("mid_cap", ct.c_int), ("act", ct.c_int), ("sequential", ct.c_int), ("sc_max", ct.c_int),
                 ("sc_tol", ct.c_double), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double),
-                ("structural", ct.c_int), ("mass", ct.c_double * 2), ("zbl", ct.c_double * 4)]
+                ("structural", ct.c_int), ("mass", ct.c_double * 2), ("zbl", ct.c_double * 4),
+                ("landau", ct.c_double * 2), ("lsf", ct.c_int), ("lsf_gamma", ct.c_double)]
 
 
 class Obs(ct.Structure):
     _fields_ = [("step", ct.c_double), ("E_nep", ct.c_double), ("E_kin", ct.c_double),
                 ("E_z", ct.c_double), ("T_lat", ct.c_double), ("T_spin", ct.c_double),
-                ("M", ct.c_double * 3), ("passes", ct.c_double), ("change", ct.c_double)]
+                ("M", ct.c_double * 3), ("passes", ct.c_double), ("change", ct.c_double),
+                ("capped", ct.c_double), ("s_len", ct.c_double)]
 
 
 _lib = None
@@ -95,7 +97,7 @@ def lib():
         L = ct.CDLL(LIB_PATH)
         P = ct.c_void_p
         L.or_eval.argtypes = [ct.c_int, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
-                              ct.c_double, P, P, P, P, P, P, P, P, P]
+                              ct.c_double, P, P, P, P, P, P, P, P, P, P]
         L.or_neighbors.argtypes = [ct.c_int, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
         L.or_philox.argtypes = [P, P, P]
         L.or_field_lin.argtypes = [ct.c_int, P, P, P, P, P, P, P, ct.c_double, ct.c_double, ct.c_int,
@@ -146,11 +148,12 @@ def _zbl(zbl):
 
 
 def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0), act=0,
-             rcR=RC_R, rcA=RC_A, want=("E", "F", "H"), zbl=None):
+             rcR=RC_R, rcA=RC_A, want=("E", "F", "H"), zbl=None, landau=None):
     """Energy, forces, fields (and optionally q, Fp, per-atom E) of one system;
     params of the spin-aware model, or of the structural-only one (spins are
     then ignored, and q / Fp keep the first 37 columns). zbl = (Z_0, Z_1,
-    r_inner, r_outer) adds the short-range repulsion to E and E_i."""
+    r_inner, r_outer) adds the short-range repulsion to E and E_i; landau =
+    (a, b) the onsite moment-length term a|s|^2 + b|s|^4 of spin carriers."""
     types = _i32(types)
     pos = _f64(pos)
     n = types.shape[0]
@@ -166,7 +169,7 @@ def evaluate(types, pos, spin, box, pbc, params, *, mu_s=1.0, B=(0.0, 0.0, 0.0),
     Fp = np.zeros((n, N_DESC)) if "Fp" in want else None
     lib().or_eval(n, _p(types), _p(pos), _p(spin), _p(_f64(box)), _p(_i32(pbc)), _p(_f64(params)),
                   rcR, rcA, act, mu_s, _p(_f64(B)), _p(E), _p(Ez), _p(Ei), _p(F), _p(H), _p(q), _p(Fp),
-                  _p(_zbl(zbl)))
+                  _p(_zbl(zbl)), _p(None if landau is None else _f64(landau)))
     out["E"] = float(E[0])
     out["Ez"] = float(Ez[0])
     for k, v in (("Ei", Ei), ("F", F), ("H", H), ("q", q), ("Fp", Fp)):
@@ -214,8 +217,13 @@ def normals(seed, atom, step, stream):
 def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, gammaL=0.0,
                 mu_s=1.0, mid_tol=1e-15, mid_cap=50, n_ramp=0, seed=0x5EED, ensemble=0,
                 K_corr=1, act=0, sequential=0, rcR=RC_R, rcA=RC_A, sc_tol=0.0, sc_max=30, sc_depth=0,
-                sc_reg=1e-10, structural=0, mass=(0.0, 0.0), zbl=None) -> StepParams:
+                sc_reg=1e-10, structural=0, mass=(0.0, 0.0), zbl=None, landau=None, lsf=0,
+                lsf_gamma=0.0) -> StepParams:
     sp = StepParams()
+    if landau is not None:
+        sp.landau[0], sp.landau[1] = landau
+    sp.lsf = lsf
+    sp.lsf_gamma = lsf_gamma
     if zbl is not None:
         for a in range(4):
             sp.zbl[a] = zbl[a]
@@ -249,7 +257,8 @@ def step_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha=0.0, ga
 
 def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps, step0=0):
     """n_steps of the spin-lattice step; returns (pos, vel, spin, step, obs[n_steps]), obs columns
-    step, E_nep, E_kin, E_z, T_lattice, T_spin, M[3], sweep passes, last change."""
+    step, E_nep, E_kin, E_z, T_lattice, T_spin, M[3], sweep passes, last change, rotations
+    stopped at the cap, mean |s|."""
     types = _i32(types)
     n = types.shape[0]
     params, spin, structural = _model(params, spin, n)
@@ -265,6 +274,6 @@ def run(types, pos, vel, spin, box, pbc, params, colour, sp: StepParams, n_steps
     lib().or_run(types.shape[0], _p(types), _p(pos), _p(vel), _p(spin), _p(_f64(box)), _p(_i32(pbc)),
                  _p(_f64(params)), _p(colour), ncol, ct.byref(sp), ct.byref(st), n_steps,
                  ct.cast(obs, ct.c_void_p))
-    ob = np.array([[o.step, o.E_nep, o.E_kin, o.E_z, o.T_lat, o.T_spin, o.M[0], o.M[1], o.M[2], o.passes, o.change]
-                   for o in obs[:n_steps]]).reshape(n_steps, 11)
+    ob = np.array([[o.step, o.E_nep, o.E_kin, o.E_z, o.T_lat, o.T_spin, o.M[0], o.M[1], o.M[2], o.passes, o.change,
+                    o.capped, o.s_len] for o in obs[:n_steps]]).reshape(n_steps, 13)
     return pos, vel, spin, st.value, ob

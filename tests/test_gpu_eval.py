@@ -132,7 +132,7 @@ def test_eval_short_range_fp64_matches_oracle(model_sr, oracle, case):
     B = (0.1, 0.3, -0.2)
     targets = (0.7, 0.95, 1.05, 1.3, 1.5, 1.75, 1.95, 2.05)
     if case == "crystal":
-        s = W.fege_lattice(4, 4, 4, noise=0.3, seed=5)
+        s = W.fege_lattice(4, 4, 4, noise=0.05, seed=5)
         pos, box = s.pos, s.box
     elif case == "close_pairs":
         s = W.fege_lattice(4, 4, 4, seed=3)

@@ -673,6 +673,138 @@ def test_nve_energy_drift(oracle):
 
 
 # --------------------------------------------------------------------------
+# Moment-length (longitudinal) fluctuations: the onsite term a|s|^2 + b|s|^4
+# and the Langevin dynamics ds/dt = (h x s)/hbar + (gamma/hbar) h + noise
+# --------------------------------------------------------------------------
+
+LANDAU = (-1.0, 0.5)     # a, b (eV): minimum at |s| = 1, curvature 8b = 4 eV there
+
+
+def _isolated_spins(n, spacing=8.0, seed=9, lengths=None):
+    rng = np.random.default_rng(seed)
+    g = np.arange(n)
+    pos = np.stack([g % 10, (g // 10) % 10, g // 100], axis=1) * spacing + 5.0
+    spin = rng.normal(size=(n, 3))
+    spin /= np.linalg.norm(spin, axis=1, keepdims=True)
+    if lengths is not None:
+        spin *= np.asarray(lengths)[:, None]
+    return pos, spin
+
+
+def test_landau_term_energy_and_field(oracle):
+    """Zero model: an isolated spin of length r has E = a r^2 + b r^4 and
+    field -(2a + 4b r^2) s + mu_s mu_B B. With the random model on a cluster,
+    central differences of E in s (spins of several lengths) give the field."""
+    a, b = LANDAU
+    box = np.array([500.0] * 3)
+    for r in (0.6, 1.0, 1.37):
+        s = np.array([[0.36, -0.48, 0.8]]) * r
+        o = oracle.evaluate([0], [[10.0, 10, 10]], s, box, np.zeros(3, np.int32), np.zeros(15438), B=(0, 0, 2.0),
+                            landau=LANDAU, want=("E", "H"))
+        assert o["E"] == pytest.approx(a * r * r + b * r ** 4, rel=1e-14)
+        want = -(2 * a + 4 * b * r * r) * s[0] + np.array([0, 0, 2.0 * MUB])
+        np.testing.assert_allclose(o["H"][0], want, rtol=1e-14, atol=1e-16)
+    st = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
+    rng = np.random.default_rng(3)
+    spin = st.spin * rng.uniform(0.7, 1.3, (st.n, 1))
+    p = W.random_params()
+    ref = oracle.evaluate(st.types, st.pos + 100, spin, box, st.pbc, p, B=(0.1, 0.2, 0.3), landau=LANDAU)
+    Hmax = np.abs(ref["H"]).max()
+    for i in np.nonzero(st.types == 0)[0][::3]:
+        for x in range(3):
+            h = 1e-6
+            sp_ = spin.copy(); sp_[i, x] += h
+            ep = oracle.evaluate(st.types, st.pos + 100, sp_, box, st.pbc, p, B=(0.1, 0.2, 0.3), landau=LANDAU,
+                                 want=())
+            sp_[i, x] -= 2 * h
+            em = oracle.evaluate(st.types, st.pos + 100, sp_, box, st.pbc, p, B=(0.1, 0.2, 0.3), landau=LANDAU,
+                                 want=())
+            fd = -((ep["E"] + ep["Ez"]) - (em["E"] + em["Ez"])) / (2 * h)
+            assert abs(fd - ref["H"][i, x]) <= 1e-6 * Hmax
+
+
+def test_lsf_no_damping_keeps_lengths_and_is_reversible(oracle):
+    """Without damping (gamma = 0) only the rotations act: every spin keeps
+    its own length (not 1) to rounding over 150 steps; with the linear
+    read-out the step is time-reversible (n steps with dt, then n with -dt)."""
+    s = W.fege_lattice(2, 2, 2, pbc=(0, 0, 0), noise=0.05)
+    rng = np.random.default_rng(5)
+    lens = np.where(s.types == 0, rng.uniform(0.8, 1.25, s.n), 0.0)
+    spin0 = s.spin * lens[:, None]
+    p = W.random_params()
+    box = np.array([500.0] * 3)
+    v0 = W.maxwell_boltzmann(s.types, 300.0)
+    sp = oracle.step_params(dt=1.0, B0=(0, 0, 2.0), landau=LANDAU, lsf=1, lsf_gamma=0.0)
+    _, _, spin, _, ob = oracle.run(s.types, s.pos + 100, v0, spin0, box, s.pbc, p, s.colour, sp, 150)
+    fe = s.types == 0
+    assert np.abs(np.linalg.norm(spin[fe], axis=1) - lens[fe]).max() <= 1e-13
+    assert ob[-1, 12] == pytest.approx(lens[fe].mean(), rel=1e-13)
+    n = 6
+    spf = oracle.step_params(dt=1.0, act=1, B0=(0, 0, 5.0), landau=LANDAU, lsf=1)
+    spb = oracle.step_params(dt=-1.0, act=1, B0=(0, 0, 5.0), landau=LANDAU, lsf=1)
+    pos, vel, spin, _, _ = oracle.run(s.types, s.pos + 100, v0, spin0, box, s.pbc, p, s.colour, spf, n)
+    pos, vel, spin, _, _ = oracle.run(s.types, pos, vel, spin, box, s.pbc, p, s.colour, spb, n)
+    assert np.abs(pos - (s.pos + 100)).max() <= 1e-10
+    assert np.abs(vel - v0).max() <= 1e-10
+    assert np.abs(spin - spin0).max() <= 1e-10
+
+
+def test_lsf_relaxes_to_landau_minimum(oracle):
+    """Zero model, no field, T = 0: the damping term (gamma/hbar) h drives
+    every isolated spin's length to the minimum sqrt(-a/2b) of the onsite
+    term, along its own direction."""
+    a, b = -1.3, 0.4
+    n = 20
+    pos, spin = _isolated_spins(n, lengths=np.linspace(0.5, 2.0, n))
+    sp = oracle.step_params(dt=1.0, landau=(a, b), lsf=1, lsf_gamma=0.2)
+    _, _, s_out, _, _ = oracle.run(np.zeros(n, np.int32), pos, np.zeros((n, 3)), spin, np.array([1e3] * 3),
+                                   np.zeros(3, np.int32), np.zeros(15438), np.zeros(n, np.int32), sp, 400)
+    r = np.linalg.norm(s_out, axis=1)
+    np.testing.assert_allclose(r, math.sqrt(-a / (2 * b)), rtol=1e-9)
+    np.testing.assert_allclose(s_out / r[:, None], spin / np.linalg.norm(spin, axis=1)[:, None], atol=1e-12)
+
+
+@pytest.mark.slow
+def test_lsf_equilibrium_distribution(oracle):
+    """Isolated spins at temperature T in a field B with the onsite term: the
+    dynamics samples P(s) ~ exp(-(a|s|^2 + b|s|^4 - mu_s mu_B B.s)/kB T) over
+    vectors s (the |s|^2 Jacobian included); <|s|>, <|s|^2> and <s.B^> against
+    two-dimensional quadrature of that density."""
+    from scipy import integrate
+    a, b = LANDAU
+    n, T, Bz = 500, 300.0, 400.0
+    kT, h = KB * T, MUB * Bz
+    pos, spin = _isolated_spins(n, seed=13)
+    sp = oracle.step_params(dt=1.0, T0=T, B0=(0, 0, Bz), landau=LANDAU, lsf=1, lsf_gamma=0.03)
+    types, col, box = np.zeros(n, np.int32), np.zeros(n, np.int32), np.array([1e4] * 3)
+    pos_, vel, spin, st, _ = oracle.run(types, pos, np.zeros((n, 3)), spin, box, np.zeros(3, np.int32),
+                                        np.zeros(15438), col, sp, 600)
+    r1, r2, mz = [], [], []
+    for _ in range(12):
+        pos_, vel, spin, st, _ = oracle.run(types, pos_, vel, spin, box, np.zeros(3, np.int32), np.zeros(15438),
+                                            col, sp, 150, step0=st)
+        r = np.linalg.norm(spin, axis=1)
+        r1.append(r.mean())
+        r2.append((r * r).mean())
+        mz.append(spin[:, 2].mean())
+
+    def mom(f):
+        w = lambda c, r: r * r * np.exp(-(a * r * r + b * r ** 4 + 0.5 - h * r * c) / kT)
+        num = integrate.dblquad(lambda c, r: f(c, r) * w(c, r), 0.2, 2.0, -1, 1, epsabs=1e-12)[0]
+        den = integrate.dblquad(w, 0.2, 2.0, -1, 1, epsabs=1e-12)[0]
+        return num / den
+    want = (mom(lambda c, r: r), mom(lambda c, r: r * r), mom(lambda c, r: r * c))
+    got = (np.mean(r1), np.mean(r2), np.mean(mz))
+    err = [np.std(x) / math.sqrt(len(x)) for x in (r1, r2, mz)]
+    print("lsf equilibrium: got", got, "want", want, "stderr", err)
+    # moment-length moments: statistical error plus the step's O(gamma dt) bias
+    assert abs(got[0] - want[0]) < 4 * err[0] + 1.5e-3
+    assert abs(got[1] - want[1]) < 4 * err[1] + 3e-3
+    # orientation: the Langevin function of x = mu_s mu_B B <|s|> / kB T
+    assert abs(got[2] - want[2]) < 4 * err[2] + 0.01
+
+
+# --------------------------------------------------------------------------
 # P14: thermostats against equilibrium statistics
 # --------------------------------------------------------------------------
 
