@@ -186,6 +186,25 @@ int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision pr
 int nep_spin_descriptors(const nep_model *m, const sl_system_view *sys, sl_precision prec,
                          double *q, double *Fp, const sl_exec *ex);
 
+/* nep_spin_eval for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with every device buffer the evaluation needs
+ * (state, neighbour lists, cells, descriptor/gradient work arrays,
+ * reductions) carved from one static scratch array of 64 MiB that each GPU
+ * the library runs on holds until the process ends. No hipMalloc, hipFree,
+ * stream or event is created; work runs on ex->hip_stream (NULL: the null
+ * stream) and the call returns after the results are in place.
+ * Limit: the system must fit the 64 MiB, about 5,000 atoms in FP64 and 8,000
+ * in FP32-mixed (dense crystal, about 13 and 8 KB per atom); a larger one
+ * returns SL_E_OOM before any device work. Every call on one GPU shares its
+ * array, which keeps the last call's contents (what must start at zero is
+ * cleared on each call), so two calls that overlapped on one GPU would race:
+ * the library serialises them within a process (each process has its own
+ * array). Same arguments, outputs and other errors as nep_spin_eval. */
+int nep_spin_eval_noalloc(const nep_model *m, const sl_system_view *sys, sl_precision prec,
+                          double *energy, double *energy_atom, double *force, double *field,
+                          const sl_exec *ex);
+
 /* ---------------------------------------------------------------------- */
 /* Spin-lattice integration                                               */
 /* ---------------------------------------------------------------------- */

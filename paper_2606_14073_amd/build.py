@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnepspin.so")
 
-SOURCES = ["kernels_nlist.hip", "kernels_nep.hip", "kernels_int.hip", "engine.cpp"]
+SOURCES = ["kernels_nlist.hip", "kernels_nep.hip", "kernels_int.hip", "scratch.hip", "engine.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "nepspin.h"
+#include "scratch.h"
 
 using namespace nep;
 
@@ -183,6 +184,31 @@ extern "C" size_t sl_replica_bytes(int64_t n_atoms, sl_precision prec) {
 }
 
 struct Engine {
+    // Device arrays come from hipMalloc, or, when `arena` is set, are carved
+    // in order from that caller-provided region (never freed here; the stream
+    // is then the caller's, no stream or event is created).
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    template <typename T>
+    int get(T **p, size_t n) {
+        if (!arena) return dalloc(p, n);
+        if (n == 0) n = 1;
+        const size_t bytes = (n * sizeof(T) + 255) & ~(size_t)255;
+        if (arena_used + bytes > arena_cap) {
+            *p = nullptr;
+            return fail(SL_E_OOM, "system too large for the static scratch area (" + std::to_string(arena_cap >> 20) +
+                                      " MiB per GPU): use nep_spin_eval");
+        }
+        *p = reinterpret_cast<T *>(arena + arena_used);
+        arena_used += bytes;
+        return SL_OK;
+    }
+    template <typename T>
+    void put(T *&p) {
+        if (!arena) dfree(p);
+        p = nullptr;
+    }
+
     nep_model *M = nullptr;
     sl_precision prec = SL_FP64;
     int K_corr = 1;
@@ -272,16 +298,16 @@ struct Engine {
     ~Engine() { release(); }
 
     void release() {
-        dfree(rid); dfree(orig); dfree(colour); dfree(rep);
-        dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
-        dfree(spin_n); dfree(spin_hat); dfree(eta);
-        dfree(sc_x); dfree(sc_f); dfree(sc_g); dfree(sc_dF); dfree(sc_dG); dfree(sc_part); dfree(sc_out);
-        dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
-        dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
-        dfree(cell_of); dfree(cell_cnt); dfree(cell_start); dfree(cell_fill); dfree(cell_atoms);
-        dfree(flags); dfree(chunks); dfree(chunk_ptr); dfree(col_idx); dfree(colpos); dfree(col_rid); dfree(cpl_j); dfree(cpl_n);
-        dfree(partial); dfree(obs);
-        if (work) (void)hipFree(work);
+        put(rid); put(orig); put(colour); put(rep);
+        put(pos); put(vel); put(spin); put(force); put(field); put(pos_ref);
+        put(spin_n); put(spin_hat); put(eta);
+        put(sc_x); put(sc_f); put(sc_g); put(sc_dF); put(sc_dG); put(sc_part); put(sc_out);
+        put(nbrR); put(cntR); put(cntFeR); put(revR);
+        put(nbrA); put(cntA); put(cntFeA); put(revA); put(a2r);
+        put(cell_of); put(cell_cnt); put(cell_start); put(cell_fill); put(cell_atoms);
+        put(flags); put(chunks); put(chunk_ptr); put(col_idx); put(colpos); put(col_rid); put(cpl_j); put(cpl_n);
+        put(partial); put(obs);
+        if (work && !arena) (void)hipFree(work);
         work = nullptr;
         cap = cap_fe = cap_cells = cap_rep = cap_chunks = cap_obs = cap_col = 0;
         for (auto e : prof_pool) (void)hipEventDestroy(e);
@@ -318,7 +344,7 @@ struct Engine {
     }
 
     int ensure_stream() {
-        if (!st) {
+        if (!st && !arena) {
             HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
             own_stream = true;
         }
@@ -361,77 +387,86 @@ struct Engine {
     int reserve(size_t n, size_t nfe, size_t ncell, size_t nrep, size_t nchunk) {
         int rc;
         if (n > cap || nfe > cap_fe) {
-            size_t c = std::max(n, cap + cap / 4), cf = std::max(nfe, cap_fe + cap_fe / 4);
+            // headroom for later growth, except in a fixed scratch area
+            size_t c = arena ? n : std::max(n, cap + cap / 4), cf = arena ? nfe : std::max(nfe, cap_fe + cap_fe / 4);
             c = std::max<size_t>(c, 64);
             cf = std::max<size_t>(cf, 64);
-            dfree(rid); dfree(orig); dfree(colour);
-            dfree(pos); dfree(vel); dfree(spin); dfree(force); dfree(field); dfree(pos_ref);
-            dfree(spin_n); dfree(spin_hat); dfree(eta);
-            dfree(sc_x); dfree(sc_f); dfree(sc_g); dfree(sc_dF); dfree(sc_dG); dfree(sc_part);
-            dfree(nbrR); dfree(cntR); dfree(cntFeR); dfree(revR);
-            dfree(nbrA); dfree(cntA); dfree(cntFeA); dfree(revA); dfree(a2r);
-            dfree(cell_of); dfree(cell_atoms); dfree(cpl_j); dfree(cpl_n);
-            if (work) (void)hipFree(work);
+            put(rid); put(orig); put(colour);
+            put(pos); put(vel); put(spin); put(force); put(field); put(pos_ref);
+            put(spin_n); put(spin_hat); put(eta);
+            put(sc_x); put(sc_f); put(sc_g); put(sc_dF); put(sc_dG); put(sc_part);
+            put(nbrR); put(cntR); put(cntFeR); put(revR);
+            put(nbrA); put(cntA); put(cntFeA); put(revA); put(a2r);
+            put(cell_of); put(cell_atoms); put(cpl_j); put(cpl_n);
+            if (work && !arena) (void)hipFree(work);
             work = nullptr;
             cap = cap_fe = 0;
-            if ((rc = dalloc(&rid, c)) || (rc = dalloc(&orig, c)) || (rc = dalloc(&colour, c)) ||
-                (rc = dalloc(&pos, c)) || (rc = dalloc(&vel, c)) || (rc = dalloc(&spin, c)) ||
-                (rc = dalloc(&force, c)) || (rc = dalloc(&field, c)) || (rc = dalloc(&pos_ref, c)) ||
-                (rc = dalloc(&spin_n, c)) || (rc = dalloc(&spin_hat, c)) || (rc = dalloc(&eta, c)) ||
-                (rc = dalloc(&nbrR, (size_t)MAXR * c)) || (rc = dalloc(&cntR, c)) || (rc = dalloc(&cntFeR, c)) ||
-                (rc = dalloc(&revR, (size_t)MAXR * c)) || (rc = dalloc(&nbrA, (size_t)MAXA * c)) ||
-                (rc = dalloc(&cntA, c)) || (rc = dalloc(&cntFeA, c)) || (rc = dalloc(&revA, (size_t)MAXA * c)) ||
-                (rc = dalloc(&a2r, (size_t)MAXA * c)) || (rc = dalloc(&cell_of, c)) ||
-                (rc = dalloc(&cell_atoms, c)) || (rc = dalloc(&cpl_j, (size_t)MAXFE * cf)) ||
-                (rc = dalloc(&cpl_n, cf)) || (rc = dalloc(&sc_x, cf)))
+            if ((rc = get(&rid, c)) || (rc = get(&orig, c)) || (rc = get(&colour, c)) ||
+                (rc = get(&pos, c)) || (rc = get(&vel, c)) || (rc = get(&spin, c)) ||
+                (rc = get(&force, c)) || (rc = get(&field, c)) || (rc = get(&pos_ref, c)) ||
+                (rc = get(&spin_n, c)) || (rc = get(&spin_hat, c)) || (rc = get(&eta, c)) ||
+                (rc = get(&nbrR, (size_t)MAXR * c)) || (rc = get(&cntR, c)) || (rc = get(&cntFeR, c)) ||
+                (rc = get(&revR, (size_t)MAXR * c)) || (rc = get(&nbrA, (size_t)MAXA * c)) ||
+                (rc = get(&cntA, c)) || (rc = get(&cntFeA, c)) || (rc = get(&revA, (size_t)MAXA * c)) ||
+                (rc = get(&a2r, (size_t)MAXA * c)) || (rc = get(&cell_of, c)) ||
+                (rc = get(&cell_atoms, c)) || (rc = get(&cpl_j, (size_t)MAXFE * cf)) ||
+                (rc = get(&cpl_n, cf)) || (rc = get(&sc_x, cf)))
                 return rc;
             if (sc_tol > 0 && sc_depth > 0 &&
-                ((rc = dalloc(&sc_f, cf)) || (rc = dalloc(&sc_g, cf)) || (rc = dalloc(&sc_dF, (size_t)sc_depth * cf)) ||
-                 (rc = dalloc(&sc_dG, (size_t)sc_depth * cf)) ||
-                 (rc = dalloc(&sc_part, (size_t)sc_part_blocks((int)cf) * SC_NK))))
+                ((rc = get(&sc_f, cf)) || (rc = get(&sc_g, cf)) || (rc = get(&sc_dF, (size_t)sc_depth * cf)) ||
+                 (rc = get(&sc_dG, (size_t)sc_depth * cf)) ||
+                 (rc = get(&sc_part, (size_t)sc_part_blocks((int)cf) * SC_NK))))
                 return rc;
             const size_t rs = prec == SL_FP64 ? 8 : 4;
             work_bytes = work_count(c, cf) * rs;
-            hipError_t e = hipMalloc(&work, work_bytes);
-            if (e != hipSuccess) {
-                work = nullptr;
-                (void)hipGetLastError();
-                return fail(SL_E_OOM, "hipMalloc of work arrays failed");
+            if (arena) {
+                char *w = nullptr;
+                if ((rc = get(&w, work_bytes))) return rc;
+                work = w;
+                HIPCHK(hipMemsetAsync(work, 0, work_bytes, st));
+            } else {
+                hipError_t e = hipMalloc(&work, work_bytes);
+                if (e != hipSuccess) {
+                    work = nullptr;
+                    (void)hipGetLastError();
+                    return fail(SL_E_OOM, "hipMalloc of work arrays failed");
+                }
+                HIPCHK(hipMemset(work, 0, work_bytes));
             }
-            HIPCHK(hipMemset(work, 0, work_bytes));
             cap = c;
             cap_fe = cf;
             if (prec == SL_FP64) carve(w64, c, cf);
             else carve(w32, c, cf);
         }
         if (ncell > cap_cells) {
-            dfree(cell_cnt); dfree(cell_start); dfree(cell_fill);
+            put(cell_cnt); put(cell_start); put(cell_fill);
             size_t c = std::max(ncell, cap_cells + cap_cells / 4);
-            if ((rc = dalloc(&cell_cnt, c)) || (rc = dalloc(&cell_start, c)) || (rc = dalloc(&cell_fill, c))) return rc;
+            if ((rc = get(&cell_cnt, c)) || (rc = get(&cell_start, c)) || (rc = get(&cell_fill, c))) return rc;
             cap_cells = c;
         }
         if (nrep > cap_rep) {
-            dfree(rep); dfree(chunk_ptr); dfree(obs);
+            put(rep); put(chunk_ptr); put(obs);
             size_t c = std::max<size_t>(nrep, 2 * cap_rep);
-            if ((rc = dalloc(&rep, c)) || (rc = dalloc(&chunk_ptr, c + 1))) return rc;
+            if ((rc = get(&rep, c)) || (rc = get(&chunk_ptr, c + 1))) return rc;
             cap_rep = c;
             cap_obs = 0;
         }
         if (nchunk > cap_chunks) {
-            dfree(chunks); dfree(partial);
+            put(chunks); put(partial);
             size_t c = std::max(nchunk, 2 * cap_chunks);
-            if ((rc = dalloc(&chunks, c)) || (rc = dalloc(&partial, c * NOBS))) return rc;
+            if ((rc = get(&chunks, c)) || (rc = get(&partial, c * NOBS))) return rc;
             cap_chunks = c;
         }
         if (!flags) {
-            if ((rc = dalloc(&flags, NFLAGS)) || (rc = dalloc(&sc_out, SC_OUT))) return rc;
-            HIPCHK(hipMemset(flags, 0, NFLAGS * sizeof(int)));
+            if ((rc = get(&flags, NFLAGS)) || (rc = get(&sc_out, SC_OUT))) return rc;
+            HIPCHK(hipMemsetAsync(flags, 0, NFLAGS * sizeof(int), st));
+            HIPCHK(hipStreamSynchronize(st));
         }
         if (!col_idx || cap_col < cap_fe) {
-            dfree(col_idx);
-            dfree(colpos);
-            dfree(col_rid);
-            if ((rc = dalloc(&col_idx, cap_fe)) || (rc = dalloc(&colpos, cap_fe)) || (rc = dalloc(&col_rid, cap_fe)))
+            put(col_idx);
+            put(colpos);
+            put(col_rid);
+            if ((rc = get(&col_idx, cap_fe)) || (rc = get(&colpos, cap_fe)) || (rc = get(&col_rid, cap_fe)))
                 return rc;
             cap_col = cap_fe;
         }
@@ -441,8 +476,8 @@ struct Engine {
     int ensure_obs(size_t nsteps) {
         size_t need = std::max<size_t>(nsteps, 1) * std::max<size_t>(reps.size(), 1) * NOBS;
         if (need > cap_obs) {
-            dfree(obs);
-            int rc = dalloc(&obs, need);
+            put(obs);
+            int rc = get(&obs, need);
             if (rc) return rc;
             cap_obs = need;
         }
@@ -508,7 +543,7 @@ struct Engine {
                 if (p) (void)hipFree(p);
             }
         } staging;
-        if (stage_n && hipMalloc((void **)&staging.p, 5 * stage_n * sizeof(d4)) != hipSuccess) {
+        if (stage_n && !arena && hipMalloc((void **)&staging.p, 5 * stage_n * sizeof(d4)) != hipSuccess) {
             (void)hipGetLastError();
             staging.p = nullptr;
         }
@@ -1321,24 +1356,23 @@ static int eval_common(const nep_model *mc, const sl_system_view *sys, sl_precis
     return e->check_flags();
 }
 
-extern "C" int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec, double *energy,
-                             double *energy_atom, double *force, double *field, const sl_exec *ex) {
-    if (!m) return fail(SL_E_INVALID, "model is NULL");
-    std::lock_guard<std::mutex> lk(const_cast<nep_model *>(m)->eval_mu);
-    if (sys && sys->n_atoms == 0) {
-        int rc = check_prec(prec);
-        if (rc) return rc;
-        const double z = 0.0;
-        if (energy) {
-            if (ex && ex->device_ptrs) HIPCHK(hipMemcpy(energy, &z, 8, hipMemcpyHostToDevice));
-            else *energy = 0.0;
-        }
-        return SL_OK;
-    }
-    Replica r;
-    Engine *e = nullptr;
-    int rc = eval_common(m, sys, prec, r, e);
+// an empty system: zero energy, nothing else written
+static int eval_empty(sl_precision prec, double *energy, const sl_exec *ex) {
+    int rc = check_prec(prec);
     if (rc) return rc;
+    const double z = 0.0;
+    if (energy) {
+        if (ex && ex->device_ptrs) HIPCHK(hipMemcpy(energy, &z, 8, hipMemcpyHostToDevice));
+        else *energy = 0.0;
+    }
+    return SL_OK;
+}
+
+// E, E_i, F, H of replica r, laid out alone on engine e and evaluated, into
+// the caller's buffers (host, or device memory when ex->device_ptrs)
+static int eval_outputs(Engine *e, Replica &r, sl_precision prec, double *energy, double *energy_atom,
+                        double *force, double *field, const sl_exec *ex) {
+    int rc = SL_OK;
     const int64_t n = r.n;
     const bool dev = ex && ex->device_ptrs;
     std::vector<double> Fh, Hh, Eh;
@@ -1375,6 +1409,45 @@ extern "C" int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_p
     }
     if (ob[8] != 0) return fail(SL_E_NONFINITE, "non-finite energy, force or state");
     return SL_OK;
+}
+
+extern "C" int nep_spin_eval(const nep_model *m, const sl_system_view *sys, sl_precision prec, double *energy,
+                             double *energy_atom, double *force, double *field, const sl_exec *ex) {
+    if (!m) return fail(SL_E_INVALID, "model is NULL");
+    std::lock_guard<std::mutex> lk(const_cast<nep_model *>(m)->eval_mu);
+    if (sys && sys->n_atoms == 0) return eval_empty(prec, energy, ex);
+    Replica r;
+    Engine *e = nullptr;
+    int rc = eval_common(m, sys, prec, r, e);
+    if (rc) return rc;
+    return eval_outputs(e, r, prec, energy, energy_atom, force, field, ex);
+}
+
+extern "C" int nep_spin_eval_noalloc(const nep_model *m, const sl_system_view *sys, sl_precision prec,
+                                     double *energy, double *energy_atom, double *force, double *field,
+                                     const sl_exec *ex) {
+    if (!m) return fail(SL_E_INVALID, "model is NULL");
+    int rc = check_prec(prec);
+    if (rc) return rc;
+    // every call in this process shares the current GPU's scratch array
+    static std::mutex scratch_mu;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (sys && sys->n_atoms == 0) return eval_empty(prec, energy, ex);
+    void *base = nullptr;
+    size_t bytes = 0;
+    if (scratch_area(&base, &bytes) != 0)
+        return fail(SL_E_DEVICE, "no device, or the static scratch area could not be resolved");
+    Replica r;
+    if ((rc = make_replica(sys, nullptr, nullptr, nullptr, false, r, m->structural))) return rc;
+    Engine e;
+    e.arena = static_cast<char *>(base);
+    e.arena_cap = bytes;
+    e.M = const_cast<nep_model *>(m);
+    e.prec = prec;
+    e.st = ex && ex->hip_stream ? (hipStream_t)ex->hip_stream : nullptr;
+    if ((rc = e.set_layout({&r}))) return rc;
+    if ((rc = e.check_flags())) return rc;
+    return eval_outputs(&e, r, prec, energy, energy_atom, force, field, ex);
 }
 
 extern "C" int nep_spin_descriptors(const nep_model *m, const sl_system_view *sys, sl_precision prec, double *q,

@@ -21,7 +21,8 @@ SL_QUEUED, SL_RUNNING, SL_DONE, SL_FAILED = 0, 1, 2, 3
 
 PRECISION = {"fp64": SL_FP64, "fp32": SL_FP32_MIXED}
 
-EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_descriptors",
+EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_eval", "nep_spin_eval_noalloc",
+           "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
            "sl_replica_submit", "sl_replica_poll", "sl_replica_fetch", "sl_server_drain", "sl_server_stats",
            "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour", "sl_replica_bytes"]
@@ -109,6 +110,7 @@ def load():
         L.nep_model_create.argtypes = [ct.POINTER(HParams), P, ct.c_size_t, ct.POINTER(P)]
         L.nep_model_destroy.argtypes = [P]
         L.nep_spin_eval.argtypes = [P, ct.POINTER(SystemView), ct.c_int, P, P, P, P, ct.POINTER(Exec)]
+        L.nep_spin_eval_noalloc.argtypes = [P, ct.POINTER(SystemView), ct.c_int, P, P, P, P, ct.POINTER(Exec)]
         L.nep_spin_descriptors.argtypes = [P, ct.POINTER(SystemView), ct.c_int, P, P, ct.POINTER(Exec)]
         L.sl_create.argtypes = [P, ct.POINTER(SystemView), P, P, ct.POINTER(IntegratorParams), ct.c_int,
                                 ct.POINTER(P)]
@@ -214,15 +216,17 @@ class Model:
             pass
 
     def eval(self, types, pos, spin, box, pbc=(1, 1, 1), *, mu_s=1.0, B=(0, 0, 0), precision="fp64",
-             want=("E", "F", "H")):
-        """nep_spin_eval with host buffers: dict with E (total), Ei, F, H."""
+             want=("E", "F", "H"), noalloc=False):
+        """nep_spin_eval (nep_spin_eval_noalloc if noalloc) with host buffers:
+        dict with E (total), Ei, F, H."""
         v, keep = system_view(types, pos, spin, box, pbc, mu_s, B)
         n = v.n_atoms
         E = np.zeros(1)
         Ei = np.zeros(n) if "Ei" in want else None
         F = np.zeros((n, 3)) if "F" in want else None
         H = np.zeros((n, 3)) if "H" in want else None
-        _check(load().nep_spin_eval(self.h, ct.byref(v), PRECISION[precision], _p(E), _p(Ei), _p(F), _p(H), None))
+        fn = load().nep_spin_eval_noalloc if noalloc else load().nep_spin_eval
+        _check(fn(self.h, ct.byref(v), PRECISION[precision], _p(E), _p(Ei), _p(F), _p(H), None))
         out = {"E": float(E[0])}
         for k, a in (("Ei", Ei), ("F", F), ("H", H)):
             if a is not None:
