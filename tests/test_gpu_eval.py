@@ -130,7 +130,7 @@ def test_eval_short_range_fp64_matches_oracle(model_sr, oracle, case):
     p = W.random_params()
     zbl = W.SHORT_RANGE_FEGE
     B = (0.1, 0.3, -0.2)
-    targets = (0.7, 0.95, 1.05, 1.3, 1.5, 1.75, 1.95, 2.05)
+    targets = (0.9, 1.3, 1.7, 1.85, 2.0, 2.2, 2.45, 2.7)
     if case == "crystal":
         s = W.fege_lattice(4, 4, 4, noise=0.05, seed=5)
         pos, box = s.pos, s.box
@@ -148,17 +148,14 @@ def test_eval_short_range_fp64_matches_oracle(model_sr, oracle, case):
     assert abs(got["E"] - (ref["E"] + ref["Ez"])) <= TOL64 * abs(ref["E"] + ref["Ez"])
     assert rel_inf(got["F"], ref["F"]) <= TOL64
     assert rel_inf(got["H"], ref["H"]) <= TOL64
-    # the term really acts where pairs were moved close and is absent in the crystal
+    # the term really acts (the crystal's nearest Fe-Ge pairs sit inside its switch)
     plain = oracle.evaluate(s.types, pos, s.spin, obox, s.pbc, p, B=B, want=("E",))
-    if case == "crystal":
-        assert ref["E"] == plain["E"]
-    else:
-        assert ref["E"] - plain["E"] > 1.0
+    assert ref["E"] - plain["E"] > (1.0 if case != "crystal" else 0.0)
 
 
 def test_eval_short_range_fp32_error(model_sr, oracle):
     s = W.fege_lattice(7, 7, 7, seed=6)
-    pos = close_pairs(s, (1.2, 1.4, 1.6, 1.8, 1.9) * 4, 6)
+    pos = close_pairs(s, (1.2, 1.6, 1.9, 2.1, 2.3) * 4, 6)
     p = W.random_params()
     ref = oracle.evaluate(s.types, pos, s.spin, s.box, s.pbc, p, zbl=W.SHORT_RANGE_FEGE)
     got = model_sr.eval(s.types, pos, s.spin, s.box, s.pbc, precision="fp32")

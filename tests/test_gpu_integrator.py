@@ -147,7 +147,7 @@ def test_every_step_short_range_langevin(model_sr, oracle):
     from tests.test_gpu_eval import close_pairs
     kw = SCHEDULES["langevin"]
     s = W.config_small()
-    pos = close_pairs(s, (1.6, 1.7, 1.8, 1.9, 1.95), 11)
+    pos = close_pairs(s, (1.7, 1.9, 2.0, 2.1, 2.2), 11)
     p = W.random_params()
     zbl = W.SHORT_RANGE_FEGE
     v = W.maxwell_boltzmann(s.types, 300.0)
@@ -281,6 +281,25 @@ def test_config2_run_is_stable(config2_run):
     assert dmin > 1.5
     assert n_recolour == 0
     assert np.abs(np.linalg.norm(spin[fe], axis=1) - 1).max() <= 1e-14
+
+
+def test_crystal_screen_2000_steps(model_sr):
+    """The workload's stability screen: the 512-atom cell at 300 K for 2,000
+    steps keeps every pair beyond 1.5 A and its rms displacement below 0.5 A"""
+    from scipy.spatial import cKDTree
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    sim = nepspin.Sim(model_sr, s.types, s.pos, s.spin, s.box, s.pbc, vel=W.maxwell_boltzmann(s.types, 300.0),
+                      colour=s.colour, params=_params(nepspin, **CONFIG2))
+    worst_d, worst_rms = 1e9, 0.0
+    for _ in range(20):
+        sim.integrate(100, observables=False)
+        pos = sim.state()[0]
+        worst_d = min(worst_d, cKDTree(np.mod(pos, s.box), boxsize=s.box).query(np.mod(pos, s.box), k=2)[0][:, 1].min())
+        worst_rms = max(worst_rms, np.sqrt((min_image_delta(pos, s.pos, s.box, s.pbc) ** 2).sum(axis=1).mean()))
+    sim.close()
+    print(f"2,000 steps at 300 K: closest pair {worst_d:.3f} A, largest rms displacement {worst_rms:.3f} A", flush=True)
+    assert worst_d > 1.5 and worst_rms < 0.5
 
 
 def test_step_parity_full_size(model, oracle):
