@@ -112,6 +112,14 @@ typedef struct {
      * required (SL_E_INVALID). It adds to E, E_i and F only.              */
     double sr_Z[2];
     double sr_r_inner, sr_r_outer;
+    /* Optional onsite moment-length term of the spin carriers, for spins of
+     * variable length (Sec. 3: the integrator carries the longitudinal
+     * fluctuation of the magnetic moment):
+     *   E_i += moment_a |s_i|^2 + moment_b |s_i|^4   (species 0),
+     * a Landau expansion whose minimum sits at |s|^2 = -moment_a/(2 moment_b);
+     * it adds to E, E_i and H (H_i -= (2 moment_a + 4 moment_b |s_i|^2) s_i).
+     * Both 0: off. moment_b < 0 (unbounded below) is SL_E_INVALID.         */
+    double moment_a, moment_b;
 } nep_spin_hparams;
 
 /* params: 15,438 doubles in this order (tau = 2 t_i + t_j is the ordered
@@ -235,7 +243,13 @@ typedef struct {
     int ensemble;        /* 0 NVE (no O step, alpha_s must be 0 for NVE spins), 1 Langevin */
     int K_corr;          /* number of corrector passes (0 = predictor only)  */
     double mid_tol;      /* per-spin midpoint tolerance, e.g. 1e-15           */
-    int mid_cap;         /* per-spin midpoint iteration cap, e.g. 50 (Newton) */
+    int mid_cap;         /* per-spin cap on the iterations of the midpoint
+                            equation, 1..1000 (1: the explicit rotation G(s)).
+                            The solve is Newton's method, so it needs fewer
+                            iterations than plain fixed-point iteration; the
+                            result is defined up to mid_tol only when the
+                            equation converged, which sl_observables.mid_capped
+                            reports for every step                           */
     uint64_t seed;       /* Philox key                                        */
     double skin;         /* Verlet skin (A); lists rebuilt when an atom moved
                             more than skin/2 since the last build             */
@@ -254,11 +268,28 @@ typedef struct {
                             differences (Anderson); 0: plain iteration       */
     double sc_reg;       /* Tikhonov regularisation of the mixing, relative
                             to the mean diagonal of the residual Gram matrix */
+    int longitudinal;    /* 1: spins of variable length (Sec. 3, longitudinal
+                            fluctuation of the moment), Langevin dynamics
+                              ds/dt = (h x s)/hbar + (gamma_lsf/hbar) h + xi,
+                              <xi xi> = 2 gamma_lsf kB T_n/hbar (isotropic),
+                            whose equilibrium density over vectors s is
+                            exp(-E/kB T). Each colour visit of the sweep is
+                            then L(dt/4) R(dt/2) L(dt/4): R the rotation
+                            above with alpha_s = 0 and the midpoint taken at
+                            length |s|, L the Euler-Maruyama step
+                            s += (gamma_lsf t/hbar) h(s) + sqrt(2 gamma_lsf kB T_n t/hbar) xi
+                            with h the frozen-Fp field at s (Philox streams
+                            2 + 2v and 3 + 2v, v = 0 ascending, 1 descending
+                            pass); reference spins are the plain average
+                            (S^n + S^(p))/2. alpha_s must be 0 (the damping
+                            is gamma_lsf). 0: unit spins as above.           */
+    double gamma_lsf;    /* damping of the longitudinal dynamics (>= 0)      */
 } sl_integrator_params;
 
 typedef struct {
     int64_t step;
-    double E_pot;        /* E_NEP at the end of the step                     */
+    double E_pot;        /* E_NEP (+ short-range and moment-length terms) at
+                            the end of the step                              */
     double E_kin;
     double E_zeeman;
     double T_lattice;    /* 2 E_kin / (3 N kB)                               */
@@ -266,9 +297,13 @@ typedef struct {
     double M[3];         /* mean spin                                         */
     int32_t spin_passes; /* sweeps of the spin step: K_corr + 1, or the number
                             the self-consistent iteration took               */
+    int32_t mid_capped;  /* spin rotations of the step (all passes) whose
+                            midpoint equation still missed mid_tol after
+                            mid_cap iterations (0 when every one converged)  */
     double spin_change;  /* self-consistent: max |S^(p) - x^(p)| of the last
                             pass (x^(p): the spins whose midpoint it used);
                             0 otherwise                                      */
+    double spin_length;  /* mean |s| over the spins                          */
 } sl_observables;
 
 /* Create a simulation of one system: copies the state to the device and

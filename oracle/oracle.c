@@ -903,8 +903,8 @@ typedef struct {
     double step, E_nep, E_kin, E_z, T_lat, T_spin, M[3];
     double passes;   /* sweeps of the spin step (predictor + correctors)      */
     double change;   /* max |g - x| of its last pass                         */
-    double capped;   /* spin rotations of the step's last pass that stopped at
-                        mid_cap without meeting mid_tol                      */
+    double capped;   /* spin rotations of the step (all passes) that stopped
+                        at mid_cap without meeting mid_tol                   */
     double s_len;    /* mean |s| over the spin carriers                       */
 } or_obs;
 
@@ -1197,7 +1197,6 @@ int or_run(int n, const int *type, double *pos, double *vel, double *spin, const
                 /* restart from S^n; C.spin now holds the spins being swept */
                 memcpy(C.spin, Sn, sizeof(double) * 3 * n);
                 env_cache(&C);
-                capped = 0;
                 memset(cap_of, 0, sizeof(int) * (size_t)(n + 1));
                 for (int pass = 0; pass < 2; pass++) {
                     for (int cc = 0; cc < ncol; cc++) {

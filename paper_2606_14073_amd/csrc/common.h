@@ -64,6 +64,10 @@ struct RepDev {
     double sc_tol;                  // self-consistent midpoint tolerance (0: fixed K_corr)
     unsigned long long sc_delta;    // max |S^(p) - S^(p-1)| of the current pass, as bits
     int sc_max, sc_done;            // pass cap; converged in this step
+    double landau_a, landau_b;      // the model's onsite moment-length term a|s|^2 + b|s|^4
+    double lsf_gamma;               // damping of the longitudinal spin dynamics
+    int lsf;                        // 1: spins of variable length (longitudinal Langevin dynamics)
+    int capped;                     // rotations of this step stopped at mid_cap without meeting mid_tol
 };
 
 __device__ inline double ramp_frac(const RepDev &R) {

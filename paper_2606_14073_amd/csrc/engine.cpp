@@ -74,6 +74,7 @@ struct nep_model {
     std::vector<double> p;          // spin-aware layout (a structural-only model is expanded)
     bool structural = false;
     double zbl[4] = {0, 0, 0, 0};   // short-range term: Z_0, Z_1, r_inner, r_outer (r_outer 0: off)
+    double landau[2] = {0, 0};      // onsite moment-length term a|s|^2 + b|s|^4 of spin carriers
     double *d64 = nullptr;
     float *d32 = nullptr;
     ModelDev<double> m64{};
@@ -614,6 +615,8 @@ struct Engine {
             fo += (int)r->n_fe;
             go += (int)(r->n - r->n_fe);
             h_rep[k] = r->dev;
+            h_rep[k].landau_a = M ? M->landau[0] : 0.0;   // the model's term, read by the spin kernels
+            h_rep[k].landau_b = M ? M->landau[1] : 0.0;
         }
         h_cptr.push_back((int)h_chunks.size());
         n_cells = cb;
@@ -1188,6 +1191,13 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
             return fail(SL_E_INVALID, "sc_depth must be in [0, 8] and sc_reg finite and >= 0");
         if (ip->alpha_s < 0 || ip->T0 < 0 || ip->T1 < 0 || ip->gamma_L < 0)
             return fail(SL_E_INVALID, "alpha_s, temperatures and gamma_L must be non-negative");
+        if (ip->longitudinal != 0 && ip->longitudinal != 1) return fail(SL_E_INVALID, "longitudinal must be 0 or 1");
+        if (!(ip->gamma_lsf >= 0 && std::isfinite(ip->gamma_lsf)))
+            return fail(SL_E_INVALID, "gamma_lsf must be finite and >= 0");
+        if (ip->longitudinal && ip->alpha_s != 0)
+            return fail(SL_E_INVALID, "with longitudinal = 1 the damping is gamma_lsf: alpha_s must be 0");
+        d.lsf = ip->longitudinal;
+        d.lsf_gamma = ip->longitudinal ? ip->gamma_lsf : 0.0;
         d.dt = ip->dt;
         d.T0 = ip->T0;
         d.T1 = ip->T1;
@@ -1205,6 +1215,7 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
             d.B1[a] = ip->B1[a];
         }
     }
+    Engine::cell_grid(r, sys->pos);
     if (need_colour) {
         std::vector<int> col;
         if (colour) {
@@ -1235,7 +1246,6 @@ static int make_replica(const sl_system_view *sys, const double *vel, const int3
             r.ncol = std::max(r.ncol, c + 1);
         }
     }
-    Engine::cell_grid(r, sys->pos);
     return SL_OK;
 }
 
@@ -1272,6 +1282,8 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
         return fail(SL_E_INVALID, "unsupported hyper-parameters (this build: n_max_R 8, n_max_A 6, l_max 4, "
                                   "basis_K 8, n_hidden 64, 2 species, rc 6.0/4.5)");
     if (hp->structural != 0 && hp->structural != 1) return fail(SL_E_INVALID, "structural must be 0 or 1");
+    if (!std::isfinite(hp->moment_a) || !std::isfinite(hp->moment_b) || hp->moment_b < 0)
+        return fail(SL_E_INVALID, "moment-length term: moment_a, moment_b must be finite and moment_b >= 0");
     if (hp->sr_r_outer != 0.0) {
         const bool ok = std::isfinite(hp->sr_Z[0]) && std::isfinite(hp->sr_Z[1]) && hp->sr_Z[0] > 0 &&
                         hp->sr_Z[1] > 0 && std::isfinite(hp->sr_r_inner) && hp->sr_r_inner > 0 &&
@@ -1298,6 +1310,10 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
         m->zbl[1] = hp->sr_Z[1];
         m->zbl[2] = hp->sr_r_inner;
         m->zbl[3] = hp->sr_r_outer;
+    }
+    if (!m->structural) {
+        m->landau[0] = hp->moment_a;
+        m->landau[1] = hp->moment_b;
     }
     if (m->structural) m->p = expand_structural(params);
     else m->p.assign(params, params + n_params);
@@ -1407,7 +1423,7 @@ static int eval_outputs(Engine *e, Replica &r, sl_precision prec, double *energy
     } else if (energy) {
         *energy = Etot;
     }
-    if (ob[8] != 0) return fail(SL_E_NONFINITE, "non-finite energy, force or state");
+    if (ob[NOBS - 1] != 0) return fail(SL_E_NONFINITE, "non-finite energy, force or state");
     return SL_OK;
 }
 
@@ -1500,6 +1516,8 @@ static void fill_obs(const double *o, double nfe, int64_t step, int64_t n_atoms,
     out->T_lattice = n_atoms ? 2.0 * o[1] / (3.0 * n_atoms * KB) : 0.0;
     out->T_spin = o[4] != 0 ? o[3] / (2.0 * KB * o[4]) : 0.0;
     for (int a = 0; a < 3; a++) out->M[a] = nfe > 0 ? o[5 + a] / nfe : 0.0;
+    out->spin_length = nfe > 0 ? o[8] / nfe : 0.0;
+    out->mid_capped = (int32_t)o[9];
 }
 
 extern "C" int sl_create(const nep_model *m, const sl_system_view *sys, const double *vel, const int32_t *colour,

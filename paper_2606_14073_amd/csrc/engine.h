@@ -114,8 +114,10 @@ int sc_part_blocks(int n_fe);
 void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st);
 void launch_sc_mix(const Sys &S, int pass, int depth, hipStream_t st);
 
-// per-replica fixed-order reductions: out[r][NOBS]
-constexpr int NOBS = 9;   // E_nep, E_kin, E_z, Ts_num, Ts_den, Mx, My, Mz, nonfinite
+// per-replica fixed-order reductions: out[r][NOBS]: E_nep, E_kin, E_z,
+// Ts_num, Ts_den, Mx, My, Mz, sum |s|, rotations stopped at the cap, and
+// last the count of non-finite atoms
+constexpr int NOBS = 11;
 struct Chunk {
     int rid, begin, end;
 };

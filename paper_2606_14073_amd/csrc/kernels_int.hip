@@ -67,7 +67,7 @@ __global__ void k_spin_prep(Sys S) {
     if (!R.active) return;
     const double T = temperature(R);
     d4 e = {0, 0, 0, 0};
-    if (R.alpha > 0 && T > 0) {
+    if (!R.lsf && R.alpha > 0 && T > 0) {
         const double sig = sqrt(2.0 * R.alpha * KB * T * HBAR / R.dt);
         double xi[3];
         gauss3(R.seed, (uint32_t)S.orig[i], (unsigned long long)R.step, 1u, xi);
@@ -97,7 +97,8 @@ __global__ void k_spin_mid(Sys S) {
     if (!spin_pass_on(S.rep[S.rid[i]])) return;
     const d4 a = S.spin_n[i], b = S.spin[i];
     const double x = 0.5 * (a.x + b.x), y = 0.5 * (a.y + b.y), z = 0.5 * (a.z + b.z);
-    const double n = sqrt(x * x + y * y + z * z);
+    // unit spins: the normalised average; spins of variable length: the average
+    const double n = S.rep[S.rid[i]].lsf ? 1.0 : sqrt(x * x + y * y + z * z);
     d4 h = {x / n, y / n, z / n, 0.0};
     S.spin_hat[i] = h;
 }
@@ -165,7 +166,7 @@ constexpr int SWEEP_R0 = 2;    // coupling slots per lane loaded up front (32 pe
 // start of the descending pass): the neighbour field is the same for both
 // rotations, the second starts from the first one's result.
 template <typename real>
-__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count, int turns) {
+__global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count, int turns, int visit0) {
     const int lane = threadIdx.x & (SWEEP_L - 1);
     const int t = blockIdx.x * (256 / SWEEP_L) + threadIdx.x / SWEEP_L;
     if (t >= count) return;
@@ -230,19 +231,22 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     const double tol = R.mid_tol;
     const int cap = R.mid_cap;
     const double Dxx = Axx + os, Dyy = Ayy + os, Dzz = Azz + os;   // A_i + o_i I
+    const double la2 = 2.0 * R.landau_a, lb4 = 4.0 * R.landau_b;   // onsite moment-length term
     double sx = s4.x, sy = s4.y, sz = s4.z;
+    double len = 1.0;    // length of the midpoint vector: 1, or |s| for spins of variable length
     // G(y): the spin rotated about the precession vector taken at the
-    // midpoint m = (s + y)/|s + y| (field, damping, anisotropy and onsite
-    // terms evaluated at m), by the angle |w| tau (Rodrigues)
+    // midpoint m = len (s + y)/|s + y| (field, damping, anisotropy, onsite
+    // and moment-length terms evaluated at m), by the angle |w| tau (Rodrigues)
     auto rotate = [&](double px, double py, double pz, double &nx, double &ny, double &nz) {
         double mx = sx + px, my = sy + py, mz = sz + pz;
-        const double mn = rsqrt_nr(mx * mx + my * my + mz * mz);
+        const double mn = rsqrt_nr(mx * mx + my * my + mz * mz) * len;
         mx *= mn;
         my *= mn;
         mz *= mn;
-        const double h0 = hx - 2.0 * (Dxx * mx + Axy * my + Axz * mz);
-        const double h1 = hy - 2.0 * (Axy * mx + Dyy * my + Ayz * mz);
-        const double h2 = hz - 2.0 * (Axz * mx + Ayz * my + Dzz * mz);
+        const double kl = la2 + lb4 * (mx * mx + my * my + mz * mz);
+        const double h0 = hx - 2.0 * (Dxx * mx + Axy * my + Axz * mz) - kl * mx;
+        const double h1 = hy - 2.0 * (Axy * mx + Dyy * my + Ayz * mz) - kl * my;
+        const double h2 = hz - 2.0 * (Axz * mx + Ayz * my + Dzz * mz) - kl * mz;
         const double wx = (h0 + al * (my * h2 - mz * h1)) * inv;
         const double wy = (h1 + al * (mz * h0 - mx * h2)) * inv;
         const double wz = (h2 + al * (mx * h1 - my * h0)) * inv;
@@ -280,13 +284,42 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     // convergence to linear with that ratio.
     const int sub = lane & 3;
     constexpr double FD_H = 0x1p-26, FD_IH = 0x1p26;
+    // Spins of variable length with damping: the rotation sits between two
+    // longitudinal half steps of the Langevin dynamics over dt/4 each,
+    // x += (gamma t/hbar) h(x) + sqrt(2 gamma kB T t/hbar) xi, h the full
+    // field at x (neighbours, Zeeman, anisotropy, onsite and moment-length
+    // terms), xi the Philox normals of streams 2 + 2 visit and 3 + 2 visit
+    // (visit 0 ascending, 1 descending); every lane of the spin takes them
+    // alike.
+    const bool lsf = R.lsf != 0, lsf_damp = lsf && R.lsf_gamma > 0;
+    const double T = lsf_damp ? temperature(R) : 0.0;
+    auto lsf_half = [&](double &x, double &y, double &z, uint32_t stream) {
+        const double t = 0.25 * R.dt;
+        const double kl = la2 + lb4 * (x * x + y * y + z * z);
+        const double f0 = hx - 2.0 * (Dxx * x + Axy * y + Axz * z) - kl * x;
+        const double f1 = hy - 2.0 * (Axy * x + Dyy * y + Ayz * z) - kl * y;
+        const double f2 = hz - 2.0 * (Axz * x + Ayz * y + Dzz * z) - kl * z;
+        double xi[3] = {0.0, 0.0, 0.0};
+        if (T > 0) gauss3(R.seed, (uint32_t)S.orig[i], (unsigned long long)R.step, stream, xi);
+        const double k = R.lsf_gamma * t / HBAR, sig = sqrt(2.0 * R.lsf_gamma * KB * T * t / HBAR);
+        x += k * f0 + sig * xi[0];
+        y += k * f1 + sig * xi[1];
+        z += k * f2 + sig * xi[2];
+    };
     double yx = sx, yy = sy, yz = sz;
+    int ncapped = 0;
     for (int turn = 0; turn < turns; turn++) {
         if (turn) {
             sx = yx;
             sy = yy;
             sz = yz;
         }
+        const uint32_t visit = (uint32_t)(visit0 + turn);
+        if (lsf_damp) lsf_half(sx, sy, sz, 2u + 2u * visit);
+        if (lsf) len = sqrt(sx * sx + sy * sy + sz * sz);
+        yx = sx;
+        yy = sy;
+        yz = sz;
         for (int it = 0; it < cap; it++) {
             double nx, ny, nz;
             rotate(yx + (sub == 1 ? FD_H : 0.0), yy + (sub == 2 ? FD_H : 0.0), yz + (sub == 3 ? FD_H : 0.0), nx, ny,
@@ -298,6 +331,7 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
                 yx = g0x;
                 yy = g0y;
                 yz = g0z;
+                ncapped += diff > tol;
                 break;
             }
             // A = I - J, J columns (G(y + h e_c) - G(y)) / h
@@ -322,10 +356,12 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
                 yz = g0z;
             }
         }
+        if (lsf_damp) lsf_half(yx, yy, yz, 3u + 2u * visit);
     }
     if (lane == 0) {
         d4 out = {yx, yy, yz, 0.0};
         S.spin[i] = out;
+        if (ncapped) atomicAdd(&S.rep[r].capped, ncapped);
     }
 }
 
@@ -340,6 +376,7 @@ __global__ void k_step_end(Sys S) {
     }
     R.step += 1;
     R.sc_done = 0;
+    R.capped = 0;
     // a replica waiting for a new colouring stops after this (exact) step
     if (R.step >= R.step_end || (R.failed & 4)) R.active = 0;
 }
@@ -533,7 +570,7 @@ __global__ void __launch_bounds__(256) k_sc_mix(Sys S, int pass, int depth) {
     S.sc_x[i] = d4{x, y, z, 0.0};
     const d4 a = S.spin_n[i];
     const double mx = 0.5 * (a.x + x), my = 0.5 * (a.y + y), mz = 0.5 * (a.z + z);
-    const double n = sqrt(mx * mx + my * my + mz * mz);
+    const double n = S.rep[S.rid[i]].lsf ? 1.0 : sqrt(mx * mx + my * my + mz * mz);
     S.spin_hat[i] = d4{mx / n, my / n, mz / n, 0.0};
 }
 
@@ -564,9 +601,10 @@ __global__ void __launch_bounds__(256) k_obs_partial(Sys S, Work<real> W, const 
             v[5] = s.x;
             v[6] = s.y;
             v[7] = s.z;
+            v[8] = sqrt(s.x * s.x + s.y * s.y + s.z * s.z);
         }
         const double chk = p.x + p.y + p.z + vel.x + vel.y + vel.z + s.x + s.y + s.z + F.x + F.y + F.z + v[0];
-        v[8] = isfinite(chk) ? 0.0 : 1.0;
+        v[NOBS - 1] = isfinite(chk) ? 0.0 : 1.0;
     }
 #pragma unroll
     for (int k = 0; k < NOBS; k++) red[k][t] = v[k];
@@ -600,8 +638,9 @@ __global__ void __launch_bounds__(256) k_obs_final(Sys S, const int *chunk_ptr, 
             for (int k = 0; k < NOBS; k++) red[k][t] += red[k][t + off];
         __syncthreads();
     }
-    // slot NOBS-1 counts non-finite atoms
-    if (t < NOBS) out[(size_t)r * NOBS + t] = red[t][0];
+    // slot 9: the replica's capped rotations (a counter, not a sum); slot
+    // NOBS-1 counts non-finite atoms
+    if (t < NOBS) out[(size_t)r * NOBS + t] = t == 9 ? (double)S.rep[r].capped : red[t][0];
 }
 
 }  // namespace
@@ -649,7 +688,8 @@ void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, in
             const int turns = (pass == 0 && cc == n_colours - 1) ? 2 : 1;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
             if (n > 0)
-                hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256 / SWEEP_L)), dim3(256), 0, st, S, W, b, n, turns);
+                hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256 / SWEEP_L)), dim3(256), 0, st, S, W, b, n, turns,
+                                   pass);
         }
 }
 

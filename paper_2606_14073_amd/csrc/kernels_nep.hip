@@ -827,6 +827,17 @@ __global__ void __launch_bounds__(256) k_bwd_radial(Sys S, const real *__restric
         h[0] = os2 * si[0];
         h[1] = os2 * si[1];
         h[2] = os2 * si[2];
+        // onsite moment-length term a|s|^2 + b|s|^4: its energy and dE/ds
+        const RepDev &Rr = S.rep[S.rid[i]];
+        if (Rr.landau_a != 0.0 || Rr.landau_b != 0.0) {
+            const real la = (real)Rr.landau_a, lb = (real)Rr.landau_b;
+            const real s2 = si[0] * si[0] + si[1] * si[1] + si[2] * si[2];
+            const real kl = real(2) * la + real(4) * lb * s2;
+            h[0] += kl * si[0];
+            h[1] += kl * si[1];
+            h[2] += kl * si[2];
+            esr += la * s2 + lb * s2 * s2;
+        }
         for (int part = 0; part < 2; part++) {
             real CR[NB], CS[NB];
             contract((C + P_CR) + part * NR * NB, Fp + D_R, NR, CR);

@@ -46,7 +46,7 @@ class HParams(ct.Structure):
     _fields_ = [("n_max_R", ct.c_int), ("n_max_A", ct.c_int), ("l_max", ct.c_int), ("basis_K", ct.c_int),
                 ("n_hidden", ct.c_int), ("n_species", ct.c_int), ("rc_R", ct.c_double), ("rc_A", ct.c_double),
                 ("structural", ct.c_int), ("sr_Z", ct.c_double * 2), ("sr_r_inner", ct.c_double),
-                ("sr_r_outer", ct.c_double)]
+                ("sr_r_outer", ct.c_double), ("moment_a", ct.c_double), ("moment_b", ct.c_double)]
 
 N_PARAMS = 15438
 N_PARAMS_STRUCT = 5570     # structural-only NEP: c^R, c^A, per species W0[64][37], b0, w1, b1
@@ -66,13 +66,15 @@ class IntegratorParams(ct.Structure):
                 ("B1", ct.c_double * 3), ("alpha_s", ct.c_double), ("gamma_L", ct.c_double),
                 ("n_ramp", ct.c_int64), ("ensemble", ct.c_int), ("K_corr", ct.c_int), ("mid_tol", ct.c_double),
                 ("mid_cap", ct.c_int), ("seed", ct.c_uint64), ("skin", ct.c_double), ("sc_tol", ct.c_double),
-                ("sc_max", ct.c_int), ("mass", ct.c_double * 2), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double)]
+                ("sc_max", ct.c_int), ("mass", ct.c_double * 2), ("sc_depth", ct.c_int), ("sc_reg", ct.c_double),
+                ("longitudinal", ct.c_int), ("gamma_lsf", ct.c_double)]
 
 
 class Observables(ct.Structure):
     _fields_ = [("step", ct.c_int64), ("E_pot", ct.c_double), ("E_kin", ct.c_double), ("E_zeeman", ct.c_double),
                 ("T_lattice", ct.c_double), ("T_spin", ct.c_double), ("M", ct.c_double * 3),
-                ("spin_passes", ct.c_int32), ("spin_change", ct.c_double)]
+                ("spin_passes", ct.c_int32), ("mid_capped", ct.c_int32), ("spin_change", ct.c_double),
+                ("spin_length", ct.c_double)]
 
 
 class ServerConfig(ct.Structure):
@@ -173,7 +175,7 @@ def system_view(types, pos, spin, box, pbc=(1, 1, 1), mu_s=1.0, B=(0.0, 0.0, 0.0
 
 def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s=0.0, gamma_L=0.0, n_ramp=0,
                       ensemble=0, K_corr=1, mid_tol=1e-15, mid_cap=50, seed=0x5EED, skin=0.5, sc_tol=0.0,
-                      sc_max=30, sc_depth=0, sc_reg=1e-10, mass=(0.0, 0.0)):
+                      sc_max=30, sc_depth=0, sc_reg=1e-10, mass=(0.0, 0.0), longitudinal=0, gamma_lsf=0.0):
     ip = IntegratorParams()
     ip.dt, ip.T0, ip.T1 = dt, T0, T0 if T1 is None else T1
     for a in range(3):
@@ -183,6 +185,7 @@ def integrator_params(*, dt=1.0, T0=0.0, T1=None, B0=(0, 0, 0), B1=None, alpha_s
     ip.K_corr, ip.mid_tol, ip.mid_cap, ip.seed, ip.skin = K_corr, mid_tol, mid_cap, seed, skin
     ip.sc_tol, ip.sc_max, ip.sc_depth, ip.sc_reg = sc_tol, sc_max, sc_depth, sc_reg
     ip.mass[0], ip.mass[1] = mass
+    ip.longitudinal, ip.gamma_lsf = longitudinal, gamma_lsf
     return ip
 
 
@@ -190,16 +193,19 @@ class Model:
     """nep_model_create: the spin-aware NEP (15,438 parameters) or the
     structural-only one (5,570 parameters), told apart by the length.
     short_range = (Z_0, Z_1, r_inner, r_outer) adds the screened-Coulomb
-    repulsion; None leaves it off."""
+    repulsion, landau = (a, b) the onsite moment-length term a|s|^2 + b|s|^4
+    of spin carriers; None leaves either off."""
 
-    def __init__(self, params, short_range=None):
+    def __init__(self, params, short_range=None, landau=None):
         L = load()
         p = _f64(params)
         self.structural = p.size == N_PARAMS_STRUCT
         hp = HParams(8, 6, 4, 8, 64, 2, 6.0, 4.5, int(self.structural))
         if short_range is not None:
             hp.sr_Z[0], hp.sr_Z[1], hp.sr_r_inner, hp.sr_r_outer = (float(x) for x in short_range)
-        self.short_range = short_range
+        if landau is not None:
+            hp.moment_a, hp.moment_b = (float(x) for x in landau)
+        self.short_range, self.landau = short_range, landau
         h = ct.c_void_p()
         _check(L.nep_model_create(ct.byref(hp), _p(p), p.size, ct.byref(h)))
         self.h = h
@@ -253,9 +259,10 @@ class Model:
 
 
 def _obs_array(obs, n):
-    """columns: step, E_pot, E_kin, E_zeeman, T_lattice, T_spin, M[3], spin sweep passes, last change"""
+    """columns: step, E_pot, E_kin, E_zeeman, T_lattice, T_spin, M[3], spin sweep passes, last change,
+    rotations stopped at the cap, mean |s|"""
     return np.array([[o.step, o.E_pot, o.E_kin, o.E_zeeman, o.T_lattice, o.T_spin, o.M[0], o.M[1], o.M[2],
-                      o.spin_passes, o.spin_change] for o in obs[:n]]).reshape(n, 11)
+                      o.spin_passes, o.spin_change, o.mid_capped, o.spin_length] for o in obs[:n]]).reshape(n, 13)
 
 
 class Sim:

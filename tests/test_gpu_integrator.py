@@ -108,9 +108,11 @@ def test_every_step_matches_oracle_small(model, oracle, sched):
 def test_config1_every_step_nve(model_sr, oracle):
     """The 512-atom workload (4x4x4 cells, random weights plus the short-range
     term, atoms at rest, 1 T field), 100 NVE steps of 1 fs: every step against
-    one oracle step from the GPU's state, observables included; and the NVE
-    energy drift over the run, |E(t) - E(0)|/N <= 1e-4 eV/atom, with the
-    fitted slope reported."""
+    one oracle step from the GPU's state, observables included. Energy: the
+    short-range term strains the lattice, which relaxes and heats towards
+    1,900 K in these 100 fs; the total energy stays within 1e-3 eV/atom of its
+    start, and the same 100 fs at dt = 0.5 fs deviate four times less (a
+    second-order integrator), with no trend beyond the fluctuation."""
     from paper_2606_14073_amd import nepspin
     kw = dict(dt=1.0, B0=(0, 0, 1.0))
     s = W.config_small()
@@ -133,11 +135,18 @@ def test_config1_every_step_nve(model_sr, oracle):
     Et = np.array(Et)
     drift = np.abs(Et - E0).max() / s.n
     slope = np.polyfit(np.arange(1, 101), Et / s.n, 1)[0]
+    sim.close()
+    half = nepspin.Sim(model_sr, s.types, s.pos, s.spin, s.box, s.pbc, vel=np.zeros((s.n, 3)), colour=s.colour,
+                       params=_params(nepspin, dt=0.5, B0=(0, 0, 1.0)))
+    ob = half.integrate(200)
+    half.close()
+    drift_half = np.abs(ob[:, 1] + ob[:, 2] + ob[:, 3] - E0).max() / s.n
     print(f"config 1, 100 NVE steps: worst per-step pos {worst[0]:.2e} vel {worst[1]:.2e} spin {worst[2]:.2e} "
-          f"observables {worst[3]:.2e}; max |E(t)-E(0)|/N {drift:.2e} eV, slope {slope:.2e} eV/atom/step",
-          flush=True)
+          f"observables {worst[3]:.2e}; max |E(t)-E(0)|/N {drift:.2e} eV (dt 0.5 fs: {drift_half:.2e}), "
+          f"slope {slope:.2e} eV/atom/step, T at the end {ob[-1, 4]:.0f} K", flush=True)
     assert max(worst) <= TOL64
-    assert drift <= 1e-4
+    assert drift <= 1e-3 and 3.0 < drift / drift_half < 5.0
+    assert abs(slope) * 100 < drift
 
 
 def test_every_step_short_range_langevin(model_sr, oracle):
@@ -278,9 +287,14 @@ def test_config2_run_is_stable(config2_run):
     fe = s.types == 0
     print(f"config 2 after 1,000 steps: colour repairs {n_recolour}, closest pair {dmin:.3f} A, rms displacement "
           f"{rms:.3f} A, T_lattice last 100 steps {obs[-100:, 4].mean():.1f} K", flush=True)
+    dn = np.abs(np.linalg.norm(spin[fe], axis=1) - 1).max()
+    print(f"largest ||s| - 1| after 1,000 steps: {dn:.1e}", flush=True)
     assert dmin > 1.5
     assert n_recolour == 0
-    assert np.abs(np.linalg.norm(spin[fe], axis=1) - 1).max() <= 1e-14
+    # four rotations per step, each rounding |s| by about 1e-16: a random walk
+    # over 4,000 rotations, whose largest excursion among 131,072 spins is a
+    # few 1e-14
+    assert dn <= 1e-13
 
 
 def test_crystal_screen_2000_steps(model_sr):
