@@ -237,6 +237,9 @@ struct Engine {
     int *nbrA = nullptr, *cntA = nullptr, *cntFeA = nullptr, *revA = nullptr, *a2r = nullptr;
     int *cell_of = nullptr, *cell_cnt = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_atoms = nullptr;
     int *flags = nullptr;
+    int *act_buf = nullptr;    // [2 cap_rep] 'active' words to set on a re-layout (-1: leave)
+    d4 *stage_buf = nullptr;   // staging of resident state across a re-layout (grow-only)
+    size_t stage_cap = 0;
     void *work = nullptr;      // real-typed work arrays, one allocation
     size_t work_bytes = 0;
     Work<double> w64{};
@@ -307,9 +310,12 @@ struct Engine {
         put(nbrA); put(cntA); put(cntFeA); put(revA); put(a2r);
         put(cell_of); put(cell_cnt); put(cell_start); put(cell_fill); put(cell_atoms);
         put(flags); put(chunks); put(chunk_ptr); put(col_idx); put(colpos); put(col_rid); put(cpl_j); put(cpl_n);
-        put(partial); put(obs);
+        put(partial); put(obs); put(act_buf);
         if (work && !arena) (void)hipFree(work);
         work = nullptr;
+        if (stage_buf) (void)hipFree(stage_buf);
+        stage_buf = nullptr;
+        stage_cap = 0;
         cap = cap_fe = cap_cells = cap_rep = cap_chunks = cap_obs = cap_col = 0;
         for (auto e : prof_pool) (void)hipEventDestroy(e);
         prof_pool.clear();
@@ -446,9 +452,9 @@ struct Engine {
             cap_cells = c;
         }
         if (nrep > cap_rep) {
-            put(rep); put(chunk_ptr); put(obs);
+            put(rep); put(chunk_ptr); put(obs); put(act_buf);
             size_t c = std::max<size_t>(nrep, 2 * cap_rep);
-            if ((rc = get(&rep, c)) || (rc = get(&chunk_ptr, c + 1))) return rc;
+            if ((rc = get(&rep, c)) || (rc = get(&chunk_ptr, c + 1)) || (rc = get(&act_buf, 2 * c))) return rc;
             cap_rep = c;
             cap_obs = 0;
         }
@@ -538,17 +544,21 @@ struct Engine {
             stage_off[k] = stage_n;
             stage_n += moved[k]->n;
         }
-        struct Staging {   // released on every way out of this function
-            d4 *p = nullptr;
-            ~Staging() {
-                if (p) (void)hipFree(p);
+        // a grow-only device buffer kept by the engine, so that admissions
+        // and retirements do not allocate each time
+        if (stage_n && !arena && 5 * stage_n > stage_cap) {
+            if (stage_buf) (void)hipFree(stage_buf);
+            stage_buf = nullptr;
+            stage_cap = 0;
+            const size_t want = 5 * std::max(stage_n, stage_cap / 5 + stage_cap / 20);
+            if (hipMalloc((void **)&stage_buf, want * sizeof(d4)) == hipSuccess) {
+                stage_cap = want;
+            } else {
+                (void)hipGetLastError();
+                stage_buf = nullptr;
             }
-        } staging;
-        if (stage_n && !arena && hipMalloc((void **)&staging.p, 5 * stage_n * sizeof(d4)) != hipSuccess) {
-            (void)hipGetLastError();
-            staging.p = nullptr;
         }
-        d4 *const stage = staging.p;
+        d4 *const stage = stage_n && stage_buf && 5 * stage_n <= stage_cap ? stage_buf : nullptr;
         std::vector<std::vector<d4>> snap(stage ? 0 : moved.size() * 5);
         for (size_t k = 0; k < moved.size(); k++) {
             Replica *r = moved[k];
@@ -692,11 +702,7 @@ struct Engine {
                 }
             }
         }
-        if (stage) {
-            HIPCHK(hipStreamSynchronize(st));
-            (void)hipFree(staging.p);
-            staging.p = nullptr;
-        }
+        if (stage) HIPCHK(hipStreamSynchronize(st));
         // clear the error flags, force a neighbour rebuild, then F and H
         int hflags[NFLAGS] = {0};
         hflags[F_REBUILD] = 1;
@@ -705,7 +711,29 @@ struct Engine {
         if (N) {
             const Sys S = sys();
             launch_rebuild(S, RC_R + max_skin(), RC_A + max_skin(), st);
-            evaluate(spin);
+            // Replicas carried over from the previous layout keep their forces
+            // and fields: neighbour order inside a replica does not depend on
+            // where the replica sits, so an evaluation here would reproduce
+            // them bitwise. Only the replicas new to the device are evaluated,
+            // the others being marked inactive meanwhile.
+            if (moved.empty()) {
+                evaluate(spin);
+            } else if (moved.size() < reps.size()) {
+                // only the 'active' words change: the rebuild may have set
+                // failure bits in the replica records, which must survive
+                std::vector<int> off(reps.size(), -1), back(reps.size(), -1);
+                for (Replica *r : moved) {
+                    off[r->slot] = 0;
+                    back[r->slot] = h_rep[r->slot].active;
+                }
+                HIPCHK(hipMemcpyAsync(act_buf, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
+                launch_set_active(rep, act_buf, (int)reps.size(), st);
+                evaluate(spin);
+                HIPCHK(hipMemcpyAsync(act_buf + reps.size(), back.data(), back.size() * sizeof(int),
+                                      hipMemcpyHostToDevice, st));
+                launch_set_active(rep, act_buf + reps.size(), (int)reps.size(), st);
+                HIPCHK(hipStreamSynchronize(st));
+            }
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));

@@ -104,6 +104,8 @@ void launch_spin_prep(const Sys &S, hipStream_t st);
 void launch_spin_restore(const Sys &S, hipStream_t st);
 void launch_spin_mid(const Sys &S, hipStream_t st);
 void launch_step_end(const Sys &S, hipStream_t st);
+// rep[r].active = act[r] for every r < n with act[r] >= 0
+void launch_set_active(RepDev *rep, const int *act, int n, hipStream_t st);
 // self-consistent midpoint: residual of the pass, per replica converged or
 // not, and with depth > 0 the mixing coefficients; sc_out[0] = replicas still
 // iterating, sc_out[1] = largest change, sc_out[2] = columns used, then gam

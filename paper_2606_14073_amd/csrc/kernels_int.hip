@@ -365,6 +365,11 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     }
 }
 
+__global__ void k_set_active(RepDev *rep, const int *act, int n) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n && act[r] >= 0) rep[r].active = act[r];
+}
+
 __global__ void k_step_end(Sys S) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= S.n_rep) return;
@@ -665,6 +670,9 @@ void launch_spin_mid(const Sys &S, hipStream_t st) {
 }
 void launch_step_end(const Sys &S, hipStream_t st) {
     if (S.n_rep) hipLaunchKernelGGL(k_step_end, dim3(nblk(S.n_rep, 64)), dim3(64), 0, st, S);
+}
+void launch_set_active(RepDev *rep, const int *act, int n, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(k_set_active, dim3(nblk(n, 64)), dim3(64), 0, st, rep, act, n);
 }
 int sc_part_blocks(int n_fe) { return nblk(n_fe, 256); }
 void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st) {
