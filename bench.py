@@ -160,6 +160,57 @@ def run_slab(model, nepspin, n_steps):
             "fp32_mixed": sim_rate(model, nepspin, s, v, ip, "fp32", n_steps)}
 
 
+def closest_pair(pos, box):
+    """closest atom pair of a slab periodic in x and y (free z), and its z extent"""
+    from scipy.spatial import cKDTree
+    L = np.asarray(box, dtype=float).reshape(-1)[:3]
+    p = pos.copy()
+    p[:, :2] %= L[:2]
+    p[:, 2] -= p[:, 2].min()
+    d, _ = cKDTree(p, boxsize=[L[0], L[1], p[:, 2].max() + 100.0]).query(p, k=2)
+    return float(d[:, 1].min()), float(p[:, 2].max())
+
+
+def run_slab_ramp(model, nepspin, n_steps, chunk=500):
+    """The slab workload over n_steps of its 20,000-step T/B ramp in chunks of
+    `chunk` steps, stopping at the first failure: per chunk the targets, the
+    lattice temperature, the energy, the magnetisation and the recolourings,
+    every 2,500 steps the closest pair (progress on stderr)."""
+    s = W.config_slab()
+    v = W.maxwell_boltzmann(s.types, 150.0)
+    ip = nepspin.integrator_params(dt=1.0, T0=150.0, T1=280.0, B0=(0, 0, 0), B1=(0, 0, 1.0), n_ramp=20000,
+                                   alpha_s=0.1, gamma_L=0.01, ensemble=1, seed=W.SEED_PHILOX)
+    sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                      precision="fp32")
+    n_fe = int((s.types == 0).sum())
+    done, t_run, nrc, err, rows = 0, 0.0, 0, None, []
+    while done < n_steps:
+        k = min(chunk, n_steps - done)
+        t0 = time.perf_counter()
+        try:
+            ob = sim.integrate(k)
+        except RuntimeError as e:
+            err = str(e)
+            break
+        t_run += time.perf_counter() - t0
+        done += k
+        nrc = sim.colour()[1]
+        f = min(done, 20000) / 20000
+        row = {"step": done, "T_target": round(150 + 130 * f, 1), "Bz_target": round(f, 4),
+               "T_lattice": round(float(ob[-min(k, 100):, 4].mean()), 1),
+               "E_pot_per_atom": round(float(ob[-1, 1]) / s.n, 5), "Mz_per_spin": round(float(ob[-1, 8]) / n_fe, 4),
+               "recolourings": nrc}
+        if done % 2500 == 0 or done == n_steps:
+            row["closest_pair_A"], row["z_extent_A"] = (round(x, 3) for x in closest_pair(sim.state()[0], s.box))
+        rows.append(row)
+        print(f"slab: {row}, {s.n * done / t_run:.4e} atom-steps/s", file=sys.stderr, flush=True)
+    sim.close()
+    return {"workload": "FeGe B20 slab 256x256x8 cells, 4,194,304 atoms, periodic x,y, free z, helix 700 A, "
+                        "T 150->280 K, B 0->1 T over 20,000 steps, FP32-mixed",
+            "steps_run": done, "steps_asked": n_steps, "stopped_by": err,
+            "atom_steps_per_s": s.n * done / t_run if t_run else None, "progress": rows}
+
+
 def run_self_consistent(model, nepspin, s, v, kw, n_steps, k1_ms_per_step, tol=1e-12):
     """The spin step iterated to a tolerance on the same workload, plain and
     with Anderson mixing (depth 3): passes per step and the cost of a step
@@ -208,9 +259,11 @@ def run_structural(nepspin, n_steps, warmup=3):
     return out
 
 
-def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
+def run_serving(model, nepspin, n_req, n_steps, rate, seed=7, budget_gb=0.0, max_slots=256):
     """Poisson arrivals of the serving request mix (cubic FeGe cells, N
-    log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed."""
+    log-uniform 2,048-262,144, T ~ U(50,300) K, B_z ~ U(0,1) T), FP32-mixed.
+    budget_gb caps the device memory the server may hold (0: free HBM less a
+    reserve). Prints progress to stderr every 20 s while replicas run."""
     reqs = W.serving_requests(n_req, rate=rate, seed=seed, n_steps=n_steps)
     built = []
     for r in reqs:
@@ -219,15 +272,25 @@ def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
         ip = nepspin.integrator_params(dt=1.0, T0=r.T, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, r.Bz),
                                        seed=r.seed)
         built.append((r, s, v, ip))
-    sv = nepspin.Server(model, precision="fp32", steps_per_batch=10, max_slots=256)
+    sv = nepspin.Server(model, precision="fp32", steps_per_batch=10, max_slots=max_slots,
+                        hbm_budget_bytes=int(budget_gb * (1 << 30)))
     t0 = time.perf_counter()
     ids = []
+    last = t0
     for r, s, v, ip in built:
         dt = r.t_arrival - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
         ids.append(sv.submit(s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
                              n_steps=r.n_steps))
+    while True:
+        done = sum(sv.poll(k)["state"] >= nepspin.SL_DONE for k in ids)
+        if done == len(ids):
+            break
+        if time.perf_counter() - last > 20:
+            last = time.perf_counter()
+            print(f"serving: {last - t0:.0f} s, {done}/{len(ids)} replicas done", file=sys.stderr, flush=True)
+        time.sleep(0.01)
     sv.drain()
     t1 = time.perf_counter()
     st = [sv.poll(k) for k in ids]
@@ -238,11 +301,12 @@ def run_serving(model, nepspin, n_req, n_steps, rate, seed=7):
     wait = [x["t_admit"] - x["t_submit"] for x in st]
     atoms = sum(s.n for _, s, _, _ in built)
     return {"requests": n_req, "steps_each": n_steps, "arrival_rate_per_s": rate,
+            "hbm_budget_gb": budget_gb or "free HBM less the reserve", "max_slots": max_slots,
             "atoms_total": atoms, "wall_s": round(t1 - t0, 3),
             "atom_steps_per_s": stats["atom_steps"] / (t1 - t0),
             "p50_step_latency_ms": 1e3 * float(np.median(lat50)),
             "p99_step_latency_ms": 1e3 * float(np.percentile(lat99, 99)),
-            "mean_queue_wait_s": float(np.mean(wait)),
+            "mean_queue_wait_s": float(np.mean(wait)), "max_queue_wait_s": float(np.max(wait)),
             "failed": int(sum(x["state"] != nepspin.SL_DONE for x in st)),
             "failures": [{"request": k, "cells": built[k][0].cells, "T": round(built[k][0].T, 1),
                           "Bz": round(built[k][0].Bz, 3), "error": x["error"], "steps_done": x["steps_done"]}
@@ -264,16 +328,19 @@ def kernel_source_hash(kernel="k_desc_angular<double>"):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel):
+def traffic_from_profile(kernel, n_atoms):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    if there is none or the kernel's sources changed since it was taken."""
+    if there is none, it was taken on another workload size, or the kernel's
+    sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
+        return None
+    if d.get("n_atoms") != n_atoms:
         return None
     k = d.get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != kernel_source_hash(kernel):
@@ -334,7 +401,7 @@ def roofline_of(group, prof, pc, n_steps, k_corr, s, real="double"):
         by = sweep_bytes_per_launch(pc, ncol, real_bytes=rb)
         ach = by / (avg * 1e-3) / 1e9
         return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK["hbm_gbs"],
-                "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": traffic_from_profile(kname),
+                "unit": "GB/s", "frac": round(ach / PEAK["hbm_gbs"], 4), "traffic": traffic_from_profile(kname, s.n),
                 "avg_launch_ms": round(avg, 5), "launches": nk, "bytes_per_launch": int(by)}
     fs = flops_per_step(group, pc, k_corr)
     if fs is None:
@@ -345,7 +412,7 @@ def roofline_of(group, prof, pc, n_steps, k_corr, s, real="double"):
     ach = fl / (avg * 1e-3) / 1e12
     peak = PEAK["fp64"] if real == "double" else PEAK["fp32"]
     out = {"kernel": kname, "bound": "mfma" if group == "readout" else "alu", "achieved": round(ach, 3),
-           "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic_from_profile(kname),
+           "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic_from_profile(kname, s.n),
            "avg_launch_ms": round(avg, 4), "launches": nl, "flop_per_launch": int(fl)}
     if real != "double":
         out["note"] = ("peak is the packed-FP32 vector rate; the kernels are built without packed FP32, whose "
@@ -408,10 +475,20 @@ def main():
     ap.add_argument("--water-steps", type=int, default=30)
     ap.add_argument("--water-only", action="store_true",
                     help="run only the structural-only NEP leg and print its result as one JSON line")
+    ap.add_argument("--crystal-only", action="store_true",
+                    help="run only the 262,144-atom crystal legs (FP64 and FP32-mixed) and print them as one JSON line")
     ap.add_argument("--sc-steps", type=int, default=20)
     ap.add_argument("--side-steps", type=int, default=50, help="timed steps of the 262,144-atom and slab legs")
     ap.add_argument("--serving-requests", type=int, default=24)
     ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-budget-gb", type=float, default=0.0,
+                    help="device-memory cap of the server (0: free HBM less a reserve)")
+    ap.add_argument("--serving-slots", type=int, default=256)
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg and print its result as one JSON line")
+    ap.add_argument("--slab-ramp", type=int, default=0, metavar="STEPS",
+                    help="run only the slab workload over STEPS steps of its ramp (stops at the first failure) "
+                         "and print the result as one JSON line")
     ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -451,6 +528,40 @@ def main():
         tot = sum(v[0] for v in prof.values()) or 1.0
         return {g: {"ms_per_step": round(m_ / n, 4), "share": round(m_ / tot, 4), "launches_per_step": n_ / n}
                 for g, (m_, n_) in prof.items()}
+
+    s2 = W.config_fp64_bench()
+    v2 = W.maxwell_boltzmann(s2.types, 300.0)
+
+    def crystal_leg():
+        pc2 = pair_counts(s2)
+        n2 = args.side_steps
+        leg = {"workload": "FeGe B20 32x32x32 cells, 262,144 atoms (131,072 spins), periodic, 300 K Langevin + "
+                           "stochastic LLG (alpha 0.1), dt 1 fs, K_corr 1, short-range term", "steps": n2}
+        _, p2 = run(s2, v2, "fp64", n2, tuple(nepspin.PROFILE_GROUPS))
+        leg["breakdown_ms_per_step"] = {g: b["ms_per_step"] for g, b in breakdown(p2, n2).items()}
+        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
+            dtx, _ = run(s2, v2, prec, n2)
+            leg[key] = s2.n * n2 / dtx
+            leg[key + "_ms_per_step"] = round(1e3 * dtx / n2, 3)
+        dom2 = max(p2, key=lambda g: p2[g][0])
+        leg["dominant"] = dom2
+        leg["roofline"] = roofline_of(dom2, p2, pc2, n2, kw["K_corr"], s2)
+        return leg
+
+    if args.serving_only:
+        print(json.dumps(run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0,
+                                     budget_gb=args.serving_budget_gb, max_slots=args.serving_slots)), flush=True)
+        model.close()
+        return
+    if args.slab_ramp:
+        print(json.dumps(run_slab_ramp(model, nepspin, args.slab_ramp)), flush=True)
+        model.close()
+        return
+
+    if args.crystal_only:
+        print(json.dumps(crystal_leg()), flush=True)
+        model.close()
+        return
 
     # Headline: the largest single-GPU workload, 96^3 cells = 7,077,888 atoms,
     # FP64, 300 K Langevin + stochastic LLG, K_corr 1. An untimed profiling
@@ -507,22 +618,8 @@ def main():
         print(f"fp32-mixed: {K} steps in {dt32:.3f} s -> {f32['value']:.4e} atom-steps/s (dominant: {dom32}); "
               f"errors {f32['errors_vs_fp64']}", file=sys.stderr, flush=True)
 
-    s2 = W.config_fp64_bench()
-    v2 = W.maxwell_boltzmann(s2.types, 300.0)
     if not args.no_262k:
-        pc2 = pair_counts(s2)
-        n2 = args.side_steps
-        leg = {"workload": "FeGe B20 32x32x32 cells, 262,144 atoms (131,072 spins), periodic, 300 K Langevin + "
-                           "stochastic LLG (alpha 0.1), dt 1 fs, K_corr 1, short-range term", "steps": n2}
-        _, p2 = run(s2, v2, "fp64", n2, tuple(nepspin.PROFILE_GROUPS))
-        leg["breakdown_ms_per_step"] = {g: b["ms_per_step"] for g, b in breakdown(p2, n2).items()}
-        for prec, key in (("fp64", "fp64"), ("fp32", "fp32_mixed")):
-            dtx, _ = run(s2, v2, prec, n2)
-            leg[key] = s2.n * n2 / dtx
-            leg[key + "_ms_per_step"] = round(1e3 * dtx / n2, 3)
-        dom2 = max(p2, key=lambda g: p2[g][0])
-        leg["dominant"] = dom2
-        leg["roofline"] = roofline_of(dom2, p2, pc2, n2, kw["K_corr"], s2)
+        leg = crystal_leg()
         extra["fege_262k"] = leg
         print(f"262,144 atoms: {leg}", file=sys.stderr, flush=True)
         if not args.no_sc:
@@ -539,7 +636,8 @@ def main():
         print(f"structural-only NEP, water: {extra['structural_water']}", file=sys.stderr, flush=True)
 
     if not args.no_serving:
-        extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0)
+        extra["serving"] = run_serving(model, nepspin, args.serving_requests, args.serving_steps, 20.0,
+                                       budget_gb=args.serving_budget_gb, max_slots=args.serving_slots)
         print(f"serving: {extra['serving']}", file=sys.stderr, flush=True)
     model.close()
 
