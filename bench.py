@@ -182,7 +182,6 @@ def run_slab_ramp(model, nepspin, n_steps, chunk=500):
                                    alpha_s=0.1, gamma_L=0.01, ensemble=1, seed=W.SEED_PHILOX)
     sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
                       precision="fp32")
-    n_fe = int((s.types == 0).sum())
     done, t_run, nrc, err, rows = 0, 0.0, 0, None, []
     while done < n_steps:
         k = min(chunk, n_steps - done)
@@ -198,7 +197,7 @@ def run_slab_ramp(model, nepspin, n_steps, chunk=500):
         f = min(done, 20000) / 20000
         row = {"step": done, "T_target": round(150 + 130 * f, 1), "Bz_target": round(f, 4),
                "T_lattice": round(float(ob[-min(k, 100):, 4].mean()), 1),
-               "E_pot_per_atom": round(float(ob[-1, 1]) / s.n, 5), "Mz_per_spin": round(float(ob[-1, 8]) / n_fe, 4),
+               "E_pot_per_atom": round(float(ob[-1, 1]) / s.n, 5), "Mz_mean": round(float(ob[-1, 8]), 5),
                "recolourings": nrc}
         if done % 2500 == 0 or done == n_steps:
             row["closest_pair_A"], row["z_extent_A"] = (round(x, 3) for x in closest_pair(sim.state()[0], s.box))
@@ -340,9 +339,11 @@ def traffic_from_profile(kernel, n_atoms):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("n_atoms") != n_atoms:
+    sets = d.get("workloads", [d])
+    match = [w for w in sets if w.get("n_atoms") == n_atoms]
+    if not match:
         return None
-    k = d.get("kernels", {}).get(kernel)
+    k = match[0].get("kernels", {}).get(kernel)
     if not k or k.get("source_hash") != kernel_source_hash(kernel):
         return None
     return k.get("bytes_per_launch")

@@ -74,6 +74,112 @@ def test_longitudinal_every_step_matches_oracle(oracle, gamma):
     assert max(worst[:4]) <= TOL64 and worst[4] == 0
 
 
+def test_longitudinal_selfconsistent_matches_oracle(oracle):
+    """the self-consistent midpoint (corrector passes until the spins change
+    by at most 1e-13, plain and with Anderson mixing) with variable lengths:
+    every step against one oracle step from the GPU's state"""
+    from paper_2606_14073_amd import nepspin
+    s = W.config_small()
+    spin0, _ = _varied_lengths(s, seed=3)
+    p = W.random_params()
+    m = _model(nepspin)
+    for depth in (0, 3):
+        kw = dict(dt=1.0, T0=300.0, gamma_L=0.01, ensemble=1, B0=(0, 0, 1.0), longitudinal=1, gamma_lsf=0.05,
+                  sc_tol=1e-13, sc_max=40, sc_depth=depth)
+        sim = nepspin.Sim(m, s.types, s.pos, spin0, s.box, s.pbc, vel=W.maxwell_boltzmann(s.types, 300.0),
+                          colour=s.colour, params=nepspin.integrator_params(**kw))
+        okw = oracle.step_params(zbl=W.SHORT_RANGE_FEGE, landau=LANDAU, **_oracle_kw(kw))
+        prev = sim.state()
+        worst = [0.0] * 3
+        passes = []
+        for k in range(6):
+            ob = sim.integrate(1)[0]
+            cur = sim.state()
+            rp, rv, rs, _, rob = oracle.run(s.types, prev[0], prev[1], prev[2], s.box, s.pbc, p, s.colour, okw,
+                                            1, step0=prev[3])
+            e = [pos_error(cur[0], rp, prev[0], s.box, s.pbc), rel_inf(cur[1], rv), np.abs(cur[2] - rs).max()]
+            worst = [max(a, b) for a, b in zip(worst, e)]
+            passes.append((int(ob[9]), int(rob[0, 9])))
+            prev = cur
+        sim.close()
+        print(f"longitudinal, self-consistent, depth {depth}: worst per-step pos {worst[0]:.2e} "
+              f"vel {worst[1]:.2e} spin {worst[2]:.2e}; passes (GPU, oracle) {passes}", flush=True)
+        assert max(worst) <= TOL64
+        assert all(abs(a - b) <= 1 for a, b in passes) and min(a for a, _ in passes) >= 2
+    m.close()
+
+
+def test_longitudinal_fp32_mixed_step_error(oracle):
+    """FP32-mixed with variable lengths and the longitudinal bath: one step
+    from the same state against the FP64 oracle"""
+    from paper_2606_14073_amd import nepspin
+    s = W.fege_lattice(7, 7, 7)
+    spin0, _ = _varied_lengths(s, seed=5)
+    p = W.random_params()
+    m = _model(nepspin)
+    kw = dict(dt=1.0, T0=300.0, gamma_L=0.01, ensemble=1, B0=(0, 0, 1.0), longitudinal=1, gamma_lsf=0.05)
+    sim = nepspin.Sim(m, s.types, s.pos, spin0, s.box, s.pbc, vel=W.maxwell_boltzmann(s.types, 300.0),
+                      colour=s.colour, params=nepspin.integrator_params(**kw), precision="fp32")
+    a = sim.state()
+    sim.integrate(1)
+    b = sim.state()
+    sim.close()
+    m.close()
+    rp, rv, rs, _, _ = oracle.run(s.types, a[0], a[1], a[2], s.box, s.pbc, p, s.colour,
+                                  oracle.step_params(zbl=W.SHORT_RANGE_FEGE, landau=LANDAU, **_oracle_kw(kw)), 1,
+                                  step0=a[3])
+    ep, ev, es = pos_error(b[0], rp, a[0], s.box, s.pbc), rel_inf(b[1], rv), np.abs(b[2] - rs).max()
+    print(f"longitudinal fp32 one step: pos {ep:.2e} vel {ev:.2e} spin {es:.2e}", flush=True)
+    assert ep < 1e-5 and ev < 1e-5 and es < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_longitudinal_replica_batching_invariant(precision):
+    """a replica with variable lengths served alone, served beside replicas
+    with and without longitudinal dynamics, and run as a direct simulation:
+    bitwise the same state"""
+    from paper_2606_14073_amd import nepspin
+    m = _model(nepspin)
+
+    def req(cells, seed, lsf, T=250.0):
+        s = W.fege_lattice(cells, cells, cells, seed=seed)
+        spin, _ = _varied_lengths(s, seed=seed) if lsf else (s.spin, None)
+        ip = nepspin.integrator_params(dt=1.0, T0=T, alpha_s=0.0 if lsf else 0.1, gamma_L=0.01, ensemble=1,
+                                       B0=(0, 0, 0.5), longitudinal=lsf, gamma_lsf=0.05 if lsf else 0.0,
+                                       seed=300 + seed)
+        return s, spin, W.maxwell_boltzmann(s.types, T, seed=seed + 1), ip
+
+    def submit(sv, r, n):
+        s, spin, v, ip = r
+        return sv.submit(s.types, s.pos, spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip, n_steps=n)
+
+    X, n = req(4, 21, 1), 9
+    sv = nepspin.Server(m, precision=precision, steps_per_batch=4, max_slots=8)
+    a = submit(sv, X, n)
+    sv.drain()
+    alone = sv.fetch(a)
+    sv.close()
+    sv = nepspin.Server(m, precision=precision, steps_per_batch=3, max_slots=8)
+    ids = [submit(sv, req(5, 22, 0), 6)]
+    b = submit(sv, X, n)
+    ids.append(submit(sv, req(4, 23, 1, T=80.0), 11))
+    sv.drain()
+    mixed = sv.fetch(b)
+    for k in ids:
+        assert sv.poll(k)["state"] == nepspin.SL_DONE
+    sv.close()
+    s, spin, v, ip = X
+    sim = nepspin.Sim(m, s.types, s.pos, spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip, precision=precision)
+    sim.integrate(n)
+    direct = sim.state()
+    sim.close()
+    m.close()
+    for x, y, z in zip(alone[:3], mixed[:3], direct[:3]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+    fe = s.types == 0
+    assert np.ptp(np.linalg.norm(alone[2][fe], axis=1)) > 0.1   # the lengths stay spread
+
+
 def test_longitudinal_lengths_kept_without_damping():
     """gamma = 0: only the rotations act; every spin keeps its own length"""
     from paper_2606_14073_amd import nepspin
