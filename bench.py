@@ -294,6 +294,7 @@ def run_serving(model, nepspin, n_req, n_steps, rate, seed=7, budget_gb=0.0, max
     t1 = time.perf_counter()
     st = [sv.poll(k) for k in ids]
     stats = sv.stats()
+    host = sv.host_stats()
     sv.close()
     lat50 = [x["step_latency_p50"] for x in st]
     lat99 = [x["step_latency_p99"] for x in st]
@@ -306,6 +307,9 @@ def run_serving(model, nepspin, n_req, n_steps, rate, seed=7, budget_gb=0.0, max
             "p50_step_latency_ms": 1e3 * float(np.median(lat50)),
             "p99_step_latency_ms": 1e3 * float(np.percentile(lat99, 99)),
             "mean_queue_wait_s": float(np.mean(wait)), "max_queue_wait_s": float(np.max(wait)),
+            "batched_steps": stats["batched_steps"], "batch_busy_s": round(stats["busy_s"], 3),
+            "relayouts": host["relayouts"], "relayout_s": round(host["relayout_s"], 3),
+            "host_gap_s": round(host["gap_s"], 3),
             "failed": int(sum(x["state"] != nepspin.SL_DONE for x in st)),
             "failures": [{"request": k, "cells": built[k][0].cells, "T": round(built[k][0].T, 1),
                           "Bz": round(built[k][0].Bz, 3), "error": x["error"], "steps_done": x["steps_done"]}

@@ -414,6 +414,15 @@ int sl_server_drain(sl_server *sv);
  * busy seconds. Any pointer may be NULL. */
 int sl_server_stats(sl_server *sv, int64_t *batched_steps, double *atom_steps, double *busy_s);
 
+/* Host time between batches since creation: the number of re-layouts (an
+ * admission, a retirement or a recolouring changed the resident set), the
+ * seconds they took (state staging, list rebuild, evaluation of the new
+ * replicas, checks), and the seconds of all gaps between the end of one
+ * batch and the start of the next (re-layouts, retirement downloads, host
+ * bookkeeping). Each gap is also counted in the latency of the first step of
+ * the batch that follows it. Any pointer may be NULL. */
+int sl_server_host_stats(sl_server *sv, int64_t *relayouts, double *relayout_s, double *gap_s);
+
 int sl_server_destroy(sl_server *sv);
 
 #ifdef __cplusplus

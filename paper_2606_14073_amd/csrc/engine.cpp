@@ -1719,6 +1719,9 @@ struct sl_server {
     size_t budget = 0, used = 0;
     int64_t batched_steps = 0;
     double atom_steps = 0, busy = 0;
+    // host time between batches: re-layouts (count, seconds) and all gaps
+    int64_t relayouts = 0;
+    double relayout_s = 0, gap_s = 0;
     size_t pending = 0;
 
     void run();
@@ -1796,10 +1799,13 @@ void sl_server::run() {
                 changed = true;
             }
         if (!rc && (changed || next != eng.reps)) {
+            const double tl = now_s();
             rc = eng.set_layout(next);
             std::vector<int> bad;
             if (!rc) rc = settle_layout(eng, bad, false);
             std::lock_guard<std::mutex> lk(mu);
+            relayouts++;
+            relayout_s += now_s() - tl;
             resident = next;
             for (size_t a = 0; a < bad.size() && !rc; a++)
                 if (bad[a] && next[a]->state == SL_RUNNING) {
@@ -1849,12 +1855,14 @@ void sl_server::run() {
             lat[q] = ms * 1e-3;
         }
         // the first step of a batch also waited for the host
-        if (last_done_t > 0) lat[0] += std::max(0.0, tb - last_done_t);
+        const double gap = last_done_t > 0 ? std::max(0.0, tb - last_done_t) : 0.0;
+        lat[0] += gap;
         last_done_t = te;
         {
             std::lock_guard<std::mutex> lk(mu);
             batched_steps += k;
             busy += te - tb;
+            gap_s += gap;
             for (size_t a = 0; a < nr; a++) {
                 Replica *r = next[a];
                 if (r->state != SL_RUNNING) continue;
@@ -1998,6 +2006,15 @@ extern "C" int sl_server_stats(sl_server *sv, int64_t *batched_steps, double *at
     if (batched_steps) *batched_steps = sv->batched_steps;
     if (atom_steps) *atom_steps = sv->atom_steps;
     if (busy_s) *busy_s = sv->busy;
+    return SL_OK;
+}
+
+extern "C" int sl_server_host_stats(sl_server *sv, int64_t *relayouts, double *relayout_s, double *gap_s) {
+    if (!sv) return fail(SL_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (relayouts) *relayouts = sv->relayouts;
+    if (relayout_s) *relayout_s = sv->relayout_s;
+    if (gap_s) *gap_s = sv->gap_s;
     return SL_OK;
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ["sl_last_error", "nep_model_create", "nep_model_destroy", "nep_spin_e
            "nep_spin_descriptors",
            "sl_create", "sl_integrate_steps", "sl_get_state", "sl_set_state", "sl_destroy", "sl_server_create",
            "sl_replica_submit", "sl_replica_poll", "sl_replica_fetch", "sl_server_drain", "sl_server_stats",
-           "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour", "sl_replica_bytes"]
+           "sl_server_host_stats", "sl_server_destroy", "sl_profile_enable", "sl_profile_read", "sl_get_colour", "sl_replica_bytes"]
 
 PROFILE_GROUPS = ["desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "gather", "couplings",
                   "sweep", "nlist", "integrate", "pairs", "bwd_angular_1"]
@@ -370,6 +370,12 @@ class Server:
         a, b, c = ct.c_int64(), ct.c_double(), ct.c_double()
         _check(load().sl_server_stats(self.h, ct.byref(a), ct.byref(b), ct.byref(c)))
         return {"batched_steps": a.value, "atom_steps": b.value, "busy_s": c.value}
+
+    def host_stats(self):
+        """re-layouts, their seconds, and the seconds of all gaps between batches"""
+        a, b, c = ct.c_int64(), ct.c_double(), ct.c_double()
+        _check(load().sl_server_host_stats(self.h, ct.byref(a), ct.byref(b), ct.byref(c)))
+        return {"relayouts": a.value, "relayout_s": b.value, "gap_s": c.value}
 
     def close(self):
         if self.h:

@@ -62,6 +62,8 @@ def test_alone_equals_mix_equals_direct(model, precision):
         assert sv.poll(k)["state"] == nepspin.SL_DONE
     stats = sv.stats()
     assert stats["atom_steps"] == pytest.approx(sum(o[0].n * m for o, m in zip(others, (7, 20, 4))) + X[0].n * n)
+    host = sv.host_stats()   # four admissions and four retirements, some sharing a re-layout
+    assert 2 <= host["relayouts"] <= 8 and host["relayout_s"] > 0 and host["gap_s"] >= 0
     sv.close()
     for x, y in zip(alone[:3], mixed[:3]):
         assert np.array_equal(x, y)
