@@ -124,6 +124,31 @@ def flops_per_step(group, pc, k_corr=1):
     return None
 
 
+def step_model(pc, k_corr, ms_per_step):
+    """Whole-step FLOPs per atom-step two ways: the survey-style estimate
+    (per-pair and per-atom figures with the run's neighbour counts: 3 forwards,
+    3 read-outs, 2 assemblies at 0.6 of the magnetic forward, the backward at 3
+    forwards, 4 sweep visits per spin), and the sum of this file's per-group
+    work model plus the sweep; with the achieved rate against the FP64 peak"""
+    N, Nfe = pc["N"], pc["N_fe"]
+    r_at, a_at = pc["R"] / N, pc["A"] / N
+    ff_r, ff_a = pc["R_fefe"] / Nfe, pc["A_fefe"] / Nfe
+    mag = (Nfe / N) * (ff_r * (36 + 4 * 2 * 81 + 72) + ff_a * (126 + 336 + 10) + 672)
+    fwd = r_at * (66 + 2 * 9 * 9) + mag + a_at * (56 + 2 * 63 + 60 + 2 * 7 * 24)
+    mlp = 2 * 2 * 102 * 64
+    sweep = (Nfe / N) * 2 * (1 + k_corr) * (ff_r * 30 + 320)
+    survey = (2 + k_corr) * (fwd + mlp) + (1 + k_corr) * 0.6 * mag + 3 * fwd + sweep
+    groups = ("desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "bwd_angular_1",
+              "couplings", "pairs")
+    counted = sum(flops_per_step(g, pc, k_corr) for g in groups) / N + sweep
+    out = {}
+    for key, f in (("survey_estimate", survey), ("work_model", counted)):
+        t = f * N / (ms_per_step * 1e-3) / 1e12
+        out[key] = {"flop_per_atom_step": round(f), "achieved_tflops": round(t, 3),
+                    "frac_fp64_peak": round(t / PEAK["fp64"], 4)}
+    return out
+
+
 def sweep_bytes_per_launch(pc, n_colours, real_bytes=8):
     """Algorithmic HBM bytes of one colour-class launch of the spin sweep: per
     spin its couplings inside rc_R (J, D, K, rhat and the neighbour index) and
@@ -596,7 +621,7 @@ def main():
         groups[g] = {"avg_launch_ms": round(ms / nl, 4), "launches": nl, "flop_per_step": int(fs),
                      "achieved_tflops": round(ach, 3), "frac_fp64_peak": round(ach / PEAK["fp64"], 4)}
     extra = {"breakdown_ms_per_step": {g: b["ms_per_step"] for g, b in breakdown(prof_all, n_prof).items()},
-             "kernel_rooflines": groups}
+             "kernel_rooflines": groups, "step_model": step_model(pc3, kw["K_corr"], 1e3 * dt64 / K)}
 
     if not args.no_fp32:
         _, p32 = run(s3, v3, "fp32", n_prof, tuple(nepspin.PROFILE_GROUPS), warm=2)
