@@ -48,18 +48,7 @@ __device__ inline void load_spin(const d4 *sp, int j, real s[3]) {
     s[2] = (real)v.z;
 }
 
-// displacement in FP64, then cast
-template <typename real>
-__device__ inline real geom(const Sys &S, const Img &R, const d4 &pi, int j, real d[3]) {
-    double dx, dy, dz;
-    min_image(R, pi, S.pos[j], dx, dy, dz);
-    d[0] = (real)dx;
-    d[1] = (real)dy;
-    d[2] = (real)dz;
-    return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-}
-
-// displacement to an already loaded neighbour position
+// displacement to an already loaded neighbour position, in FP64, then cast
 template <typename real>
 __device__ inline real geom_p(const Img &R, const d4 &pi, const d4 &pj, real d[3]) {
     double dx, dy, dz;
@@ -1286,10 +1275,17 @@ __global__ void __launch_bounds__(64) k_assemble_angular(Sys S, const real *__re
     const real rc = (real)RC_A, rc2 = rc * rc;
     const int nfe = S.cntFeA[i];
     const size_t ld = S.N, lf = S.N_fe;
+    // this lane's neighbour index two rounds ahead, its position one round ahead
+    int j1 = lane < nfe ? S.nbrA[(size_t)lane * ld + i] : 0;
+    int j2 = lane + 8 < nfe ? S.nbrA[(size_t)(lane + 8) * ld + i] : j1;
+    d4 p1 = S.pos[j1];
     for (int s = lane; s < nfe; s += 8) {
-        const int j = S.nbrA[s * ld + i];
+        const d4 pj = p1;
+        j1 = j2;
+        p1 = S.pos[j1];
+        if (s + 16 < nfe) j2 = S.nbrA[(size_t)(s + 16) * ld + i];
         real d[3];
-        const real r2 = geom(S, R, pi, j, d);
+        const real r2 = geom_p(R, pi, pj, d);
         if (r2 >= rc2) continue;
         real r, ir;
         r_and_inv(r2, r, ir);
@@ -1343,10 +1339,18 @@ __global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__res
     {
         real CS[NB];
         contract((C + P_CSI), Fp + D_SI, NR, CS);
+        // neighbour index two slots ahead, its position one slot ahead
+        int j1 = 0 < nfe ? S.nbrR[i] : 0;
+        int j2 = 1 < nfe ? S.nbrR[ld + i] : j1;
+        d4 p1 = S.pos[j1];
         for (int s = 0; s < nfe; s++) {
-            const int j = S.nbrR[s * ld + i];
+            const int j = j1;
+            const d4 pj = p1;
+            j1 = j2;
+            p1 = S.pos[j1];
+            if (s + 2 < nfe) j2 = S.nbrR[(size_t)(s + 2) * ld + i];
             real d[3];
-            const real r2 = geom(S, R, pi, j, d);
+            const real r2 = geom_p(R, pi, pj, d);
             if (r2 >= rc2) continue;
             real r, ir;
             r_and_inv(r2, r, ir);
@@ -1386,10 +1390,16 @@ __global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__res
     {
         real CS[NB];
         contract((C + P_CSI) + 1 * NR * NB, Fp + D_SI, NR, CS);
+        int j1 = nfe_all < cnt ? S.nbrR[(size_t)nfe_all * ld + i] : 0;
+        int j2 = nfe_all + 1 < cnt ? S.nbrR[(size_t)(nfe_all + 1) * ld + i] : j1;
+        d4 p1 = S.pos[j1];
         for (int s = nfe_all; s < cnt; s++) {
-            const int j = S.nbrR[s * ld + i];
+            const d4 pj = p1;
+            j1 = j2;
+            p1 = S.pos[j1];
+            if (s + 2 < cnt) j2 = S.nbrR[(size_t)(s + 2) * ld + i];
             real d[3];
-            const real r2 = geom(S, R, pi, j, d);
+            const real r2 = geom_p(R, pi, pj, d);
             if (r2 >= rc2) continue;
             real r, ir;
             r_and_inv(r2, r, ir);
