@@ -74,6 +74,42 @@ def test_longitudinal_every_step_matches_oracle(oracle, gamma):
     assert max(worst[:4]) <= TOL64 and worst[4] == 0
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_eval_with_moment_length_term(oracle, precision):
+    """one evaluation with spins of lengths 0.7-1.3 and the onsite
+    moment-length term: E, E_i, F, H against the oracle (FP64 to 1e-12;
+    FP32-mixed within its bounds); the term's own energy and field are
+    checked against a|s|^2 + b|s|^4 and -(2a + 4b|s|^2) s"""
+    from paper_2606_14073_amd import nepspin
+    s = W.fege_lattice(4, 4, 4, seed=9)
+    spin, lens = _varied_lengths(s, 0.7, 1.3, seed=9)
+    p = W.random_params()
+    B = (0.0, 0.2, 0.7)
+    m = _model(nepspin)
+    got = m.eval(s.types, s.pos, spin, s.box, s.pbc, B=B, precision=precision, want=("E", "Ei", "F", "H"))
+    m.close()
+    ref = oracle.evaluate(s.types, s.pos, spin, s.box, s.pbc, p, B=B, want=("E", "F", "H", "Ei"),
+                          zbl=W.SHORT_RANGE_FEGE, landau=LANDAU)
+    plain = oracle.evaluate(s.types, s.pos, spin, s.box, s.pbc, p, B=B, want=("E", "H", "Ei"),
+                            zbl=W.SHORT_RANGE_FEGE)
+    a, b = LANDAU
+    fe = s.types == 0
+    np.testing.assert_allclose((ref["Ei"] - plain["Ei"])[fe], a * lens[fe] ** 2 + b * lens[fe] ** 4, rtol=1e-12,
+                               atol=1e-13)
+    np.testing.assert_allclose((ref["H"] - plain["H"])[fe], -(2 * a + 4 * b * lens[fe, None] ** 2) * spin[fe],
+                               rtol=1e-11, atol=1e-12)
+    etot = ref["E"] + ref["Ez"]
+    if precision == "fp64":
+        assert rel_inf(got["Ei"], ref["Ei"]) <= TOL64
+        assert abs(got["E"] - etot) <= TOL64 * abs(etot)
+        assert rel_inf(got["F"], ref["F"]) <= TOL64
+        assert rel_inf(got["H"], ref["H"]) <= TOL64
+    else:
+        assert abs(got["E"] - etot) / s.n <= 1e-6
+        assert np.linalg.norm(got["F"] - ref["F"]) <= 1e-5 * np.linalg.norm(ref["F"])
+        assert np.linalg.norm(got["H"] - ref["H"]) <= 1e-5 * np.linalg.norm(ref["H"])
+
+
 def test_longitudinal_selfconsistent_matches_oracle(oracle):
     """the self-consistent midpoint (corrector passes until the spins change
     by at most 1e-13, plain and with Anderson mixing) with variable lengths:

@@ -46,6 +46,30 @@ def test_structural_eval_matches_oracle(smodel, oracle, name, spec):
     assert np.abs(got["H"]).max() == 0.0
 
 
+def test_structural_short_range_matches_oracle(oracle):
+    """the structural-only model with the short-range term (Z = 8, 1 for O
+    and H, switched off over 0.8-1.2 A, so that the O-H bonds sit inside the
+    switch): E, E_i, F against the oracle, periodic and free"""
+    from paper_2606_14073_amd import nepspin
+    zbl = (8.0, 1.0, 0.8, 1.2)
+    p = W.random_params_structural()
+    m = nepspin.Model(p, short_range=zbl)
+    for free in (False, True):
+        s = W.water_box(5, noise=0.05, seed=4)
+        box, pbc = (np.zeros(3), np.zeros(3, np.int32)) if free else (s.box, s.pbc)
+        obox = np.array([1e4] * 3) if free else s.box
+        ref = oracle.evaluate(s.types, s.pos, None, obox, pbc, p, want=("E", "F", "Ei"), zbl=zbl)
+        plain = oracle.evaluate(s.types, s.pos, None, obox, pbc, p, want=("E",))
+        got = m.eval(s.types, s.pos, None, box, pbc, want=("E", "Ei", "F"))
+        print(f"water 5^3 {'free' if free else 'periodic'} with the short-range term: E {ref['E']:.6f} "
+              f"(without {plain['E']:.6f})", flush=True)
+        assert ref["E"] - plain["E"] > 1.0          # the term acts on the bonds
+        assert rel_inf(got["Ei"], ref["Ei"]) <= TOL64
+        assert abs(got["E"] - ref["E"]) <= TOL64 * abs(ref["E"])
+        assert rel_inf(got["F"], ref["F"]) <= TOL64
+    m.close()
+
+
 def test_structural_fp32_error(smodel):
     s = W.water_box(12, noise=0.05)
     ref = smodel.eval(s.types, s.pos, None, s.box, s.pbc, want=("E", "F"))
