@@ -125,8 +125,8 @@ def flops_per_step(group, pc, k_corr=1):
 
 
 def step_model(pc, k_corr, ms_per_step):
-    """Whole-step FLOPs per atom-step two ways: the survey-style estimate
-    (per-pair and per-atom figures with the run's neighbour counts: 3 forwards,
+    """Whole-step FLOPs per atom-step two ways: an estimate of the method's
+    work (per-pair and per-atom figures with the run's neighbour counts: 3 forwards,
     3 read-outs, 2 assemblies at 0.6 of the magnetic forward, the backward at 3
     forwards, 4 sweep visits per spin), and the sum of this file's per-group
     work model plus the sweep; with the achieved rate against the FP64 peak"""
@@ -137,12 +137,12 @@ def step_model(pc, k_corr, ms_per_step):
     fwd = r_at * (66 + 2 * 9 * 9) + mag + a_at * (56 + 2 * 63 + 60 + 2 * 7 * 24)
     mlp = 2 * 2 * 102 * 64
     sweep = (Nfe / N) * 2 * (1 + k_corr) * (ff_r * 30 + 320)
-    survey = (2 + k_corr) * (fwd + mlp) + (1 + k_corr) * 0.6 * mag + 3 * fwd + sweep
+    estimate = (2 + k_corr) * (fwd + mlp) + (1 + k_corr) * 0.6 * mag + 3 * fwd + sweep
     groups = ("desc_radial", "desc_angular", "readout", "bwd_radial", "bwd_angular", "bwd_angular_1",
               "couplings", "pairs")
     counted = sum(flops_per_step(g, pc, k_corr) for g in groups) / N + sweep
     out = {}
-    for key, f in (("survey_estimate", survey), ("work_model", counted)):
+    for key, f in (("method_estimate", estimate), ("work_model", counted)):
         t = f * N / (ms_per_step * 1e-3) / 1e12
         out[key] = {"flop_per_atom_step": round(f), "achieved_tflops": round(t, 3),
                     "frac_fp64_peak": round(t / PEAK["fp64"], 4)}
