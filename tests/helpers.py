@@ -39,11 +39,12 @@ def pos_error(pos1, rp, pos0, box, pbc):
 
 def cluster_around(types, pos, spin, box, pbc, k, radius):
     """Atoms within `radius` of atom k, unwrapped by minimum image into a free
-    cluster; returns (types, pos, spin, index of k in the cluster)."""
+    cluster centred on atom k (at the origin), so that its displacements to
+    the others are the minimum-image ones bit for bit; returns (types, pos,
+    spin, index of k in the cluster)."""
     d = min_image_delta(pos, pos[k], box, pbc)
     sel = np.nonzero((d * d).sum(axis=1) < radius * radius)[0]
-    cpos = pos[k] + d[sel] + 1000.0
-    return types[sel], cpos, spin[sel], int(np.nonzero(sel == k)[0][0])
+    return types[sel], d[sel], spin[sel], int(np.nonzero(sel == k)[0][0])
 
 
 def oracle_local(oracle, types, pos, spin, box, pbc, params, atoms, *, B=(0, 0, 0), mu_s=1.0, zbl=None):

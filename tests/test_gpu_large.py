@@ -1,5 +1,6 @@
 """The two largest workloads at their full sizes, on sampled outputs and on
-properties that hold at any size.
+properties that hold at any size, with the model the benchmark times (seeded
+random weights plus the short-range term).
 
 * Precision form: 96x96x96 cells = 7,077,888 atoms, periodic. FP64 and
   FP32-mixed E, F, H on the same state; the FP32 errors against FP64 are held
@@ -26,7 +27,7 @@ MUB = 5.7883818060e-5
 @pytest.fixture(scope="module")
 def model():
     from paper_2606_14073_amd import nepspin
-    return nepspin.Model(W.random_params())
+    return nepspin.Model(W.random_params(), short_range=W.SHORT_RANGE_FEGE)
 
 
 @pytest.fixture(scope="module")
@@ -43,7 +44,7 @@ def test_precision_form_errors_7m(model, oracle, cube96):
     # FP64 against the oracle on sampled atoms (first, last, both species, random)
     rng = np.random.default_rng(3)
     atoms = np.concatenate([[0, 5, s.n - 1, s.n - 8, s.n // 2], rng.integers(0, s.n, 11)])
-    Ei, F, H = oracle_local(oracle, s.types, s.pos, s.spin, s.box, s.pbc, p, atoms, B=B)
+    Ei, F, H = oracle_local(oracle, s.types, s.pos, s.spin, s.box, s.pbc, p, atoms, B=B, zbl=W.SHORT_RANGE_FEGE)
     assert rel_inf(ref["Ei"][atoms], Ei) <= TOL64
     assert rel_inf(ref["F"][atoms], F) <= TOL64
     assert rel_inf(ref["H"][atoms], H) <= TOL64
@@ -89,7 +90,9 @@ def test_precision_form_step_7m(model, cube96):
     print(f"fp32 vs fp64 after 2 steps, 7,077,888 atoms: pos {np.abs(d).max():.2e} A, "
           f"vel rel {rel_inf(v32, v64):.2e}, spin {np.abs(s32 - s64).max():.2e}, "
           f"E_pot/N {abs(o32[-1][1] - o64[-1][1]) / s.n:.2e} eV", flush=True)
-    assert np.abs(d).max() < 1e-9
+    # FP32 force errors (rel-l2 ~1e-6, up to ~1e-4 eV/A on single atoms with
+    # the short-range term) move an atom by ~kappa dF dt^2 / m ~ 4e-9 A in two steps
+    assert np.abs(d).max() < 2e-8
     assert rel_inf(v32, v64) < 1e-4
     assert np.abs(s32 - s64).max() < 1e-4
     assert abs(o32[-1][1] - o64[-1][1]) / s.n < 1e-6
@@ -129,7 +132,8 @@ def test_slab_ramp_4m(model, oracle):
     zs = pos[:, 2]
     rng = np.random.default_rng(5)
     atoms = np.concatenate([[int(np.argmin(zs)), int(np.argmax(zs)), 0, s.n - 1], rng.integers(0, s.n, 8)])
-    Ei, F, H = oracle_local(oracle, s.types, pos, spin, s.box, s.pbc, p, atoms, B=(0, 0, bz))
+    Ei, F, H = oracle_local(oracle, s.types, pos, spin, s.box, s.pbc, p, atoms, B=(0, 0, bz),
+                            zbl=W.SHORT_RANGE_FEGE)
     assert rel_inf(ref["Ei"][atoms], Ei) <= TOL64
     assert rel_inf(ref["F"][atoms], F) <= TOL64
     assert rel_inf(ref["H"][atoms], H) <= TOL64
