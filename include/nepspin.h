@@ -394,8 +394,12 @@ int sl_server_create(const nep_model *m, const sl_server_config *cfg, sl_server 
 size_t sl_replica_bytes(int64_t n_atoms, sl_precision prec);
 
 /* Queue a replica (inputs copied; colour may be NULL). ip->K_corr must equal
- * the server's and ip->sc_tol be 0 (fixed corrector passes). Errors:
- * SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the whole budget). */
+ * the server's. A replica may iterate the midpoint to a tolerance
+ * (ip->sc_tol > 0) with plain iteration only (ip->sc_depth 0): each replica
+ * stops on its own criterion, those with fixed corrector passes after their
+ * K_corr, so the result is the same as alone or as a single-system
+ * simulation; its observables report its own pass count and last change.
+ * Errors: SL_E_INVALID, SL_E_BOX, SL_E_OOM (larger than the whole budget). */
 int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const double *vel,
                       const int32_t *colour, const sl_integrator_params *ip, int64_t n_steps,
                       uint64_t *id_out);

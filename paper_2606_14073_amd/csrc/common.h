@@ -68,6 +68,8 @@ struct RepDev {
     double lsf_gamma;               // damping of the longitudinal spin dynamics
     int lsf;                        // 1: spins of variable length (longitudinal Langevin dynamics)
     int capped;                     // rotations of this step stopped at mid_cap without meeting mid_tol
+    int sc_passes;                  // sweep passes of the last spin step (self-consistent batches)
+    double sc_last;                 // and the change of its last pass
 };
 
 __device__ inline double ramp_frac(const RepDev &R) {

@@ -168,6 +168,8 @@ struct Replica {
     int64_t obs_step = 0;
     size_t bytes = 0;
     int64_t n_recolour = 0;                // colourings replaced since creation
+    int last_passes = 0;                   // self-consistent: sweep passes of the last step run
+    double last_change = 0;                // and the change of its last pass
     bool need_recolour = false;            // paused on a colour conflict in the list shell
 };
 
@@ -785,8 +787,16 @@ struct Engine {
     void spin_step(const ModelDev<real> &m, const Work<real> &w) {
         const Sys S = sys();
         { ProfScope q(this, 9); launch_spin_prep(S, st); }
-        const bool sc = sc_tol > 0;
-        const int last = sc ? sc_max : K_corr;
+        // iterated to a tolerance when any replica asks for it (each stops on
+        // its own criterion; the others after their K_corr correctors)
+        bool sc = false;
+        int cap = 0;
+        for (const Replica *r : reps)
+            if (r->dev.sc_tol > 0) {
+                sc = true;
+                cap = std::max(cap, r->dev.sc_max);
+            }
+        const int last = sc ? std::max(cap, K_corr) : K_corr;
         int passes = 0;
         double change = 0;
         for (int p = 0; p <= last; p++) {
@@ -808,7 +818,7 @@ struct Engine {
                 double out[2] = {0, 0};
                 {
                     ProfScope q(this, 9);
-                    launch_sc_check(S, p, sc_depth, sc_reg, st);
+                    launch_sc_check(S, p, sc_depth, sc_reg, K_corr, st);
                 }
                 if (hipMemcpyAsync(out, sc_out, sizeof(out), hipMemcpyDeviceToHost, st) != hipSuccess ||
                     hipStreamSynchronize(st) != hipSuccess)
@@ -1891,6 +1901,8 @@ void sl_server::run() {
                 if (kk > 0) {
                     std::memcpy(r->obs_last, hobs.data() + ((kk - 1) * nr + a) * NOBS, NOBS * 8);
                     r->obs_step = r->step0 + r->steps_done + kk;
+                    r->last_passes = dv[a].sc_passes;
+                    r->last_change = dv[a].sc_last;
                 }
                 r->steps_done += kk;
                 atom_steps += (double)kk * r->n;
@@ -1933,7 +1945,8 @@ extern "C" int sl_replica_submit(sl_server *sv, const sl_system_view *sys, const
                                  const sl_integrator_params *ip, int64_t n_steps, uint64_t *id_out) {
     if (!sv || !ip || !id_out) return fail(SL_E_INVALID, "server, params and id_out are required");
     if (ip->K_corr != sv->cfg.K_corr) return fail(SL_E_INVALID, "K_corr must equal the server's");
-    if (ip->sc_tol != 0) return fail(SL_E_INVALID, "the replica server runs a fixed number of corrector passes");
+    if (ip->sc_tol != 0 && ip->sc_depth != 0)
+        return fail(SL_E_INVALID, "replicas in the server iterate the midpoint without mixing: sc_depth must be 0");
     if (n_steps < 1) return fail(SL_E_INVALID, "n_steps must be >= 1");
     auto r = std::make_unique<Replica>();
     int rc = make_replica(sys, vel, colour, ip, !sv->m->structural, *r, sv->m->structural);
@@ -1987,7 +2000,9 @@ extern "C" int sl_replica_fetch(sl_server *sv, uint64_t id, double *pos, double 
     if (vel) std::memcpy(vel, r->vel.data(), 24 * r->n);
     if (spin) std::memcpy(spin, r->spin.data(), 24 * r->n);
     if (obs) {
-        fill_obs(r->obs_last, (double)r->n_fe, r->obs_step, r->n, obs, sv->eng.K_corr + 1, 0.0);
+        const bool sc = r->dev.sc_tol > 0;
+        fill_obs(r->obs_last, (double)r->n_fe, r->obs_step, r->n, obs, sc ? r->last_passes : sv->eng.K_corr + 1,
+                 sc ? r->last_change : 0.0);
     }
     return SL_OK;
 }

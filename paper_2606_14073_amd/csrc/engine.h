@@ -113,7 +113,7 @@ constexpr int SC_OUT = 12;
 constexpr int SC_MAXD = 8;                                     // deepest mixing history
 constexpr int SC_NK = SC_MAXD * (SC_MAXD + 1) / 2 + SC_MAXD;   // Gram entries + right-hand side
 int sc_part_blocks(int n_fe);
-void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st);
+void launch_sc_check(const Sys &S, int pass, int depth, double reg, int k_corr, hipStream_t st);
 void launch_sc_mix(const Sys &S, int pass, int depth, hipStream_t st);
 
 // per-replica fixed-order reductions: out[r][NOBS]: E_nep, E_kin, E_z,

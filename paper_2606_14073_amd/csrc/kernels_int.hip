@@ -480,13 +480,16 @@ __global__ void __launch_bounds__(256) k_sc_check(Sys S, int pass, int depth, in
     }
 }
 
-// One workgroup: converged or capped replicas stop; count the others. With
+// One workgroup: converged or capped replicas stop; count the others. A
+// replica with a fixed number of correctors (sc_tol 0) iterating beside
+// others stops after its k_corr corrector passes, as it would alone; every
+// replica records its pass count and last change when it stops. With
 // mixing, the Gram matrix is summed over the workgroups in order and the
 // regularised normal equations (G + lam I) gam = r, lam = reg * trace(G) / mk,
 // are solved by Cholesky; a pivot below 1e-13 of its diagonal entry (a column
 // in the span of the others) gives the plain step. sc_out: pending replicas,
 // largest change of this pass, used columns, gam[mk].
-__global__ void __launch_bounds__(256) k_sc_decide(Sys S, int pass, int mk, int nblocks, double reg) {
+__global__ void __launch_bounds__(256) k_sc_decide(Sys S, int pass, int mk, int nblocks, double reg, int k_corr) {
     __shared__ int cnt;
     __shared__ unsigned long long dmax;
     __shared__ double sum[SC_NK];
@@ -498,10 +501,24 @@ __global__ void __launch_bounds__(256) k_sc_decide(Sys S, int pass, int mk, int 
     int mine = 0;
     for (int r = threadIdx.x; r < S.n_rep; r += blockDim.x) {
         RepDev &R = S.rep[r];
-        if (!R.active || R.sc_tol <= 0 || R.sc_done) continue;
+        if (!R.active || R.sc_done) continue;
+        if (R.sc_tol <= 0) {
+            if (pass >= k_corr) {
+                R.sc_done = 1;
+                R.sc_passes = pass + 1;
+                R.sc_last = 0;
+            } else {
+                mine++;
+            }
+            continue;
+        }
         const double dl = __longlong_as_double((long long)R.sc_delta);
         if (pass >= 1) atomicMax(&dmax, R.sc_delta);
-        if (pass >= 1 && (dl <= R.sc_tol || pass >= R.sc_max)) R.sc_done = 1;
+        if (pass >= 1 && (dl <= R.sc_tol || pass >= R.sc_max)) {
+            R.sc_done = 1;
+            R.sc_passes = pass + 1;
+            R.sc_last = dl;
+        }
         R.sc_delta = 0;
         mine += !R.sc_done;
     }
@@ -675,11 +692,11 @@ void launch_set_active(RepDev *rep, const int *act, int n, hipStream_t st) {
     if (n) hipLaunchKernelGGL(k_set_active, dim3(nblk(n, 64)), dim3(64), 0, st, rep, act, n);
 }
 int sc_part_blocks(int n_fe) { return nblk(n_fe, 256); }
-void launch_sc_check(const Sys &S, int pass, int depth, double reg, hipStream_t st) {
+void launch_sc_check(const Sys &S, int pass, int depth, double reg, int k_corr, hipStream_t st) {
     const int mk = depth > 0 ? (pass < depth ? pass : depth) : 0;
     const int nb = nblk(S.N_fe, 256);
     if (S.N_fe) hipLaunchKernelGGL(k_sc_check, dim3(nb), dim3(256), 0, st, S, pass, depth, mk);
-    hipLaunchKernelGGL(k_sc_decide, dim3(1), dim3(256), 0, st, S, pass, S.N_fe ? mk : 0, nb, reg);
+    hipLaunchKernelGGL(k_sc_decide, dim3(1), dim3(256), 0, st, S, pass, S.N_fe ? mk : 0, nb, reg, k_corr);
 }
 void launch_sc_mix(const Sys &S, int pass, int depth, hipStream_t st) {
     if (S.N_fe) hipLaunchKernelGGL(k_sc_mix, dim3(nblk(S.N_fe, 256)), dim3(256), 0, st, S, pass, depth);

@@ -551,14 +551,16 @@ def test_selfconsistent_reversible(model):
     assert dp <= 1e-10 and dv <= 1e-10 and ds <= 1e-10
 
 
-def test_selfconsistent_rejected_by_server(model):
+def test_accelerated_selfconsistent_rejected_by_server(model):
+    """the server iterates the midpoint plainly; Anderson mixing (one Gram
+    system for the whole batch) is refused"""
     from paper_2606_14073_amd import nepspin
     s = W.config_small()
     srv = nepspin.Server(model, hbm_budget_bytes=1 << 30, max_slots=2, precision="fp64", steps_per_batch=4)
     try:
         with pytest.raises(nepspin.NepError) as e:
             srv.submit(s.types, s.pos, s.spin, s.box, s.pbc, colour=s.colour, n_steps=2,
-                       params=_params(nepspin, sc_tol=1e-12))
+                       params=_params(nepspin, sc_tol=1e-12, sc_max=40, sc_depth=3))
         assert e.value.code == nepspin.SL_E_INVALID
     finally:
         srv.close()

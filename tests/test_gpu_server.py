@@ -78,6 +78,56 @@ def test_alone_equals_mix_equals_direct(model, precision):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_selfconsistent_replicas_alone_equal_mix_equal_direct(model, precision):
+    """replicas iterating the midpoint to a tolerance beside replicas with a
+    fixed number of correctors: each is bitwise the same alone, in the mix and
+    as a direct simulation, and reports its own pass count"""
+    from paper_2606_14073_amd import nepspin
+
+    def req(cells, T, Bz, seed, **sc):
+        s = W.fege_lattice(cells, cells, cells, seed=seed)
+        v = W.maxwell_boltzmann(s.types, T, seed=seed + 7)
+        ip = nepspin.integrator_params(dt=1.0, T0=T, alpha_s=0.1, gamma_L=0.01, ensemble=1, B0=(0, 0, Bz),
+                                       seed=1000 + seed, **sc)
+        return s, v, ip
+
+    # FP32-mixed fields settle the iteration only to FP32 precision
+    tol = 1e-12 if precision == "fp64" else 1e-7
+    X = req(4, 200.0, 0.5, 31, sc_tol=tol, sc_max=40)
+    Y = req(5, 150.0, 0.2, 32)
+    Z = req(4, 280.0, 0.9, 33, sc_tol=100 * tol, sc_max=40)
+    n = 7
+
+    def serve(items):
+        sv = nepspin.Server(model, precision=precision, steps_per_batch=3, max_slots=8)
+        ids = [_submit(sv, r, m) for r, m in items]
+        sv.drain()
+        out = [sv.fetch(k) for k in ids]
+        for k in ids:
+            assert sv.poll(k)["state"] == nepspin.SL_DONE
+        sv.close()
+        return out
+
+    x_alone, = serve([(X, n)])
+    y_alone, = serve([(Y, n)])
+    y_mix, x_mix, _ = serve([(Y, n), (X, n), (Z, 11)])
+    for r, alone, mix in ((X, x_alone, x_mix), (Y, y_alone, y_mix)):
+        s, v, ip = r
+        sim = nepspin.Sim(model, s.types, s.pos, s.spin, s.box, s.pbc, vel=v, colour=s.colour, params=ip,
+                          precision=precision)
+        ob = sim.integrate(n)
+        direct = sim.state()
+        sim.close()
+        for a, b, c in zip(alone[:3], mix[:3], direct[:3]):
+            assert np.array_equal(a, b) and np.array_equal(a, c)
+        assert alone[3][9] == mix[3][9] == ob[-1, 9]
+        assert alone[3][10] == mix[3][10]
+    print(f"{precision}: passes of the last step, iterated {x_alone[3][9]:.0f}, fixed {y_alone[3][9]:.0f}",
+          flush=True)
+    assert 2 < x_alone[3][9] < 41 and y_alone[3][9] == 2 and 0 < x_alone[3][10] <= tol
+
+
 def test_budget_admission_and_oom(model):
     from paper_2606_14073_amd import nepspin
     reqs = [_request(4, 100.0 + 20 * k, 0.2 * k, 20 + k) for k in range(4)]
