@@ -48,8 +48,18 @@ KERNEL_NAME = {"desc_radial": "k_desc_radial<{r}>", "desc_angular": "k_desc_angu
                "sweep": "k_sweep<{r}>", "nlist": "k_build_cells", "integrate": "k_kick"}
 
 
-def kernel_name(group, real="double"):
-    """the largest kernel of a profile group, named as in the kernel trace"""
+# The library's sweep launcher gives colour classes of this many spins or more
+# 8 lanes per spin (kernel k_sweep<real,8>), smaller ones 16.
+SWEEP_WIDE_MIN = 8192
+
+
+def kernel_name(group, real="double", colour=None):
+    """the largest kernel of a profile group, named as in the kernel trace
+    (for the sweep, the lane layout of the largest colour class)"""
+    if group == "sweep" and colour is not None:
+        c = np.asarray(colour)
+        lanes = 8 if np.bincount(c[c >= 0]).max() >= SWEEP_WIDE_MIN else 16
+        return f"k_sweep<{real},{lanes}>"
     return KERNEL_NAME.get(group, group).replace("{r}", real)
 
 
@@ -418,7 +428,7 @@ def roofline_of(group, prof, pc, n_steps, k_corr, s, real="double"):
     vector (or MFMA) peak with the work model of flops_per_step"""
     ms, nl = prof.get(group, (0.0, 0))
     rb = 8 if real == "double" else 4
-    kname = kernel_name(group, real)
+    kname = kernel_name(group, real, s.colour)
     if not nl:
         return {"kernel": kname, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "note": "no timed launches"}

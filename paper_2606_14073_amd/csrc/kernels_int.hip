@@ -147,93 +147,127 @@ __device__ inline double quad_bcast(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// One coupling's contribution to the field on a spin: exchange J s_j, DMI
+// D s_j x r, anisotropic exchange K (s_j . r) r, subtracted from h, with
+// explicit fused multiply-adds and no other contraction.
+__device__ inline void coupling_field(double J, double D, double K, double rx, double ry, double rz, double sx,
+                                      double sy, double sz, double &hx, double &hy, double &hz) {
+#pragma clang fp contract(off)
+    const double sr = fma(sz, rz, fma(sy, ry, sx * rx));
+    const double ks = K * sr;
+    hx -= fma(J, sx, fma(D, fma(sy, rz, -(sz * ry)), ks * rx));
+    hy -= fma(J, sy, fma(D, fma(sz, rx, -(sx * rz)), ks * ry));
+    hz -= fma(J, sz, fma(D, fma(sx, ry, -(sy * rx)), ks * rz));
+}
+
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
-// SWEEP_L lanes share a spin: they split the neighbour gather (couplings stored
-// in colour-list order, so a wavefront reads contiguous records), reduce, and
-// then solve the midpoint equation together (each quad of lanes evaluates the
-// rotation at four points per Newton step); lane 0 stores the result.
+// L lanes share a spin (L = 8 or 16): they split the neighbour gather
+// (couplings stored in colour-list order, so a wavefront reads contiguous
+// records), reduce, and then solve the midpoint equation together (each quad
+// of lanes evaluates the rotation at four points per Newton step); lane 0
+// stores the result.
+// The field sum has one order whatever L is: sixteen virtual lanes v each
+// add the couplings in slots v, v + 16, v + 32, ... in turn, and a butterfly
+// over v (xor 1, 2, 4, 8) adds the sixteen partial sums. Lane l of L carries
+// the virtual lanes l + L k, k < 16 / L; the butterfly levels below L run
+// across lanes and the others inside the lane. A spin's result thus has the
+// same bits with either L, so each launch takes the L that suits the size of
+// its colour class (fewer, fuller waves for large classes, more workgroups
+// for small ones) and a replica still gives the same bits alone and in any
+// batch.
 // Latency is what bounds a colour class, so the loads are issued in two
 // waves: everything indexed by the colour-list position (atom, replica,
-// coupling count, self terms, the first SWEEP_R0 coupling slots of each lane,
-// read whether or not they are in use and masked afterwards), then the
-// neighbours' spins, the spin itself, its noise and the replica record.
-// Eight lanes per spin with four slots each (32 per spin, enough for the 30
-// Fe-Fe couplings of the B20 crystal) take fewer waves per colour class than
-// sixteen lanes with two: on a seven-million-atom crystal the sweep runs about
-// a quarter faster, on a quarter-million-atom one (a few hundred workgroups per
-// class) slightly slower. The lane count fixes the order of the field sum, so it
-// is one constant for every batch, whatever its size.
-constexpr int SWEEP_L = 8;     // lanes per spin
-constexpr int SWEEP_R0 = 4;    // coupling slots per lane loaded up front (32 per spin)
+// coupling count, self terms, the first 32 coupling slots, read whether or
+// not they are in use and masked afterwards), then the neighbours' spins, the
+// spin itself, its noise and the replica record.
+constexpr int SWEEP_V = 16;              // virtual lanes of the field sum
+constexpr int SWEEP_WIDE_MIN = 8192;     // classes of at least this many spins take 8 lanes per spin
 
 // turns = 2 takes the colour twice in a row (the end of the ascending and the
 // start of the descending pass): the neighbour field is the same for both
 // rotations, the second starts from the first one's result.
-template <typename real>
+// The kernel's own arithmetic is not contracted: the compiler would fuse
+// multiplies and adds differently in the two lane layouts (their code is
+// scheduled apart), and their results would then differ in the last bit;
+// where a fused multiply-add is wanted it is written out.
+template <typename real, int L>
 __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, int count, int turns, int visit0) {
-    const int lane = threadIdx.x & (SWEEP_L - 1);
-    const int t = blockIdx.x * (256 / SWEEP_L) + threadIdx.x / SWEEP_L;
+#pragma clang fp contract(off)
+    constexpr int P = SWEEP_V / L;   // virtual lanes per lane
+    constexpr int R0 = 2 * P;        // coupling slots per lane loaded up front
+    const int lane = threadIdx.x & (L - 1);
+    const int t = blockIdx.x * (256 / L) + threadIdx.x / L;
     if (t >= count) return;
     const int p = base + t;
     const size_t lf = S.N_fe;
-    // first wave of loads
+    // first wave of loads; up-front slot u = 2 k + w is slot lane + L k + 16 w
     const int i = S.col_idx[p];
     const int r = S.col_rid[p];
     const int nc = W.cpl_n[p];
     const real *o = W.selfc + (size_t)p * 8;
     const double Axx = o[0], Ayy = o[1], Azz = o[2], Axy = o[3], Axz = o[4], Ayz = o[5], os = o[6];
-    int cj[SWEEP_R0];
-    double cv[SWEEP_R0][6];
+    int cj[R0];
+    double cv[R0][6];
 #pragma unroll
-    for (int k = 0; k < SWEEP_R0; k++) {
-        const size_t q = (size_t)(lane + SWEEP_L * k) * lf + p;
-        cj[k] = W.cpl_j[q];
+    for (int u = 0; u < R0; u++) {
+        const size_t q = (size_t)(lane + L * (u >> 1) + SWEEP_V * (u & 1)) * lf + p;
+        cj[u] = W.cpl_j[q];
         const real *c = W.cpl + q * 6;
 #pragma unroll
-        for (int x = 0; x < 6; x++) cv[k][x] = c[x];
+        for (int x = 0; x < 6; x++) cv[u][x] = c[x];
     }
     // second wave
     const RepDev &R = S.rep[r];
     const d4 e = S.eta[i];
     const d4 s4 = S.spin[i];
-    double hx = 0, hy = 0, hz = 0;
-    d4 sj[SWEEP_R0];
+    double px[P], py[P], pz[P];
 #pragma unroll
-    for (int k = 0; k < SWEEP_R0; k++) sj[k] = S.spin[lane + SWEEP_L * k < nc ? cj[k] : i];
+    for (int k = 0; k < P; k++) px[k] = py[k] = pz[k] = 0;
+    d4 sj[R0];
 #pragma unroll
-    for (int k = 0; k < SWEEP_R0; k++) {
-        if (lane + SWEEP_L * k >= nc) continue;
-        const double J = cv[k][0], D = cv[k][1], K = cv[k][2], rx = cv[k][3], ry = cv[k][4], rz = cv[k][5];
-        const double sr = sj[k].x * rx + sj[k].y * ry + sj[k].z * rz;
-        hx -= J * sj[k].x + D * (sj[k].y * rz - sj[k].z * ry) + K * sr * rx;
-        hy -= J * sj[k].y + D * (sj[k].z * rx - sj[k].x * rz) + K * sr * ry;
-        hz -= J * sj[k].z + D * (sj[k].x * ry - sj[k].y * rx) + K * sr * rz;
-    }
-    // spins with more than SWEEP_L * SWEEP_R0 couplings
-    for (int s = lane + SWEEP_L * SWEEP_R0; s < nc; s += SWEEP_L) {
-        const int j = W.cpl_j[(size_t)s * lf + p];
-        const real *c = W.cpl + ((size_t)s * lf + p) * 6;
-        const double J = c[0], D = c[1], K = c[2], rx = c[3], ry = c[4], rz = c[5];
-        const d4 v = S.spin[j];
-        const double sr = v.x * rx + v.y * ry + v.z * rz;
-        hx -= J * v.x + D * (v.y * rz - v.z * ry) + K * sr * rx;
-        hy -= J * v.y + D * (v.z * rx - v.x * rz) + K * sr * ry;
-        hz -= J * v.z + D * (v.x * ry - v.y * rx) + K * sr * rz;
-    }
+    for (int u = 0; u < R0; u++) sj[u] = S.spin[lane + L * (u >> 1) + SWEEP_V * (u & 1) < nc ? cj[u] : i];
 #pragma unroll
-    for (int m = 1; m < SWEEP_L; m <<= 1) {
-        hx += __shfl_xor(hx, m);
-        hy += __shfl_xor(hy, m);
-        hz += __shfl_xor(hz, m);
+    for (int u = 0; u < R0; u++) {
+        const int k = u >> 1;
+        if (lane + L * k + SWEEP_V * (u & 1) >= nc) continue;
+        coupling_field(cv[u][0], cv[u][1], cv[u][2], cv[u][3], cv[u][4], cv[u][5], sj[u].x, sj[u].y, sj[u].z, px[k],
+                       py[k], pz[k]);
     }
+    // spins with more than 32 couplings
+#pragma unroll
+    for (int k = 0; k < P; k++)
+        for (int s = lane + L * k + 2 * SWEEP_V; s < nc; s += SWEEP_V) {
+            const int j = W.cpl_j[(size_t)s * lf + p];
+            const real *c = W.cpl + ((size_t)s * lf + p) * 6;
+            const d4 v = S.spin[j];
+            coupling_field(c[0], c[1], c[2], c[3], c[4], c[5], v.x, v.y, v.z, px[k], py[k], pz[k]);
+        }
+    // butterfly: levels 1 .. L/2 across the lanes, then L .. 8 inside them
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1)
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            px[k] += __shfl_xor(px[k], m);
+            py[k] += __shfl_xor(py[k], m);
+            pz[k] += __shfl_xor(pz[k], m);
+        }
+#pragma unroll
+    for (int b = 1; b < P; b <<= 1)
+#pragma unroll
+        for (int k = 0; k < P; k += 2 * b) {
+            px[k] += px[k + b];
+            py[k] += py[k + b];
+            pz[k] += pz[k + b];
+        }
+    double hx = px[0], hy = py[0], hz = pz[0];
     if (!spin_pass_on(R)) return;
     const double fr = ramp_frac(R), zs = R.mu_s * MUB;
-    hx += zs * (R.B0[0] + (R.B1[0] - R.B0[0]) * fr) + e.x;
-    hy += zs * (R.B0[1] + (R.B1[1] - R.B0[1]) * fr) + e.y;
-    hz += zs * (R.B0[2] + (R.B1[2] - R.B0[2]) * fr) + e.z;
-    const double al = R.alpha, inv = 1.0 / (1.0 + al * al), tau = 0.5 * R.dt / HBAR;
+    hx += fma(zs, fma(R.B1[0] - R.B0[0], fr, R.B0[0]), e.x);
+    hy += fma(zs, fma(R.B1[1] - R.B0[1], fr, R.B0[1]), e.y);
+    hz += fma(zs, fma(R.B1[2] - R.B0[2], fr, R.B0[2]), e.z);
+    const double al = R.alpha, inv = 1.0 / fma(al, al, 1.0), tau = 0.5 * R.dt / HBAR;
     const double tol = R.mid_tol;
     const int cap = R.mid_cap;
     const double Dxx = Axx + os, Dyy = Ayy + os, Dzz = Azz + os;   // A_i + o_i I
@@ -245,18 +279,18 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     // and moment-length terms evaluated at m), by the angle |w| tau (Rodrigues)
     auto rotate = [&](double px, double py, double pz, double &nx, double &ny, double &nz) {
         double mx = sx + px, my = sy + py, mz = sz + pz;
-        const double mn = rsqrt_nr(mx * mx + my * my + mz * mz) * len;
+        const double mn = rsqrt_nr(fma(mz, mz, fma(my, my, mx * mx))) * len;
         mx *= mn;
         my *= mn;
         mz *= mn;
-        const double kl = la2 + lb4 * (mx * mx + my * my + mz * mz);
-        const double h0 = hx - 2.0 * (Dxx * mx + Axy * my + Axz * mz) - kl * mx;
-        const double h1 = hy - 2.0 * (Axy * mx + Dyy * my + Ayz * mz) - kl * my;
-        const double h2 = hz - 2.0 * (Axz * mx + Ayz * my + Dzz * mz) - kl * mz;
-        const double wx = (h0 + al * (my * h2 - mz * h1)) * inv;
-        const double wy = (h1 + al * (mz * h0 - mx * h2)) * inv;
-        const double wz = (h2 + al * (mx * h1 - my * h0)) * inv;
-        const double w2 = wx * wx + wy * wy + wz * wz;
+        const double kl = fma(lb4, fma(mz, mz, fma(my, my, mx * mx)), la2);
+        const double h0 = fma(-kl, mx, fma(-2.0, fma(Axz, mz, fma(Axy, my, Dxx * mx)), hx));
+        const double h1 = fma(-kl, my, fma(-2.0, fma(Ayz, mz, fma(Dyy, my, Axy * mx)), hy));
+        const double h2 = fma(-kl, mz, fma(-2.0, fma(Dzz, mz, fma(Ayz, my, Axz * mx)), hz));
+        const double wx = fma(al, fma(my, h2, -(mz * h1)), h0) * inv;
+        const double wy = fma(al, fma(mz, h0, -(mx * h2)), h1) * inv;
+        const double wz = fma(al, fma(mx, h1, -(my * h0)), h2) * inv;
+        const double w2 = fma(wz, wz, fma(wy, wy, wx * wx));
         if (w2 == 0.0) {
             nx = sx;
             ny = sy;
@@ -274,10 +308,10 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
             omc = 1.0 - cs;
         }
         const double ux = wx * iw, uy = wy * iw, uz = wz * iw;
-        const double us = ux * sx + uy * sy + uz * sz;
-        nx = sx * cs + (uy * sz - uz * sy) * sn + ux * us * omc;
-        ny = sy * cs + (uz * sx - ux * sz) * sn + uy * us * omc;
-        nz = sz * cs + (ux * sy - uy * sx) * sn + uz * us * omc;
+        const double us = fma(uz, sz, fma(uy, sy, ux * sx)), uo = us * omc;
+        nx = fma(ux, uo, fma(fma(uy, sz, -(uz * sy)), sn, sx * cs));
+        ny = fma(uy, uo, fma(fma(uz, sx, -(ux * sz)), sn, sy * cs));
+        nz = fma(uz, uo, fma(fma(ux, sy, -(uy * sx)), sn, sz * cs));
     };
     // The midpoint equation y = G(y) is solved by Newton's method on
     // G(y) - y with a forward-difference Jacobian: the four lanes of each
@@ -349,13 +383,14 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
                          a22 = 1.0 - (quad_bcast<3>(nz) - g0z) * FD_IH;
             // y += A^-1 r (Cramer's rule); a plain fixed-point step if A is not
             // safely invertible (never for a contracting map)
-            const double c00 = a11 * a22 - a12 * a21, c01 = a12 * a20 - a10 * a22, c02 = a10 * a21 - a11 * a20;
-            const double det = a00 * c00 + a01 * c01 + a02 * c02;
+            auto det2 = [](double a, double b, double c, double d) { return fma(a, b, -(c * d)); };   // ab - cd
+            const double c00 = det2(a11, a22, a12, a21), c01 = det2(a12, a20, a10, a22), c02 = det2(a10, a21, a11, a20);
+            const double det = fma(a02, c02, fma(a01, c01, a00 * c00));
             if (fabs(det) > 0.25) {
                 const double id = 1.0 / det;
-                yx += (c00 * rx + (a02 * a21 - a01 * a22) * ry + (a01 * a12 - a02 * a11) * rz) * id;
-                yy += (c01 * rx + (a00 * a22 - a02 * a20) * ry + (a02 * a10 - a00 * a12) * rz) * id;
-                yz += (c02 * rx + (a01 * a20 - a00 * a21) * ry + (a00 * a11 - a01 * a10) * rz) * id;
+                yx += fma(det2(a01, a12, a02, a11), rz, fma(det2(a02, a21, a01, a22), ry, c00 * rx)) * id;
+                yy += fma(det2(a02, a10, a00, a12), rz, fma(det2(a00, a22, a02, a20), ry, c01 * rx)) * id;
+                yz += fma(det2(a00, a11, a01, a10), rz, fma(det2(a01, a20, a00, a21), ry, c02 * rx)) * id;
             } else {
                 yx = g0x;
                 yy = g0y;
@@ -718,8 +753,11 @@ void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, in
             const int c = pass == 0 ? cc : n_colours - 1 - cc;
             const int turns = (pass == 0 && cc == n_colours - 1) ? 2 : 1;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
-            if (n > 0)
-                hipLaunchKernelGGL(k_sweep<real>, dim3(nblk(n, 256 / SWEEP_L)), dim3(256), 0, st, S, W, b, n, turns,
+            if (n >= SWEEP_WIDE_MIN)
+                hipLaunchKernelGGL((k_sweep<real, 8>), dim3(nblk(n, 256 / 8)), dim3(256), 0, st, S, W, b, n, turns,
+                                   pass);
+            else if (n > 0)
+                hipLaunchKernelGGL((k_sweep<real, 16>), dim3(nblk(n, 256 / 16)), dim3(256), 0, st, S, W, b, n, turns,
                                    pass);
         }
 }

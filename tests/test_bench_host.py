@@ -74,3 +74,18 @@ def test_pair_counts_of_the_crystal():
         assert pc["A"] / pc["N"] == pytest.approx(29, abs=0.5)
         assert pc["A_fe"] == pc["A_fefe"] + pc["A_fege"] // 2
     assert a["A"] / a["N"] == pytest.approx(b["A"] / b["N"], rel=0.01)
+
+
+def test_sweep_kernel_named_by_class_size():
+    """the bench names the sweep kernel by the lane layout the library's
+    launcher takes for the largest colour class: 8 lanes per spin from
+    8,192 spins up, else 16"""
+    import numpy as np
+    small = np.repeat(np.arange(32), 4096)            # 262,144-atom crystal: 4,096 spins per colour
+    large = np.repeat(np.arange(32), 110592)          # 7,077,888 atoms: 110,592 per colour
+    ge = -np.ones(10, dtype=np.int64)                 # atoms without a spin carry no colour
+    assert bench.kernel_name("sweep", "double", np.concatenate([small, ge])) == "k_sweep<double,16>"
+    assert bench.kernel_name("sweep", "float", large) == "k_sweep<float,8>"
+    assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8192)) == "k_sweep<double,8>"
+    assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8191)) == "k_sweep<double,16>"
+    assert bench.kernel_name("desc_angular", "double") == "k_desc_angular<double>"
