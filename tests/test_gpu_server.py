@@ -83,9 +83,12 @@ def test_large_batch_sweep_layout_same_bits(model, precision):
     """A colour class of 8,192 spins or more is swept with 8 lanes per spin,
     a smaller one with 16; both sum the field in one order. A small replica
     alone (colour classes of 8 spins) and beside a 42^3-cell crystal
-    (classes of 9,269 spins) gives the same bits."""
+    (classes of 9,269 spins) gives the same bits. The small one is
+    compressed to 0.92 of its lattice constant, so that its spins have 37-42
+    couplings and both layouts also take their second coupling loop."""
     from paper_2606_14073_amd import nepspin
     X = _request(4, 200.0, 0.5, 21)
+    X[0].pos, X[0].box = X[0].pos * 0.92, X[0].box * 0.92
     big = _request(42, 300.0, 0.0, 22)
     assert np.bincount(big[0].colour[big[0].colour >= 0]).min() >= 8192
     n = 6
