@@ -48,9 +48,10 @@ KERNEL_NAME = {"desc_radial": "k_desc_radial<{r}>", "desc_angular": "k_desc_angu
                "sweep": "k_sweep<{r}>", "nlist": "k_build_cells", "integrate": "k_kick"}
 
 
-# The library's sweep launcher gives colour classes of this many spins or more
-# 8 lanes per spin (kernel k_sweep<real,8>), smaller ones 16.
-SWEEP_WIDE_MIN = 8192
+# The library's sweep launcher gives colour classes of at least SWEEP_WIDER_MIN
+# spins 4 lanes per spin (kernel k_sweep<real,4>), of at least SWEEP_WIDE_MIN
+# 8, smaller ones 16.
+SWEEP_WIDE_MIN, SWEEP_WIDER_MIN = 8192, 32768
 
 
 def kernel_name(group, real="double", colour=None):
@@ -58,7 +59,8 @@ def kernel_name(group, real="double", colour=None):
     (for the sweep, the lane layout of the largest colour class)"""
     if group == "sweep" and colour is not None:
         c = np.asarray(colour)
-        lanes = 8 if np.bincount(c[c >= 0]).max() >= SWEEP_WIDE_MIN else 16
+        big = np.bincount(c[c >= 0]).max()
+        lanes = 4 if big >= SWEEP_WIDER_MIN else 8 if big >= SWEEP_WIDE_MIN else 16
         return f"k_sweep<{real},{lanes}>"
     return KERNEL_NAME.get(group, group).replace("{r}", real)
 

@@ -163,7 +163,7 @@ __device__ inline void coupling_field(double J, double D, double K, double rx, d
 // One colour class: every spin takes an implicit-midpoint Rodrigues rotation
 // over tau = dt/2 in the field of its (other-colour) neighbours, its own
 // anisotropy/onsite terms at the midpoint, the Zeeman field and the noise.
-// L lanes share a spin (L = 8 or 16): they split the neighbour gather
+// L lanes share a spin (L = 4, 8 or 16): they split the neighbour gather
 // (couplings stored in colour-list order, so a wavefront reads contiguous
 // records), reduce, and then solve the midpoint equation together (each quad
 // of lanes evaluates the rotation at four points per Newton step); lane 0
@@ -173,7 +173,7 @@ __device__ inline void coupling_field(double J, double D, double K, double rx, d
 // over v (xor 1, 2, 4, 8) adds the sixteen partial sums. Lane l of L carries
 // the virtual lanes l + L k, k < 16 / L; the butterfly levels below L run
 // across lanes and the others inside the lane. A spin's result thus has the
-// same bits with either L, so each launch takes the L that suits the size of
+// same bits with any L, so each launch takes the L that suits the size of
 // its colour class (fewer, fuller waves for large classes, more workgroups
 // for small ones) and a replica still gives the same bits alone and in any
 // batch.
@@ -184,6 +184,7 @@ __device__ inline void coupling_field(double J, double D, double K, double rx, d
 // spin itself, its noise and the replica record.
 constexpr int SWEEP_V = 16;              // virtual lanes of the field sum
 constexpr int SWEEP_WIDE_MIN = 8192;     // classes of at least this many spins take 8 lanes per spin
+constexpr int SWEEP_WIDER_MIN = 32768;   // and of at least this many 4
 
 // turns = 2 takes the colour twice in a row (the end of the ascending and the
 // start of the descending pass): the neighbour field is the same for both
@@ -753,7 +754,10 @@ void launch_sweep(const Sys &S, const Work<real> &W, const int *col_ptr_host, in
             const int c = pass == 0 ? cc : n_colours - 1 - cc;
             const int turns = (pass == 0 && cc == n_colours - 1) ? 2 : 1;
             const int b = col_ptr_host[c], n = col_ptr_host[c + 1] - b;
-            if (n >= SWEEP_WIDE_MIN)
+            if (n >= SWEEP_WIDER_MIN)
+                hipLaunchKernelGGL((k_sweep<real, 4>), dim3(nblk(n, 256 / 4)), dim3(256), 0, st, S, W, b, n, turns,
+                                   pass);
+            else if (n >= SWEEP_WIDE_MIN)
                 hipLaunchKernelGGL((k_sweep<real, 8>), dim3(nblk(n, 256 / 8)), dim3(256), 0, st, S, W, b, n, turns,
                                    pass);
             else if (n > 0)

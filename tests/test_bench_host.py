@@ -78,14 +78,16 @@ def test_pair_counts_of_the_crystal():
 
 def test_sweep_kernel_named_by_class_size():
     """the bench names the sweep kernel by the lane layout the library's
-    launcher takes for the largest colour class: 8 lanes per spin from
-    8,192 spins up, else 16"""
+    launcher takes for the largest colour class: 4 lanes per spin from
+    32,768 spins up, 8 from 8,192, else 16"""
     import numpy as np
     small = np.repeat(np.arange(32), 4096)            # 262,144-atom crystal: 4,096 spins per colour
     large = np.repeat(np.arange(32), 110592)          # 7,077,888 atoms: 110,592 per colour
     ge = -np.ones(10, dtype=np.int64)                 # atoms without a spin carry no colour
     assert bench.kernel_name("sweep", "double", np.concatenate([small, ge])) == "k_sweep<double,16>"
-    assert bench.kernel_name("sweep", "float", large) == "k_sweep<float,8>"
+    assert bench.kernel_name("sweep", "float", large) == "k_sweep<float,4>"
+    assert bench.kernel_name("sweep", "double", np.repeat(np.arange(2), 32768)) == "k_sweep<double,4>"
+    assert bench.kernel_name("sweep", "double", np.repeat(np.arange(2), 32767)) == "k_sweep<double,8>"
     assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8192)) == "k_sweep<double,8>"
     assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8191)) == "k_sweep<double,16>"
     assert bench.kernel_name("desc_angular", "double") == "k_desc_angular<double>"

@@ -80,32 +80,37 @@ def test_alone_equals_mix_equals_direct(model, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_large_batch_sweep_layout_same_bits(model, precision):
-    """A colour class of 8,192 spins or more is swept with 8 lanes per spin,
-    a smaller one with 16; both sum the field in one order. A small replica
-    alone (colour classes of 8 spins) and beside a 42^3-cell crystal
-    (classes of 9,269 spins) gives the same bits. The small one is
-    compressed to 0.92 of its lattice constant, so that its spins have 37-42
-    couplings and both layouts also take their second coupling loop."""
+    """Colour classes of 32,768 spins or more are swept with 4 lanes per
+    spin, of 8,192 or more with 8, smaller ones with 16; all sum the field in
+    one order. A small replica gives the same bits alone (colour classes of 8
+    spins), beside a 42^3-cell crystal (classes of 9,269 spins) and beside a
+    64^3-cell one (32,776). The small one is compressed to 0.92 of its
+    lattice constant, so that its spins have 37-42 couplings and every
+    layout also takes its second coupling loop."""
     from paper_2606_14073_amd import nepspin
     X = _request(4, 200.0, 0.5, 21)
     X[0].pos, X[0].box = X[0].pos * 0.92, X[0].box * 0.92
-    big = _request(42, 300.0, 0.0, 22)
-    assert np.bincount(big[0].colour[big[0].colour >= 0]).min() >= 8192
     n = 6
     out = []
-    for mix in (False, True):
+    for cells, least in ((0, 0), (42, 8192), (64, 32768)):
         sv = nepspin.Server(model, precision=precision, steps_per_batch=3, max_slots=4)
-        ids = [_submit(sv, big, 5 * n)] if mix else []
+        ids = []
+        if cells:
+            big = _request(cells, 300.0, 0.0, 22)
+            assert np.bincount(big[0].colour[big[0].colour >= 0]).min() >= least
+            ids = [_submit(sv, big, 5 * n)]
+            del big
         a = _submit(sv, X, n)
         sv.drain()
         st = [sv.poll(k) for k in ids + [a]]
         assert all(x["state"] == nepspin.SL_DONE for x in st)
-        if mix:   # X was resident only while the crystal was
+        if cells:   # X was resident only while the crystal was
             assert st[0]["t_admit"] <= st[1]["t_admit"] and st[1]["t_done"] <= st[0]["t_done"]
         out.append(sv.fetch(a))
         sv.close()
-    for x, y in zip(out[0][:3], out[1][:3]):
-        assert np.array_equal(x, y)
+    for other in out[1:]:
+        for x, y in zip(out[0][:3], other[:3]):
+            assert np.array_equal(x, y)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
