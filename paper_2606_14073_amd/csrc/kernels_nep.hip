@@ -73,6 +73,22 @@ __device__ inline void contract(const real *c, const real *Fp, int nn, real C[NB
     }
 }
 
+// The same, with the atom's NR values read in one burst and the loop
+// unrolled: for the per-atom coefficient kernels, whose many resident waves
+// would otherwise evict an atom's row between the rolled loop's reads of it.
+template <typename real>
+__device__ inline void contract_burst(const real *c, const real *Fp, real C[NB]) {
+    real f[NR];
+#pragma unroll
+    for (int n = 0; n < NR; n++) f[n] = Fp[n];
+#pragma unroll
+    for (int k = 0; k < NB; k++) C[k] = 0;
+#pragma unroll
+    for (int n = 0; n < NR; n++)
+#pragma unroll
+        for (int k = 0; k < NB; k++) C[k] += f[n] * c[n * NB + k];
+}
+
 template <typename real>
 __device__ inline real dotk(const real C[NB], const real f[NB]) {
     real s = 0;
@@ -690,13 +706,13 @@ __device__ inline void put_pair(real *pb, size_t idx, const real G[3], const rea
 template <typename real>
 __device__ inline void mag_coef(const real *__restrict__ C, const real *Fp, real *m) {
     real CX[NB];
-    contract((C + P_CEX), Fp + D_EX, NR, CX);
+    contract_burst((C + P_CEX), Fp + D_EX, CX);
 #pragma unroll
     for (int k = 0; k < NB; k++) m[k] = CX[k];
-    contract((C + P_CDM), Fp + D_DM, NR, CX);
+    contract_burst((C + P_CDM), Fp + D_DM, CX);
 #pragma unroll
     for (int k = 0; k < NB; k++) m[NB + k] = CX[k];
-    contract((C + P_CAN), Fp + D_AN, NR, CX);
+    contract_burst((C + P_CAN), Fp + D_AN, CX);
 #pragma unroll
     for (int k = 0; k < NB; k++) m[2 * NB + k] = CX[k];
 }
@@ -712,13 +728,13 @@ __global__ void __launch_bounds__(256) k_radial_coef(Sys S, const real *__restri
 #pragma unroll 1
     for (int p = 0; p < 2; p++) {
         real CR[NB];
-        contract((C + P_CR) + (2 * t + p) * NR * NB, Fp + D_R, NR, CR);
+        contract_burst((C + P_CR) + (2 * t + p) * NR * NB, Fp + D_R, CR);
         real *oR = W.rcoef + ((size_t)p * ld + i) * NB;
 #pragma unroll
         for (int k = 0; k < NB; k++) oR[k] = CR[k];
         if (fe && S.mag) {   // single-ion block, read only for spin-carrying partners
             real CS[NB];
-            contract((C + P_CSI) + p * NR * NB, Fp + D_SI, NR, CS);
+            contract_burst((C + P_CSI) + p * NR * NB, Fp + D_SI, CS);
             real *oS = W.rcoef + ((size_t)(2 + p) * ld + i) * NB;
 #pragma unroll
             for (int k = 0; k < NB; k++) oS[k] = CS[k];
