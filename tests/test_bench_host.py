@@ -91,3 +91,13 @@ def test_sweep_kernel_named_by_class_size():
     assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8192)) == "k_sweep<double,8>"
     assert bench.kernel_name("sweep", "double", np.repeat(np.arange(3), 8191)) == "k_sweep<double,16>"
     assert bench.kernel_name("desc_angular", "double") == "k_desc_angular<double>"
+
+
+def test_sweep_thresholds_match_the_library():
+    """the bench's copy of the sweep launcher's class-size thresholds equals
+    the constants in the kernel source"""
+    import re
+    src = open(os.path.join(ROOT, "paper_2606_14073_amd", "csrc", "kernels_int.hip")).read()
+    wide = int(re.search(r"constexpr int SWEEP_WIDE_MIN = (\d+);", src).group(1))
+    wider = int(re.search(r"constexpr int SWEEP_WIDER_MIN = (\d+);", src).group(1))
+    assert (bench.SWEEP_WIDE_MIN, bench.SWEEP_WIDER_MIN) == (wide, wider)
