@@ -19,7 +19,7 @@ step latency), the roofline of the dominant kernel (HIP-event time over the
 timed region against an algorithmic FLOP or byte count) and the CPU oracle on
 the host cores.
 
-Prints one JSON line. --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line. --gpus N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -534,7 +534,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="run only the copy kernel used to calibrate counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: --gpus {args.gpus} requested, but this build runs on one GPU only; "
+        print(f"bench.py: --gpus {args.gpus} requested, but the library runs on one GPU only; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calib:

@@ -81,7 +81,7 @@ typedef struct sl_server sl_server;
 /* Model                                                                  */
 /* ---------------------------------------------------------------------- */
 
-/* Hyper-parameters of the spin-aware NEP. This build supports exactly:
+/* Hyper-parameters of the spin-aware NEP. The library supports exactly:
  * n_max_R = 8 (9 radial-set functions), n_max_A = 6 (7 angular-set
  * functions), l_max = 4, basis_K = 8 (Chebyshev T_0..T_8), n_hidden = 64,
  * n_species = 2, rc_R = 6.0, rc_A = 4.5 (Angstrom); anything else is

@@ -23,8 +23,9 @@
  *     scheduled last (Sec. 3 and Sec. 5.1 "Self-consistent midpoint spin
  *     update"), with finite-temperature baths on lattice and spins (Sec. 8).
  * The paper names these parts without formulas; the exact forms used here are
- * the build's stated readings (descriptor definitions, B A O S A B splitting,
- * implicit-midpoint Rodrigues spin rotation, Philox4x32-10 normals).
+ * readings of those names, each stated with the function that takes it
+ * (descriptor definitions, B A O S A B splitting, implicit-midpoint Rodrigues
+ * spin rotation, Philox4x32-10 normals).
  *
  * Everything is the plain definition: the angular channels are the Legendre
  * double sums over neighbour pairs, derivatives are written out by calculus,

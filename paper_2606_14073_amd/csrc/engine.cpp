@@ -1317,7 +1317,7 @@ extern "C" int nep_model_create(const nep_spin_hparams *hp, const double *params
     if (!hp || !params) return fail(SL_E_INVALID, "hparams and params are required");
     if (hp->n_max_R != 8 || hp->n_max_A != 6 || hp->l_max != 4 || hp->basis_K != 8 || hp->n_hidden != 64 ||
         hp->n_species != 2 || hp->rc_R != RC_R || hp->rc_A != RC_A)
-        return fail(SL_E_INVALID, "unsupported hyper-parameters (this build: n_max_R 8, n_max_A 6, l_max 4, "
+        return fail(SL_E_INVALID, "unsupported hyper-parameters (supported: n_max_R 8, n_max_A 6, l_max 4, "
                                   "basis_K 8, n_hidden 64, 2 species, rc 6.0/4.5)");
     if (hp->structural != 0 && hp->structural != 1) return fail(SL_E_INVALID, "structural must be 0 or 1");
     if (!std::isfinite(hp->moment_a) || !std::isfinite(hp->moment_b) || hp->moment_b < 0)
