@@ -242,6 +242,8 @@ struct Engine {
     int *act_buf = nullptr;    // [2 cap_rep] 'active' words to set on a re-layout (-1: leave)
     d4 *stage_buf = nullptr;   // staging of resident state across a re-layout (grow-only)
     size_t stage_cap = 0;
+    int *src_buf = nullptr;    // re-layout: old row of each new row (grow-only)
+    size_t src_cap = 0;
     void *work = nullptr;      // real-typed work arrays, one allocation
     size_t work_bytes = 0;
     Work<double> w64{};
@@ -318,6 +320,9 @@ struct Engine {
         if (stage_buf) (void)hipFree(stage_buf);
         stage_buf = nullptr;
         stage_cap = 0;
+        if (src_buf) (void)hipFree(src_buf);
+        src_buf = nullptr;
+        src_cap = 0;
         cap = cap_fe = cap_cells = cap_rep = cap_chunks = cap_obs = cap_col = 0;
         for (auto e : prof_pool) (void)hipEventDestroy(e);
         prof_pool.clear();
@@ -537,22 +542,20 @@ struct Engine {
             if (std::find(new_reps.begin(), new_reps.end(), r) != new_reps.end() && r->fe_off >= 0) moved.push_back(r);
         }
         // Snapshot the resident state (the arrays may be reallocated and the
-        // new ranges may overlap the old ones): into a device staging buffer,
-        // five state arrays of every moved replica, or into host memory when
-        // that buffer cannot be allocated.
-        size_t stage_n = 0;
-        std::vector<size_t> stage_off(moved.size());
-        for (size_t k = 0; k < moved.size(); k++) {
-            stage_off[k] = stage_n;
-            stage_n += moved[k]->n;
-        }
+        // new ranges may overlap the old ones). On the device: the five state
+        // arrays copied whole into a staging buffer and the replica records in
+        // one copy, the kept replicas' rows placed afterwards by one gather
+        // kernel, so that a re-layout costs a few calls however many replicas
+        // stay. In host memory, replica by replica, when that buffer cannot be
+        // allocated.
+        const size_t n_old = moved.empty() ? 0 : (size_t)N;
         // a grow-only device buffer kept by the engine, so that admissions
         // and retirements do not allocate each time
-        if (stage_n && !arena && 5 * stage_n > stage_cap) {
+        if (n_old && !arena && 5 * n_old > stage_cap) {
+            const size_t want = 5 * std::max(n_old, stage_cap / 5 + stage_cap / 20);
             if (stage_buf) (void)hipFree(stage_buf);
             stage_buf = nullptr;
             stage_cap = 0;
-            const size_t want = 5 * std::max(stage_n, stage_cap / 5 + stage_cap / 20);
             if (hipMalloc((void **)&stage_buf, want * sizeof(d4)) == hipSuccess) {
                 stage_cap = want;
             } else {
@@ -560,24 +563,33 @@ struct Engine {
                 stage_buf = nullptr;
             }
         }
-        d4 *const stage = stage_n && stage_buf && 5 * stage_n <= stage_cap ? stage_buf : nullptr;
-        std::vector<std::vector<d4>> snap(stage ? 0 : moved.size() * 5);
+        d4 *const stage = n_old && stage_buf && 5 * n_old <= stage_cap ? stage_buf : nullptr;
+        std::vector<int> old_fe(moved.size()), old_ge(moved.size());
         for (size_t k = 0; k < moved.size(); k++) {
+            old_fe[k] = moved[k]->fe_off;
+            old_ge[k] = moved[k]->ge_off;
+        }
+        std::vector<std::vector<d4>> snap(stage ? 0 : moved.size() * 5);
+        if (stage) {
+            const d4 *src[5] = {pos, vel, spin, force, field};
+            for (int a = 0; a < 5; a++)
+                HIPCHK(hipMemcpyAsync(stage + a * n_old, src[a], n_old * sizeof(d4), hipMemcpyDeviceToDevice, st));
+            std::vector<RepDev> old(reps.size());
+            HIPCHK(hipMemcpyAsync(old.data(), rep, reps.size() * sizeof(RepDev), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (Replica *r : moved) r->dev = old[r->slot];
+        }
+        for (size_t k = 0; k < moved.size() && !stage; k++) {
             Replica *r = moved[k];
             d4 *src[5] = {pos, vel, spin, force, field};
             for (int a = 0; a < 5; a++) {
-                d4 *to = nullptr;
-                hipMemcpyKind kind = hipMemcpyDeviceToDevice;
-                if (stage) {
-                    to = stage + a * stage_n + stage_off[k];
-                } else {
-                    snap[5 * k + a].resize(r->n);
-                    to = snap[5 * k + a].data();
-                    kind = hipMemcpyDeviceToHost;
-                }
-                if (r->n_fe) HIPCHK(hipMemcpyAsync(to, src[a] + r->fe_off, r->n_fe * sizeof(d4), kind, st));
+                snap[5 * k + a].resize(r->n);
+                d4 *to = snap[5 * k + a].data();
+                if (r->n_fe)
+                    HIPCHK(hipMemcpyAsync(to, src[a] + r->fe_off, r->n_fe * sizeof(d4), hipMemcpyDeviceToHost, st));
                 if (r->n - r->n_fe)
-                    HIPCHK(hipMemcpyAsync(to + r->n_fe, src[a] + r->ge_off, (r->n - r->n_fe) * sizeof(d4), kind, st));
+                    HIPCHK(hipMemcpyAsync(to + r->n_fe, src[a] + r->ge_off, (r->n - r->n_fe) * sizeof(d4),
+                                          hipMemcpyDeviceToHost, st));
             }
             HIPCHK(hipMemcpyAsync(&r->dev, rep + r->slot, sizeof(RepDev), hipMemcpyDeviceToHost, st));
         }
@@ -666,21 +678,44 @@ struct Engine {
             HIPCHK(hipMemcpyAsync(col_idx, h_colidx.data(), h_colidx.size() * 4, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(col_rid, h_colrid.data(), h_colrid.size() * 4, hipMemcpyHostToDevice, st));
         }
-        // state
+        // state: the kept replicas' rows from the staging buffer in one gather
+        if (stage && n) {
+            if (n > src_cap) {
+                if (src_buf) (void)hipFree(src_buf);
+                src_buf = nullptr;
+                src_cap = 0;
+                if (hipMalloc((void **)&src_buf, n * sizeof(int)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(SL_E_OOM, "hipMalloc of the re-layout index failed");
+                }
+                src_cap = n;
+            }
+            std::vector<int> h_src(n, -1);
+            for (size_t m = 0; m < moved.size(); m++) {
+                const Replica *r = moved[m];
+                for (int64_t q = 0; q < r->n_fe; q++) h_src[r->fe_off + q] = old_fe[m] + (int)q;
+                for (int64_t q = 0; q < r->n - r->n_fe; q++) h_src[r->ge_off + q] = old_ge[m] + (int)q;
+            }
+            HIPCHK(hipMemcpyAsync(src_buf, h_src.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+            launch_gather_state(stage, n_old, src_buf, (int)n, pos, vel, spin, force, field, st);
+            HIPCHK(hipStreamSynchronize(st));
+        }
         std::vector<d4> buf;
         for (size_t k = 0; k < reps.size(); k++) {
             Replica *r = reps[k];
             auto mk = std::find(moved.begin(), moved.end(), r);
             d4 *dst[5] = {pos, vel, spin, force, field};
             if (mk != moved.end()) {
+                if (stage) continue;   // gathered above
                 size_t m = mk - moved.begin();
                 for (int a = 0; a < 5; a++) {
-                    const d4 *from = stage ? stage + a * stage_n + stage_off[m] : snap[5 * m + a].data();
-                    const hipMemcpyKind kind = stage ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-                    if (r->n_fe) HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, from, r->n_fe * sizeof(d4), kind, st));
-                    if (r->n - r->n_fe)
-                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, from + r->n_fe, (r->n - r->n_fe) * sizeof(d4), kind,
+                    const d4 *from = snap[5 * m + a].data();
+                    if (r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->fe_off, from, r->n_fe * sizeof(d4), hipMemcpyHostToDevice,
                                               st));
+                    if (r->n - r->n_fe)
+                        HIPCHK(hipMemcpyAsync(dst[a] + r->ge_off, from + r->n_fe, (r->n - r->n_fe) * sizeof(d4),
+                                              hipMemcpyHostToDevice, st));
                 }
             } else {
                 const double *src[3] = {r->pos.data(), r->vel.data(), r->spin.data()};

@@ -106,6 +106,10 @@ void launch_spin_mid(const Sys &S, hipStream_t st);
 void launch_step_end(const Sys &S, hipStream_t st);
 // rep[r].active = act[r] for every r < n with act[r] >= 0
 void launch_set_active(RepDev *rep, const int *act, int n, hipStream_t st);
+// re-layout: row k of the five state arrays takes row src[k] of the staged old
+// arrays (array a at stage + a n_old); src[k] < 0 leaves row k alone
+void launch_gather_state(const d4 *stage, size_t n_old, const int *src, int n, d4 *pos, d4 *vel, d4 *spin, d4 *force,
+                         d4 *field, hipStream_t st);
 // self-consistent midpoint: residual of the pass, per replica converged or
 // not, and with depth > 0 the mixing coefficients; sc_out[0] = replicas still
 // iterating, sc_out[1] = largest change, sc_out[2] = columns used, then gam

@@ -407,6 +407,22 @@ __global__ void __launch_bounds__(256) k_sweep(Sys S, Work<real> W, int base, in
     }
 }
 
+// Re-layout of the resident replicas: atom k of the new layout takes the state
+// rows of atom src[k] of the old one, whose five arrays were copied whole to
+// the staging buffer; src[k] = -1 marks atoms of replicas new to the device.
+__global__ void __launch_bounds__(256) k_gather_state(const d4 *stage, size_t n_old, const int *src, int n, d4 *pos,
+                                                      d4 *vel, d4 *spin, d4 *force, d4 *field) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int s = src[k];
+    if (s < 0 || (size_t)s >= n_old) return;
+    pos[k] = stage[s];
+    vel[k] = stage[n_old + s];
+    spin[k] = stage[2 * n_old + s];
+    force[k] = stage[3 * n_old + s];
+    field[k] = stage[4 * n_old + s];
+}
+
 __global__ void k_set_active(RepDev *rep, const int *act, int n) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n && act[r] >= 0) rep[r].active = act[r];
@@ -732,6 +748,11 @@ void launch_step_end(const Sys &S, hipStream_t st) {
 }
 void launch_set_active(RepDev *rep, const int *act, int n, hipStream_t st) {
     if (n) hipLaunchKernelGGL(k_set_active, dim3(nblk(n, 64)), dim3(64), 0, st, rep, act, n);
+}
+void launch_gather_state(const d4 *stage, size_t n_old, const int *src, int n, d4 *pos, d4 *vel, d4 *spin, d4 *force,
+                         d4 *field, hipStream_t st) {
+    if (n) hipLaunchKernelGGL(k_gather_state, dim3(nblk(n, 256)), dim3(256), 0, st, stage, n_old, src, n, pos, vel,
+                              spin, force, field);
 }
 int sc_part_blocks(int n_fe) { return nblk(n_fe, 256); }
 void launch_sc_check(const Sys &S, int pass, int depth, double reg, int k_corr, hipStream_t st) {
