@@ -1359,15 +1359,35 @@ __global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__res
         int j1 = 0 < nfe ? S.nbrR[i] : 0;
         int j2 = 1 < nfe ? S.nbrR[ld + i] : j1;
         d4 p1 = S.pos[j1];
+        // first the in-cutoff slots (nfe <= MAXFE = 64 bits), then the work in
+        // slot order over those alone: at temperature the lanes of a
+        // wavefront have their out-of-cutoff slots at different places, and
+        // a loop over all slots would run its body for their union
+        uint64_t in = 0;
         for (int s = 0; s < nfe; s++) {
-            const int j = j1;
             const d4 pj = p1;
             j1 = j2;
             p1 = S.pos[j1];
             if (s + 2 < nfe) j2 = S.nbrR[(size_t)(s + 2) * ld + i];
             real d[3];
+            if (geom_p(R, pi, pj, d) < rc2) in |= 1ull << s;
+        }
+        int s = in ? __ffsll((long long)in) - 1 : -1;
+        in = in ? in & (in - 1) : 0;
+        int jn = s >= 0 ? S.nbrR[(size_t)s * ld + i] : 0;
+        d4 pn = S.pos[jn];
+        while (s >= 0) {
+            const int j = jn;
+            const d4 pj = pn;
+            const int s_ = s;
+            s = in ? __ffsll((long long)in) - 1 : -1;
+            in = in ? in & (in - 1) : 0;
+            if (s >= 0) {
+                jn = S.nbrR[(size_t)s * ld + i];
+                pn = S.pos[jn];
+            }
+            real d[3];
             const real r2 = geom_p(R, pi, pj, d);
-            if (r2 >= rc2) continue;
             real r, ir;
             r_and_inv(r2, r, ir);
             const real rh[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
@@ -1382,8 +1402,8 @@ __global__ void __launch_bounds__(256) k_assemble_pairs(Sys S, const real *__res
                 K += (Ci[2 * NB + k] + mj[2 * NB + k]) * f[k];
             }
             if (r2 < rca2) {
-                const int t = min(S.revR[s * ld + i], MAXFE - 1);
-                J += W.csa[(size_t)s * lf + i] + W.csa[(size_t)t * lf + j];
+                const int t = min(S.revR[s_ * ld + i], MAXFE - 1);
+                J += W.csa[(size_t)s_ * lf + i] + W.csa[(size_t)t * lf + j];
             }
             const real g = dotk(CS, f);
             Axx += g * rh[0] * rh[0];
